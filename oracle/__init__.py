@@ -1,0 +1,69 @@
+"""Oracle: a plain, slow FP64 flooding sum-product decoder on the CPU.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the decoder library and
+its Python binding never do.  It shares no code with the GPU path.
+
+``decode`` follows Section II of arxiv 1812.06545 (Tanner graph of H, two-phase
+message passing, Algorithm 1's loop order) with the sum-product check rule of
+Section I; see spa_oracle.c for the exact definition and readings.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB, compile_oracle
+
+R_MAX = 20.0  # clamp on check-to-variable messages (a reading: the paper gives none)
+
+_lib = None
+
+
+def _load(path: str = LIB):
+    global _lib
+    if _lib is None or path != LIB:
+        if not os.path.exists(path):
+            compile_oracle(out=path) if path == LIB else None
+        lib = ctypes.CDLL(path)
+        f = lib.oracle_spa_decode
+        P = ctypes.c_void_p
+        f.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int,
+                      ctypes.c_double, P, P, P, P, P, ctypes.c_int]
+        f.restype = ctypes.c_int
+        if path != LIB:
+            return lib
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def decode(code, llr, max_iter: int, early_stop: bool, r_max: float = R_MAX, nthreads: int = 1,
+           want_trace: bool = True, lib=None):
+    """Decode frames ``llr`` (F, n) -> dict(bits, iters, posterior, cond, min_abs).
+
+    float32 input is upcast to float64 unchanged, so both sides see the same
+    values.  ``lib`` lets the tests point at a deliberately broken build.
+    """
+    llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float64)
+    F, n = llr.shape
+    assert n == code.n
+    rp = np.ascontiguousarray(code.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(code.col_idx, dtype=np.int32)
+    bits = np.zeros((F, n), dtype=np.uint8)
+    iters = np.zeros(F, dtype=np.int32)
+    post = np.zeros((F, n), dtype=np.float64)
+    cond = np.zeros((F, n), dtype=np.float64)
+    mabs = np.zeros((F, max_iter + 1), dtype=np.float64) if want_trace else None
+    L = lib if lib is not None else _load()
+    st = L.oracle_spa_decode(code.m, n, _ptr(rp), _ptr(ci), F, _ptr(llr), int(max_iter),
+                             int(bool(early_stop)), float(r_max), _ptr(bits), _ptr(iters), _ptr(post),
+                             _ptr(cond), _ptr(mabs), int(nthreads))
+    if st != 0:
+        raise ValueError(f"oracle_spa_decode failed with status {st}")
+    return {"bits": bits, "iters": iters, "posterior": post, "cond": cond, "min_abs": mabs}

@@ -1,0 +1,180 @@
+"""Pins for the oracle: checks against what mathematics fixes, independent of
+the oracle's own code.  Each check takes a decoder callable
+``dec(code, llr, max_iter, early_stop) -> dict`` so that the same checks run
+against the real oracle and against deliberately broken copies of it.
+
+Pins (each names what it fixes):
+  spc_map           single parity check, 1 iteration: posterior = exact bitwise
+                    MAP (brute force), which pins the check rule (tanh product
+                    over the *other* edges, factor 1/2 and 2, sign) and the
+                    variable rule's channel term.
+  repetition_sum    path of degree-2 checks: after n-1 iterations every
+                    posterior equals the sum of all channel LLRs (the exact MAP
+                    of a repetition code), and not yet after n-2 iterations;
+                    pins extrinsic subtraction and the flooding schedule depth.
+  tree_map          random cycle-free Tanner graphs: posterior = exact MAP once
+                    t >= ceil(D/2) (D = variable-to-variable diameter), and not
+                    at t = ceil(D/2) - 1.
+  clamp             two-bit parity check with |L| = 30: r = 2 atanh(tanh(15)) = 30
+                    is clamped to R_MAX = 20, so the posterior is 30 + 20.
+  noiseless         L = A(1-2c) for a codeword c: iters 0, bits c, posterior = L.
+  zero_iter         max_iter = 0: bits = [L < 0] (+0 and -0 give 0), posterior = L.
+  symmetry          decoding L*(1-2c) gives bits xor c, the same iters and the
+                    same |posterior| (tanh/atanh odd, signs exact).
+  zero_syndrome     early stop: every frame that stopped before max_iter has
+                    H bits = 0 by an independent dense product.
+  prefix            a run with a larger max_iter that stopped at iters <= T
+                    equals the run with max_iter T.
+  fixed_iters       early stop off: iters = max_iter for every frame.
+  stop_iteration    with early stop, iters is the first t whose hard decision
+                    (taken from the early-stop-off run truncated at t) has a
+                    zero syndrome by an independent dense product, else T.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from workloads import channel, codes, configs
+from mapref import all_codewords, dense_syndrome, map_llr
+
+R_MAX = 20.0
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def spc_map(dec):
+    for n, seed in ((2, 1), (3, 2), (5, 3), (8, 4), (12, 5)):
+        code = codes.single_parity_check(n)
+        llr = _rng(seed).normal(0.0, 1.5, size=(6, n))
+        ref = map_llr(code, llr)
+        for T in (1, 3):
+            out = dec(code, llr, T, False)
+            np.testing.assert_allclose(out["posterior"], ref, rtol=1e-12, atol=1e-12,
+                                       err_msg=f"SPC n={n} T={T}")
+
+
+def repetition_sum(dec):
+    for n, seed in ((4, 11), (6, 12), (9, 13)):
+        code = codes.repetition_chain(n)
+        llr = _rng(seed).uniform(-2.0, 2.0, size=(4, n))
+        total = llr.sum(axis=1, keepdims=True) * np.ones((1, n))
+        np.testing.assert_allclose(map_llr(code, llr), total, rtol=1e-12, atol=1e-12)
+        out = dec(code, llr, n - 1, False)
+        np.testing.assert_allclose(out["posterior"], total, rtol=1e-9, atol=1e-9,
+                                   err_msg=f"repetition n={n} after n-1 iterations")
+        early = dec(code, llr, n - 2, False)
+        assert np.abs(early["posterior"] - total).max() > 1e-3, "repetition exact too early"
+
+
+def tree_map(dec):
+    checked = 0
+    for nv, seed in ((6, 21), (8, 22), (9, 23), (11, 24), (12, 25), (14, 26)):
+        code = codes.random_tree_code(nv, seed)
+        D = codes.tanner_vn_diameter(code)
+        t_exact = math.ceil(D / 2)
+        llr = _rng(seed + 100).uniform(-1.2, 1.2, size=(3, nv))
+        ref = map_llr(code, llr)
+        out = dec(code, llr, t_exact, False)
+        np.testing.assert_allclose(out["posterior"], ref, rtol=1e-9, atol=1e-9,
+                                   err_msg=f"tree nv={nv} D={D} at t={t_exact}")
+        later = dec(code, llr, t_exact + 3, False)
+        np.testing.assert_allclose(later["posterior"], ref, rtol=1e-9, atol=1e-9)
+        if t_exact >= 2:
+            before = dec(code, llr, t_exact - 1, False)
+            assert np.abs(before["posterior"] - ref).max() > 1e-6, f"tree nv={nv} exact too early"
+            checked += 1
+    assert checked >= 3
+
+
+def clamp(dec):
+    code = codes.single_parity_check(2)
+    llr = np.array([[30.0, 30.0], [-30.0, 30.0], [3.0, 30.0]])
+    out = dec(code, llr, 1, False)
+    want = np.array([[50.0, 50.0], [-30.0 + 20.0, 30.0 - 20.0], [3.0 + 20.0, 30.0 + 3.0]])
+    np.testing.assert_allclose(out["posterior"], want, rtol=1e-9, atol=1e-9)
+
+
+def _gallager_noisy(frames, seed, ebn0=2.0):
+    code = configs.gallager504(frames=frames).code
+    cw = configs.gallager504(frames=frames).codewords
+    llr = channel.bpsk_awgn_llr(cw, ebn0, 0.5, seed, dtype=np.float64)
+    return code, cw, llr
+
+
+def noiseless(dec):
+    code, cw, _ = _gallager_noisy(8, 31)
+    for A in (0.5, 3.0):
+        llr = channel.noiseless_llr(cw, A)
+        out = dec(code, llr, 20, True)
+        assert (out["iters"] == 0).all()
+        assert (out["bits"] == cw).all()
+        assert (out["posterior"] == llr).all()
+
+
+def zero_iter(dec):
+    code, cw, llr = _gallager_noisy(4, 32)
+    llr = llr.copy()
+    llr[0, :4] = [0.0, -0.0, -1e-300, 1e-300]
+    for es in (False, True):
+        out = dec(code, llr, 0, es)
+        assert (out["iters"] == 0).all()
+        assert (out["bits"] == (llr < 0)).all()
+        assert (out["posterior"] == llr).all()
+    assert list(out["bits"][0, :4]) == [0, 0, 1, 0]
+
+
+def symmetry(dec):
+    code, cw, llr = _gallager_noisy(12, 33, ebn0=1.5)
+    base = dec(code, llr, 20, True)
+    cw2 = configs.gallager504(frames=24).codewords[12:24]
+    flipped = llr * (1.0 - 2.0 * cw2)
+    out = dec(code, flipped, 20, True)
+    assert (out["bits"] == (base["bits"] ^ cw2)).all()
+    assert (out["iters"] == base["iters"]).all()
+    assert (np.abs(out["posterior"]) == np.abs(base["posterior"])).all()
+
+
+def zero_syndrome(dec):
+    code, cw, llr = _gallager_noisy(40, 34)
+    out = dec(code, llr, 20, True)
+    stopped = out["iters"] < 20
+    assert stopped.sum() >= 20
+    assert (dense_syndrome(code, out["bits"][stopped]) == 0).all()
+
+
+def prefix(dec):
+    code, cw, llr = _gallager_noisy(30, 35, ebn0=1.5)
+    a = dec(code, llr, 8, True)
+    b = dec(code, llr, 25, True)
+    sel = b["iters"] <= 8
+    assert sel.sum() >= 5
+    assert (a["iters"][sel] == b["iters"][sel]).all()
+    assert (a["bits"][sel] == b["bits"][sel]).all()
+    assert (a["posterior"][sel] == b["posterior"][sel]).all()
+
+
+def fixed_iters(dec):
+    code, cw, llr = _gallager_noisy(10, 36)
+    out = dec(code, llr, 7, False)
+    assert (out["iters"] == 7).all()
+
+
+def stop_iteration(dec):
+    code, cw, llr = _gallager_noisy(24, 37, ebn0=1.8)
+    T = 12
+    es = dec(code, llr, T, True)
+    first = np.full(llr.shape[0], T)
+    for t in range(T, -1, -1):
+        bits_t = dec(code, llr, t, False)["bits"]
+        ok = (dense_syndrome(code, bits_t) == 0).all(axis=1)
+        first[ok] = t
+    assert len(set(first.tolist())) >= 3
+    assert (es["iters"] == first).all()
+
+
+ALL = [spc_map, repetition_sum, tree_map, clamp, noiseless, zero_iter, symmetry, zero_syndrome,
+       prefix, fixed_iters, stop_iteration]
