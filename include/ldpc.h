@@ -1,0 +1,166 @@
+/*
+ * ldpc.h - C ABI of libldpc: flooding sum-product LDPC decoding on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operation (arxiv 1812.06545, Section II): a binary LDPC code is given by
+ * its sparse m x n parity-check matrix H (H[i][j] = 1 joins check node i to
+ * variable node j of the Tanner graph).  Given channel log-likelihood ratios
+ * L_ch (LLR = ln P(bit=0)/P(bit=1), so a negative value favours 1) for many
+ * frames, the decoder runs belief propagation (the sum-product algorithm of
+ * Section I) on a flooding (two-phase) schedule, Algorithm 1's loop order:
+ *   Loop 1  q_mn = L_ch,n
+ *   Loop 2  r_mn = 2 atanh( prod_{n' in N(m), n' != n} tanh(q_mn' / 2) ),
+ *           clamped to [-LDPC_R_MAX, LDPC_R_MAX]
+ *   Loop 3  L_n = L_ch,n + sum_{m in M(n)} r_mn ;  q_mn = L_n - r_mn
+ *   Loop 4  x_n = 1 if L_n < 0 else 0
+ * for t = 1 .. max_iter.  With LDPC_EARLY_STOP the syndrome H x (mod 2) is
+ * tested before iteration 1 and after every Loop 4; a frame stops at the
+ * first all-zero syndrome.  The per-frame iteration count is the number of
+ * iterations run (0 when the channel decision already is a codeword;
+ * max_iter when the syndrome never clears or early stop is off).
+ *
+ * Conventions for every call:
+ *   - Frame buffers are row-major [frames][n]: frame f, bit j at f*n + j.
+ *   - "device" pointers are HIP device memory of the device the code handle
+ *     was created on, which must be the current device at the call.
+ *   - Decoding calls are asynchronous on the given hipStream_t (passed as
+ *     void*; NULL = the null stream).  They return after enqueueing.
+ *   - Argument errors are detected before anything is enqueued: the call
+ *     returns LDPC_EINVAL (or LDPC_EUNSUPPORTED) and writes nothing.
+ *   - A HIP launch failure returns LDPC_EDEVICE; faults during execution
+ *     surface at the caller's next synchronisation.
+ *   - frames == 0 is a no-op returning LDPC_OK.
+ *   - LLR inputs must be finite.
+ *   - The caller owns every frame buffer, workspace and stream; the library
+ *     owns code handles (device-resident, immutable after creation, safe to
+ *     share between threads) and plans.
+ */
+#ifndef LDPC_H
+#define LDPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LDPC_OK = 0,
+    LDPC_EINVAL = -1,       /* invalid argument; nothing was enqueued or written */
+    LDPC_ENOMEM = -2,       /* device or host allocation failed */
+    LDPC_EDEVICE = -3,      /* HIP runtime error */
+    LDPC_EBUSY = -4,        /* resource temporarily unavailable (server full) */
+    LDPC_EUNSUPPORTED = -5  /* valid but outside this build's limits */
+} ldpc_status;
+
+typedef enum { LDPC_F32 = 0, LDPC_F64 = 1 } ldpc_dtype;
+
+#define LDPC_EARLY_STOP 1u  /* flag: stop a frame at its first zero syndrome */
+
+/* Clamp on check-to-variable messages (the paper gives none; 20 keeps the
+ * FP64 tanh/atanh evaluation accurate). */
+#define LDPC_R_MAX 20.0
+
+/* Limits of this build. */
+#define LDPC_MAX_ROW_DEGREE 64
+#define LDPC_MAX_FRAMES (1 << 24)
+
+typedef struct ldpc_code_s *ldpc_code;
+
+/* Human-readable name of a status code (static storage). */
+const char *ldpc_status_str(ldpc_status status);
+
+/*
+ * Create a code from H in CSR form (Section II: the H-matrix / Tanner graph).
+ *   m, n     rows (check nodes) >= 1 and columns (variable nodes) >= 1
+ *   row_ptr  host, m+1 entries, row_ptr[0] = 0, non-decreasing
+ *   col_idx  host, row_ptr[m] entries; columns of row i in
+ *            col_idx[row_ptr[i] .. row_ptr[i+1]); any order, no duplicates
+ * The matrix is copied to the current device; the caller keeps its arrays.
+ * Rows may be empty (always satisfied); columns may be empty (L = L_ch).
+ * Errors: EINVAL for bad sizes, out-of-range or duplicate columns, NULL
+ * pointers; EUNSUPPORTED for a row degree above LDPC_MAX_ROW_DEGREE;
+ * ENOMEM / EDEVICE on allocation or copy failure.  *out is set only on OK.
+ */
+ldpc_status ldpc_code_from_csr(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                               ldpc_code *out);
+
+/*
+ * Create a quasi-cyclic code from an mb x nb base matrix of circulant shifts
+ * (host, row-major, -1 = all-zero block, otherwise 0 <= shift < Z).  Block
+ * (i, j) with shift s joins check row i*Z + r to variable column
+ * j*Z + ((r + s) mod Z), r = 0 .. Z-1; so m = mb*Z, n = nb*Z.
+ * Errors as ldpc_code_from_csr, plus EINVAL for shifts outside [-1, Z).
+ * QC codes additionally get the circulant-block layout used by the fused
+ * (frame-resident) kernels.
+ */
+ldpc_status ldpc_code_from_qc(int32_t mb, int32_t nb, int32_t Z, const int32_t *shifts, ldpc_code *out);
+
+/* Sizes of a code: m, n and the number of edges (ones of H).  Any output may be NULL. */
+ldpc_status ldpc_code_info(ldpc_code code, int32_t *m, int32_t *n, int64_t *edges);
+
+/* Release a code.  The caller must ensure no enqueued work still uses it.  NULL is ignored. */
+void ldpc_code_destroy(ldpc_code code);
+
+/*
+ * Workspace needed by ldpc_decode for `frames` frames of `code` in `dtype`
+ * with at most `max_iter` iterations.  Frames are padded to a multiple of 64;
+ * the messages are stored edge-major with frames innermost.
+ */
+ldpc_status ldpc_workspace_bytes(ldpc_code code, ldpc_dtype dtype, int32_t frames, int32_t max_iter,
+                                 size_t *bytes);
+
+/*
+ * Decode `frames` frames with per-iteration kernel launches (the plain
+ * flooding path: one check-node and one variable-node kernel per iteration,
+ * messages streamed through device memory).
+ *   dtype      LDPC_F32 (llr/posterior are float) or LDPC_F64 (double)
+ *   max_iter   >= 0; 0 returns the hard decision of llr, iters 0, posterior = llr
+ *   flags      0 or LDPC_EARLY_STOP
+ *   llr        device, [frames][n] of dtype, read only
+ *   bits       device, [frames][n] uint8 0/1 (written)
+ *   iters      device, [frames] int32 (written)
+ *   posterior  device, [frames][n] of dtype, or NULL (written if non-NULL)
+ *   workspace  device, at least ldpc_workspace_bytes(...) bytes, 256-byte aligned
+ *   stream     hipStream_t or NULL
+ */
+ldpc_status ldpc_decode(ldpc_code code, ldpc_dtype dtype, int32_t frames, int32_t max_iter, uint32_t flags,
+                        const void *llr, uint8_t *bits, int32_t *iters, void *posterior, void *workspace,
+                        size_t workspace_bytes, void *stream);
+
+/* One decoding job of a batch: same meaning as the ldpc_decode arguments. */
+typedef struct {
+    ldpc_code code;
+    int32_t frames;
+    int32_t max_iter;
+    uint32_t flags;
+    const void *llr;
+    uint8_t *bits;
+    int32_t *iters;
+    void *posterior; /* may be NULL */
+} ldpc_job;
+
+/*
+ * Workspace for ldpc_decode_batch over these jobs (all of one dtype).
+ */
+ldpc_status ldpc_batch_workspace_bytes(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, size_t *bytes);
+
+/*
+ * Decode a batch of jobs of possibly different codes, lengths and rates.
+ * Jobs whose code fits the fused frame-resident kernel (messages of one
+ * frame held in LDS) run together in ONE persistent launch whose workgroups
+ * pull (job, frame) items from a device-side queue; each workgroup runs every
+ * iteration of its frame, with per-frame early stop.  Jobs whose code does
+ * not fit run through the plain per-iteration kernels on the same stream.
+ * Each frame's result is identical to decoding that frame alone.
+ * Errors as ldpc_decode; jobs with frames == 0 are skipped.
+ */
+ldpc_status ldpc_decode_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, void *workspace,
+                              size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDPC_H */

@@ -1,0 +1,266 @@
+"""Python binding of libldpc (flooding sum-product LDPC decoding on MI355X).
+
+A thin ctypes layer over the C ABI declared in include/ldpc.h: the functions
+``ldpc_*`` below take the same arguments as their C namesakes (device memory
+as torch tensors or raw pointers, the stream as a torch stream) and only
+marshal them; every step of decoding runs in the HIP kernels of libldpc.so.
+PyTorch supplies device memory and streams, nothing else.
+
+There is no CPU fallback: importing this package fails loudly when the
+library has not been built (``python -m paper_1812_06545_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch  # loads the HIP runtime that libldpc.so then shares
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldpc.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ldpc.h")
+
+LDPC_OK, LDPC_EINVAL, LDPC_ENOMEM, LDPC_EDEVICE, LDPC_EBUSY, LDPC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+LDPC_F32, LDPC_F64 = 0, 1
+LDPC_EARLY_STOP = 1
+LDPC_R_MAX = 20.0
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1812_06545_amd.build` "
+                      "(there is no fallback decoder)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+
+
+class ldpc_job(ctypes.Structure):
+    _fields_ = [("code", _P), ("frames", _I32), ("max_iter", _I32), ("flags", ctypes.c_uint32),
+                ("llr", _P), ("bits", _P), ("iters", _P), ("posterior", _P)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("ldpc_status_str", ctypes.c_char_p, [ctypes.c_int])
+_sig("ldpc_code_from_csr", ctypes.c_int, [_I32, _I32, _P, _P, ctypes.POINTER(_P)])
+_sig("ldpc_code_from_qc", ctypes.c_int, [_I32, _I32, _I32, _P, ctypes.POINTER(_P)])
+_sig("ldpc_code_info", ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_int64)])
+_sig("ldpc_code_destroy", None, [_P])
+_sig("ldpc_workspace_bytes", ctypes.c_int, [_P, ctypes.c_int, _I32, _I32, ctypes.POINTER(ctypes.c_size_t)])
+_sig("ldpc_decode", ctypes.c_int, [_P, ctypes.c_int, _I32, _I32, ctypes.c_uint32, _P, _P, _P, _P, _P,
+                                   ctypes.c_size_t, _P])
+_sig("ldpc_batch_workspace_bytes", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int,
+                                                  ctypes.POINTER(ctypes.c_size_t)])
+_sig("ldpc_decode_batch", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, _P, ctypes.c_size_t, _P])
+
+
+class LdpcError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {ldpc_status_str(status)} ({status})")
+
+
+def header_functions():
+    """Names of the functions include/ldpc.h declares."""
+    text = open(HEADER_PATH).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ldpc_[a-z0-9_]+)\s*\(", text)))
+
+
+def library():
+    return _lib
+
+
+def _check(st, where):
+    if st != LDPC_OK:
+        raise LdpcError(st, where)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dtype_code(dt):
+    if dt in (torch.float32, LDPC_F32):
+        return LDPC_F32
+    if dt in (torch.float64, LDPC_F64):
+        return LDPC_F64
+    raise ValueError(f"unsupported dtype {dt}")
+
+
+# ---------------------------------------------------------------- C names --
+
+def ldpc_status_str(status: int) -> str:
+    return _lib.ldpc_status_str(int(status)).decode()
+
+
+def ldpc_code_from_csr(m, n, row_ptr, col_idx) -> int:
+    import numpy as np
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    out = _P()
+    _check(_lib.ldpc_code_from_csr(int(m), int(n), rp.ctypes.data, ci.ctypes.data if ci.size else None,
+                                   ctypes.byref(out)), "ldpc_code_from_csr")
+    return out.value
+
+
+def ldpc_code_from_qc(mb, nb, Z, shifts) -> int:
+    import numpy as np
+    s = np.ascontiguousarray(shifts, dtype=np.int32)
+    out = _P()
+    _check(_lib.ldpc_code_from_qc(int(mb), int(nb), int(Z), s.ctypes.data, ctypes.byref(out)), "ldpc_code_from_qc")
+    return out.value
+
+
+def ldpc_code_info(handle):
+    m, n, e = _I32(), _I32(), ctypes.c_int64()
+    _check(_lib.ldpc_code_info(handle, ctypes.byref(m), ctypes.byref(n), ctypes.byref(e)), "ldpc_code_info")
+    return m.value, n.value, e.value
+
+
+def ldpc_code_destroy(handle):
+    _lib.ldpc_code_destroy(handle)
+
+
+def ldpc_workspace_bytes(handle, dtype, frames, max_iter) -> int:
+    b = ctypes.c_size_t()
+    _check(_lib.ldpc_workspace_bytes(handle, _dtype_code(dtype), int(frames), int(max_iter), ctypes.byref(b)),
+           "ldpc_workspace_bytes")
+    return b.value
+
+
+def ldpc_decode(handle, dtype, frames, max_iter, flags, llr, bits, iters, posterior, workspace, workspace_bytes,
+                stream=None) -> int:
+    return _lib.ldpc_decode(handle, _dtype_code(dtype), int(frames), int(max_iter), int(flags), _ptr(llr),
+                            _ptr(bits), _ptr(iters), _ptr(posterior), _ptr(workspace), int(workspace_bytes),
+                            _stream_handle(stream))
+
+
+def _jobs_array(jobs):
+    arr = (ldpc_job * max(len(jobs), 1))()
+    for i, j in enumerate(jobs):
+        arr[i] = j
+    return arr
+
+
+def ldpc_batch_workspace_bytes(jobs, dtype) -> int:
+    arr = _jobs_array(jobs)
+    b = ctypes.c_size_t()
+    _check(_lib.ldpc_batch_workspace_bytes(arr, len(jobs), _dtype_code(dtype), ctypes.byref(b)),
+           "ldpc_batch_workspace_bytes")
+    return b.value
+
+
+def ldpc_decode_batch(jobs, dtype, workspace, workspace_bytes, stream=None) -> int:
+    arr = _jobs_array(jobs)
+    return _lib.ldpc_decode_batch(arr, len(jobs), _dtype_code(dtype), _ptr(workspace), int(workspace_bytes),
+                                  _stream_handle(stream))
+
+
+# ------------------------------------------------------------ conveniences --
+
+class Code:
+    """Owns an ldpc_code handle on the current device."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+        self.m, self.n, self.edges = ldpc_code_info(handle)
+
+    @classmethod
+    def from_csr(cls, m, n, row_ptr, col_idx):
+        return cls(ldpc_code_from_csr(m, n, row_ptr, col_idx))
+
+    @classmethod
+    def from_qc(cls, mb, nb, Z, shifts):
+        return cls(ldpc_code_from_qc(mb, nb, Z, shifts))
+
+    @classmethod
+    def from_workload(cls, code):
+        """From a workloads.codes.Code (QC layout when it carries one)."""
+        if code.qc is not None:
+            q = code.qc
+            return cls.from_qc(q["mb"], q["nb"], q["Z"], q["shifts"])
+        return cls.from_csr(code.m, code.n, code.row_ptr, code.col_idx)
+
+    def close(self):
+        if self.handle:
+            ldpc_code_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _workspace(nbytes, device):
+    # 256-byte alignment is required; torch's allocator gives at least 512.
+    ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+def decode(code: Code, llr: torch.Tensor, max_iter: int, early_stop: bool = False, want_posterior: bool = True,
+           stream=None, workspace: torch.Tensor = None):
+    """Decode llr [frames, n] (float32 or float64, on the GPU).  Returns
+    (bits uint8 [frames, n], iters int32 [frames], posterior or None)."""
+    assert llr.is_cuda and llr.dim() == 2 and llr.shape[1] == code.n and llr.is_contiguous()
+    frames = llr.shape[0]
+    dev = llr.device
+    bits = torch.empty((frames, code.n), dtype=torch.uint8, device=dev)
+    iters = torch.empty(frames, dtype=torch.int32, device=dev)
+    post = torch.empty_like(llr) if want_posterior else None
+    need = ldpc_workspace_bytes(code.handle, llr.dtype, frames, max_iter)
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, dev)
+    flags = LDPC_EARLY_STOP if early_stop else 0
+    _check(ldpc_decode(code.handle, llr.dtype, frames, max_iter, flags, llr, bits, iters, post, workspace,
+                       workspace.numel(), stream), "ldpc_decode")
+    return bits, iters, post
+
+
+class Job:
+    """One job of a batch, holding its output tensors."""
+
+    def __init__(self, code: Code, llr: torch.Tensor, max_iter: int, early_stop: bool = False,
+                 want_posterior: bool = True):
+        assert llr.is_cuda and llr.dim() == 2 and llr.shape[1] == code.n and llr.is_contiguous()
+        self.code, self.llr, self.max_iter, self.early_stop = code, llr, max_iter, early_stop
+        dev = llr.device
+        self.bits = torch.empty((llr.shape[0], code.n), dtype=torch.uint8, device=dev)
+        self.iters = torch.empty(llr.shape[0], dtype=torch.int32, device=dev)
+        self.posterior = torch.empty_like(llr) if want_posterior else None
+
+    def c_struct(self) -> ldpc_job:
+        return ldpc_job(self.code.handle, self.llr.shape[0], self.max_iter,
+                        LDPC_EARLY_STOP if self.early_stop else 0, _ptr(self.llr), _ptr(self.bits),
+                        _ptr(self.iters), _ptr(self.posterior))
+
+
+def decode_batch(jobs, stream=None, workspace: torch.Tensor = None):
+    """Decode a list of Job in one ldpc_decode_batch call (outputs land in the Jobs)."""
+    assert jobs
+    dt = jobs[0].llr.dtype
+    cj = [j.c_struct() for j in jobs]
+    need = ldpc_batch_workspace_bytes(cj, dt)
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, jobs[0].llr.device)
+    _check(ldpc_decode_batch(cj, dt, workspace, workspace.numel(), stream), "ldpc_decode_batch")
+    return jobs

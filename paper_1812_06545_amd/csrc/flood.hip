@@ -1,0 +1,355 @@
+// Plain flooding path: one check-node and one variable-node kernel per
+// iteration, with every message of every frame streamed through HBM.
+//
+// Schedule (arxiv 1812.06545, Section II, two-phase message passing and
+// Algorithm 1): iteration t runs Loop 2 (all check nodes) as one launch, then
+// Loops 3 and 4 (all variable nodes; the hard decision is the sign of the
+// stored posterior) as a second launch; the launch boundary is the global
+// barrier the flooding schedule needs.
+//
+// Data layout (frame-interleaved, the idea of Section III-B's interleaving
+// kernels): every per-edge or per-variable array is stored [edge or
+// variable][frame] with frames innermost and padded to a multiple of 64, so a
+// wavefront holds one check row (or one variable) for 64 consecutive frames:
+// each lane is a frame, every load and store is a 256-byte (FP32) contiguous
+// segment, and the row's CSR indices are wave-uniform scalar loads.
+//
+// Stored state per frame: r (one message per edge), the posterior L (one per
+// variable) and the scaled channel values Lch.  The check kernel forms
+// q = L - r_old on the fly (Loop 3's extrinsic message), so q is never
+// written back; per iteration the HBM traffic is
+//   check:    read r, gather L (served from L2), write r
+//   variable: read r, read Lch, write L.
+//
+// Early stop: the check kernel of iteration t also forms the syndrome of the
+// previous hard decision x^(t-1) = [L^(t-1) < 0] from the L values it
+// gathers anyway, and marks unsatisfied frames.  The variable kernel of
+// iteration t then retires a frame whose syndrome was zero (iters = t-1) and
+// leaves its posterior untouched.  No host synchronisation is needed.
+#include <algorithm>
+
+#include "ldpc_internal.h"
+#include "spa_math.h"
+
+namespace ldpc {
+namespace {
+
+constexpr int kWaves = 4;  // wavefronts (rows or columns) per 256-thread block
+
+// Block -> (group of kWaves rows, frame chunk).  Workgroups are dispatched to
+// the 8 XCDs round-robin; when the chunk count allows it, XCD x gets chunks
+// x, x+8, ... and sweeps every row of one chunk before the next, so that the
+// chunk's posterior slice (n x 64 values) stays resident in that XCD's L2
+// while all rows gather from it.
+__device__ __forceinline__ void map_block(int b, int groups, int nchunk, int &group, int &chunk)
+{
+    if ((nchunk & 7) == 0) {
+        const int xcd = b & 7, j = b >> 3;
+        chunk = (j / groups) * 8 + xcd;
+        group = j % groups;
+    } else {
+        chunk = b / groups;
+        group = b % groups;
+    }
+}
+
+template <class A, int DMAX, bool FIRST, bool ES>
+__global__ __launch_bounds__(256) void k_check(const int32_t *__restrict__ row_ptr,
+                                               const int32_t *__restrict__ col_idx, int32_t m, int32_t groups,
+                                               int32_t nchunk, int64_t Fp, typename A::T *__restrict__ R,
+                                               const typename A::T *__restrict__ L, const int32_t *__restrict__ done,
+                                               int32_t *__restrict__ unsat)
+{
+    using T = typename A::T;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    int group, chunk;
+    map_block(static_cast<int>(blockIdx.x), groups, nchunk, group, chunk);
+    const int row = group * kWaves + wave;
+    if (row >= m)
+        return;
+    const int64_t f = static_cast<int64_t>(chunk) * 64 + lane;
+    if (ES && done[f] >= 0)
+        return;
+    const int32_t e0 = row_ptr[row];
+    const int32_t d = row_ptr[row + 1] - e0;
+    T a[DMAX], pre[DMAX];
+    T acc = T(0);
+    uint32_t sign_total = 0, parity = 0;
+#pragma unroll
+    for (int k = 0; k < DMAX; ++k) {
+        if (k < d) {
+            const int32_t col = col_idx[e0 + k];
+            const T lv = L[static_cast<int64_t>(col) * Fp + f];
+            if (ES)
+                parity ^= static_cast<uint32_t>(lv < T(0));
+            const T q = FIRST ? lv : lv - R[static_cast<int64_t>(e0 + k) * Fp + f];
+            check_row_forward<A>(q, a[k], pre[k], acc, sign_total);
+        }
+    }
+    if (ES && parity)
+        unsat[f] = 1;
+    check_row_backward<A, DMAX>(a, pre, d, sign_total,
+                                [&](int k, T r) { R[static_cast<int64_t>(e0 + k) * Fp + f] = r; });
+}
+
+template <class A, bool ES>
+__global__ __launch_bounds__(256) void k_variable(const int32_t *__restrict__ col_ptr,
+                                                  const int32_t *__restrict__ col_edge, int32_t n, int32_t groups,
+                                                  int32_t nchunk, int64_t Fp, const typename A::T *__restrict__ R,
+                                                  const typename A::T *__restrict__ Lch, typename A::T *__restrict__ L,
+                                                  int32_t *__restrict__ done, const int32_t *__restrict__ unsat,
+                                                  int32_t t_prev)
+{
+    using T = typename A::T;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    int group, chunk;
+    map_block(static_cast<int>(blockIdx.x), groups, nchunk, group, chunk);
+    const int col = group * kWaves + wave;
+    if (col >= n)
+        return;
+    const int64_t f = static_cast<int64_t>(chunk) * 64 + lane;
+    if (ES) {
+        if (done[f] >= 0)
+            return;
+        if (unsat[f] == 0) {  // x^(t-1) is a codeword: the frame stops at t-1
+            done[f] = t_prev;
+            return;
+        }
+    }
+    const int32_t k0 = col_ptr[col], k1 = col_ptr[col + 1];
+    T acc = Lch[static_cast<int64_t>(col) * Fp + f];
+#pragma unroll 4
+    for (int32_t k = k0; k < k1; ++k)
+        acc += R[static_cast<int64_t>(col_edge[k]) * Fp + f];
+    L[static_cast<int64_t>(col) * Fp + f] = acc;
+}
+
+// [frames][n] -> [n][Fp] through a 64x64 LDS tile; padding frames get LLR 1.
+template <class A>
+__global__ __launch_bounds__(256) void k_ingest(const typename A::T *__restrict__ llr, int32_t F, int32_t n,
+                                                int64_t Fp, typename A::T *__restrict__ Lch,
+                                                typename A::T *__restrict__ L)
+{
+    using T = typename A::T;
+    __shared__ T tile[64][65];
+    const int c0 = blockIdx.x * 64, f0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int f = f0 + i, c = c0 + tx;
+        T v = T(1);
+        if (f < F && c < n)
+            v = llr[static_cast<int64_t>(f) * n + c];
+        tile[i][tx] = v * T(A::kIn);
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int c = c0 + i;
+        if (c < n) {
+            const T v = tile[tx][i];
+            const int64_t o = static_cast<int64_t>(c) * Fp + f0 + tx;
+            Lch[o] = v;
+            L[o] = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_frames_init(int64_t Fp, int32_t *__restrict__ done,
+                                                     int32_t *__restrict__ unsat, int64_t unsat_words)
+{
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < Fp + unsat_words;
+         i += stride) {
+        if (i < Fp)
+            done[i] = -1;
+        else
+            unsat[i - Fp] = 0;
+    }
+}
+
+// [n][Fp] -> bits / posterior [frames][n]; iters.  A frame that ran no
+// iteration reports the caller's LLRs bit-exactly as its posterior.
+template <class A>
+__global__ __launch_bounds__(256) void k_output(const typename A::T *__restrict__ L,
+                                                const typename A::T *__restrict__ llr,
+                                                const int32_t *__restrict__ done, int32_t F, int32_t n, int64_t Fp,
+                                                int32_t max_iter, int32_t es, uint8_t *__restrict__ bits,
+                                                int32_t *__restrict__ iters, typename A::T *__restrict__ posterior)
+{
+    using T = typename A::T;
+    __shared__ T tile[64][65];
+    __shared__ int32_t it[64];
+    const int c0 = blockIdx.x * 64, f0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    if (threadIdx.x < 64) {
+        const int64_t f = f0 + threadIdx.x;
+        const int32_t v = (es && done[f] >= 0) ? done[f] : max_iter;
+        it[threadIdx.x] = v;
+        if (blockIdx.x == 0 && f < F)
+            iters[f] = v;
+    }
+    for (int i = ty; i < 64; i += 4) {
+        const int c = c0 + i;
+        tile[i][tx] = c < n ? L[static_cast<int64_t>(c) * Fp + f0 + tx] : T(0);
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int f = f0 + i, c = c0 + tx;
+        if (f < F && c < n) {
+            const T v = tile[tx][i];
+            const int64_t o = static_cast<int64_t>(f) * n + c;
+            bits[o] = static_cast<uint8_t>(v < T(0));
+            if (posterior)
+                posterior[o] = it[i] == 0 ? llr[o] : v * T(A::kOut);
+        }
+    }
+}
+
+struct Carve {
+    char *p;
+    template <class U>
+    U *take(size_t count)
+    {
+        U *r = reinterpret_cast<U *>(p);
+        p += align_up(count * sizeof(U), 256);
+        return r;
+    }
+};
+
+template <class A>
+size_t ws_bytes(const ldpc_code_s *c, int64_t Fp, int32_t max_iter)
+{
+    using T = typename A::T;
+    size_t b = 0;
+    b += align_up(static_cast<size_t>(c->E) * Fp * sizeof(T), 256);
+    b += 2 * align_up(static_cast<size_t>(c->n) * Fp * sizeof(T), 256);
+    b += align_up(static_cast<size_t>(Fp) * sizeof(int32_t), 256);
+    b += align_up(static_cast<size_t>(std::max(max_iter, 1)) * Fp * sizeof(int32_t), 256);
+    return b;
+}
+
+template <class A, int DMAX>
+void launch_check(const ldpc_code_s *c, bool first, bool es, dim3 grid, hipStream_t s, int32_t groups,
+                  int32_t nchunk, int64_t Fp, typename A::T *R, const typename A::T *L, const int32_t *done,
+                  int32_t *unsat)
+{
+#define LDPC_CHECK_LAUNCH(F_, E_)                                                                                \
+    hipLaunchKernelGGL((k_check<A, DMAX, F_, E_>), grid, dim3(256), 0, s, c->row_ptr, c->col_idx, c->m, groups, \
+                       nchunk, Fp, R, L, done, unsat)
+    if (first) {
+        if (es)
+            LDPC_CHECK_LAUNCH(true, true);
+        else
+            LDPC_CHECK_LAUNCH(true, false);
+    } else {
+        if (es)
+            LDPC_CHECK_LAUNCH(false, true);
+        else
+            LDPC_CHECK_LAUNCH(false, false);
+    }
+#undef LDPC_CHECK_LAUNCH
+}
+
+template <class A>
+ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, uint32_t flags, const void *llr_v,
+                        uint8_t *bits, int32_t *iters, void *post_v, void *ws, hipStream_t s)
+{
+    using T = typename A::T;
+    const int64_t Fp = frames_padded(frames);
+    const int32_t nchunk = static_cast<int32_t>(Fp / kChunk);
+    const bool es = (flags & LDPC_EARLY_STOP) != 0;
+    const T *llr = static_cast<const T *>(llr_v);
+    T *post = static_cast<T *>(post_v);
+
+    Carve cv{static_cast<char *>(ws)};
+    T *R = cv.take<T>(static_cast<size_t>(c->E) * Fp);
+    T *L = cv.take<T>(static_cast<size_t>(c->n) * Fp);
+    T *Lch = cv.take<T>(static_cast<size_t>(c->n) * Fp);
+    int32_t *done = cv.take<int32_t>(Fp);
+    int32_t *unsat = cv.take<int32_t>(static_cast<size_t>(std::max(max_iter, 1)) * Fp);
+
+    const int64_t unsat_words = es ? static_cast<int64_t>(max_iter) * Fp : 0;
+    const int init_blocks = static_cast<int>(std::min<int64_t>((Fp + unsat_words + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_frames_init, dim3(init_blocks), dim3(256), 0, s, Fp, done, unsat, unsat_words);
+    const dim3 tiles((c->n + 63) / 64, nchunk);
+    hipLaunchKernelGGL((k_ingest<A>), tiles, dim3(256), 0, s, llr, frames, c->n, Fp, Lch, L);
+
+    const int32_t rgroups = (c->m + kWaves - 1) / kWaves;
+    const int32_t cgroups = (c->n + kWaves - 1) / kWaves;
+    const dim3 rgrid(static_cast<unsigned>(rgroups) * nchunk), cgrid(static_cast<unsigned>(cgroups) * nchunk);
+    const int dmax = c->max_row_deg;
+    for (int32_t t = 1; t <= max_iter; ++t) {
+        const bool first = (t == 1);
+        int32_t *unsat_t = unsat + static_cast<int64_t>(t - 1) * Fp;
+        if (dmax <= 8)
+            launch_check<A, 8>(c, first, es, rgrid, s, rgroups, nchunk, Fp, R, L, done, unsat_t);
+        else if (dmax <= 16)
+            launch_check<A, 16>(c, first, es, rgrid, s, rgroups, nchunk, Fp, R, L, done, unsat_t);
+        else if (dmax <= 24)
+            launch_check<A, 24>(c, first, es, rgrid, s, rgroups, nchunk, Fp, R, L, done, unsat_t);
+        else if (dmax <= 32)
+            launch_check<A, 32>(c, first, es, rgrid, s, rgroups, nchunk, Fp, R, L, done, unsat_t);
+        else
+            launch_check<A, 64>(c, first, es, rgrid, s, rgroups, nchunk, Fp, R, L, done, unsat_t);
+        if (es)
+            hipLaunchKernelGGL((k_variable<A, true>), cgrid, dim3(256), 0, s, c->col_ptr, c->col_edge, c->n, cgroups,
+                               nchunk, Fp, R, Lch, L, done, unsat_t, t - 1);
+        else
+            hipLaunchKernelGGL((k_variable<A, false>), cgrid, dim3(256), 0, s, c->col_ptr, c->col_edge, c->n,
+                               cgroups, nchunk, Fp, R, Lch, L, done, unsat_t, t - 1);
+    }
+    hipLaunchKernelGGL((k_output<A>), tiles, dim3(256), 0, s, L, llr, done, frames, c->n, Fp, max_iter,
+                       static_cast<int32_t>(es), bits, iters, post);
+    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EDEVICE;
+}
+
+}  // namespace
+
+size_t stream_workspace_bytes(const ldpc_code_s *c, ldpc_dtype dt, int32_t frames, int32_t max_iter)
+{
+    const int64_t Fp = frames_padded(frames);
+    return dt == LDPC_F64 ? ws_bytes<ArithF64>(c, Fp, max_iter) : ws_bytes<ArithF32>(c, Fp, max_iter);
+}
+
+ldpc_status stream_decode(const ldpc_code_s *c, ldpc_dtype dt, int32_t frames, int32_t max_iter, uint32_t flags,
+                          const void *llr, uint8_t *bits, int32_t *iters, void *posterior, void *ws,
+                          hipStream_t stream)
+{
+    if (dt == LDPC_F64)
+        return decode_impl<ArithF64>(c, frames, max_iter, flags, llr, bits, iters, posterior, ws, stream);
+    return decode_impl<ArithF32>(c, frames, max_iter, flags, llr, bits, iters, posterior, ws, stream);
+}
+
+}  // namespace ldpc
+
+extern "C" ldpc_status ldpc_workspace_bytes(ldpc_code code, ldpc_dtype dtype, int32_t frames, int32_t max_iter,
+                                            size_t *bytes)
+{
+    if (!code || !bytes || frames < 0 || frames > LDPC_MAX_FRAMES || max_iter < 0 ||
+        (dtype != LDPC_F32 && dtype != LDPC_F64))
+        return LDPC_EINVAL;
+    *bytes = ldpc::stream_workspace_bytes(code, dtype, frames, max_iter);
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_decode(ldpc_code code, ldpc_dtype dtype, int32_t frames, int32_t max_iter,
+                                   uint32_t flags, const void *llr, uint8_t *bits, int32_t *iters, void *posterior,
+                                   void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!code || frames < 0 || frames > LDPC_MAX_FRAMES || max_iter < 0 || (flags & ~LDPC_EARLY_STOP) != 0 ||
+        (dtype != LDPC_F32 && dtype != LDPC_F64))
+        return LDPC_EINVAL;
+    if (frames == 0)
+        return LDPC_OK;
+    if (!llr || !bits || !iters || !workspace)
+        return LDPC_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return LDPC_EINVAL;
+    if (workspace_bytes < ldpc::stream_workspace_bytes(code, dtype, frames, max_iter))
+        return LDPC_EINVAL;
+    if (!ldpc::code_on_current_device(code))
+        return LDPC_EINVAL;
+    return ldpc::stream_decode(code, dtype, frames, max_iter, flags, llr, bits, iters, posterior, workspace,
+                               static_cast<hipStream_t>(stream));
+}

@@ -1,0 +1,66 @@
+// Internal declarations shared by the libldpc translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "ldpc.h"
+
+#define LDPC_HIP_OR_RETURN(expr)                 \
+    do {                                         \
+        hipError_t ldpc_e_ = (expr);             \
+        if (ldpc_e_ != hipSuccess)               \
+            return LDPC_EDEVICE;                 \
+    } while (0)
+
+// A code handle: H in device memory, in two layouts.
+//   CSR/CSC (every code): edges numbered in CSR order (rows ascending,
+//   columns ascending inside a row); col_edge lists each column's edges in
+//   ascending row order.  Used by the per-iteration streaming kernels.
+//   Circulant-block tables (QC codes only): blocks numbered row-major over
+//   the base matrix; the edge of block b in check row i*Z + r is b*Z + r.
+//   Used by the fused frame-resident kernel.
+struct ldpc_code_s {
+    int device = 0;
+    int32_t m = 0, n = 0;
+    int64_t E = 0;
+    int32_t max_row_deg = 0, max_col_deg = 0;
+    void *d_mem = nullptr;
+    const int32_t *row_ptr = nullptr;   // m + 1
+    const int32_t *col_idx = nullptr;   // E
+    const int32_t *col_ptr = nullptr;   // n + 1
+    const int32_t *col_edge = nullptr;  // E
+    // circulant-block tables (is_qc)
+    bool is_qc = false;
+    int32_t mb = 0, nb = 0, Z = 0, nblocks = 0;
+    int32_t max_brow_deg = 0, max_bcol_deg = 0;
+    // qc_tab layout (int32 words):
+    //   [0, mb]                 row_blk_start   (first block of block-row i; mb+1 entries)
+    //   [mb+1, +nblocks)        blk_col         (base column j of block b)
+    //   [.., +nblocks)          blk_shift       (shift s of block b)
+    //   [.., +nb+1)             col_blk_start   (nb+1 entries)
+    //   [.., +nblocks)          col_blk         (blocks of base column j, ascending block-row)
+    const int32_t *qc_tab = nullptr;
+    int32_t qc_words = 0;
+    std::vector<int32_t> h_qc_tab;
+};
+
+namespace ldpc {
+
+constexpr int kChunk = 64;  // frames per wavefront in the streaming layout
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int64_t frames_padded(int64_t frames) { return (frames + kChunk - 1) / kChunk * kChunk; }
+
+bool code_on_current_device(const ldpc_code_s *c);
+
+// Streaming (per-iteration) path.
+size_t stream_workspace_bytes(const ldpc_code_s *c, ldpc_dtype dt, int32_t frames, int32_t max_iter);
+ldpc_status stream_decode(const ldpc_code_s *c, ldpc_dtype dt, int32_t frames, int32_t max_iter, uint32_t flags,
+                          const void *llr, uint8_t *bits, int32_t *iters, void *posterior, void *ws,
+                          hipStream_t stream);
+
+}  // namespace ldpc
