@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Decoded Mbit/s of flooding sum-product LDPC decoding on one MI355X.
+
+Workload (one "step" = one batch through the whole decoder: ingest, 10
+iterations of check-node / variable-node updates with hard decisions, output):
+a seeded quasi-cyclic rate-1/2 code with a 12 x 24 base matrix and Z = 81
+(n = 1944), 4096 random codewords per batch, BPSK over AWGN, FP32, exactly 10
+iterations (early stop off).  Four batches at Eb/N0 = 1.0, 1.5, 2.0, 2.5 dB
+are resident in HBM and the steps cycle through them.
+
+Prints one JSON line: throughput (coded bits per second of device time), the
+dominant kernel's roofline position measured with HIP events inside the
+timed region, and the CPU oracle timed on the host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--path", choices=("plain", "batch"), default="plain",
+                    help="plain: per-iteration kernels (ldpc_decode); batch: ldpc_decode_batch")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+HBM_PEAK_GBS = 8000.0
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE={world}): "
+              "frames are independent, so multi-GPU decoding is a frame split with no exchange and is not "
+              "measured here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1812_06545_amd as L
+    from workloads import configs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    T = 10
+    batches = [configs.qc1944(snr) for snr in configs.QC1944_SNRS]
+    code = batches[0].code
+    F, n, E = batches[0].llr.shape[0], code.n, code.edges
+    k_info = batches[0].k
+    h = L.Code.from_workload(code)
+    llrs = [torch.from_numpy(b.llr).to(dev) for b in batches]
+    bits = torch.empty((F, n), dtype=torch.uint8, device=dev)
+    iters = torch.empty(F, dtype=torch.int32, device=dev)
+    post = torch.empty((F, n), dtype=torch.float32, device=dev)
+
+    if args.path == "plain":
+        ws_bytes = L.ldpc_workspace_bytes(h.handle, torch.float32, F, T)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+
+        def step(i):
+            st = L.ldpc_decode(h.handle, torch.float32, F, T, 0, llrs[i % 4], bits, iters, post, ws, ws_bytes)
+            if st != 0:
+                raise L.LdpcError(st, "ldpc_decode")
+    else:
+        jobs = [[L.ldpc_job(h.handle, F, T, 0, llrs[i].data_ptr(), bits.data_ptr(), iters.data_ptr(),
+                            post.data_ptr())] for i in range(4)]
+        ws_bytes = L.ldpc_batch_workspace_bytes(jobs[0], torch.float32)
+        ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+
+        def step(i):
+            st = L.ldpc_decode_batch(jobs[i % 4], torch.float32, ws, ws_bytes)
+            if st != 0:
+                raise L.LdpcError(st, "ldpc_decode_batch")
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    L.ldpc_profile_collect()
+    L.ldpc_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    L.ldpc_profile_enable(False)
+    prof = L.ldpc_profile_collect()
+
+    ms_per_step = elapsed * 1e3 / args.steps
+    coded_bits = F * n
+    value = coded_bits * args.steps / elapsed / 1e6
+
+    # Roofline of the dominant kernel.  Algorithmic bytes of one check-node
+    # launch over F frames: read r (4E, not on the first iteration), write r
+    # (4E), read the posterior once per variable (4n).
+    if args.path == "plain":
+        name, (kms, kcount) = "check", prof["check"]
+        per_frame_first = 4 * E + 4 * n
+        per_frame_later = 8 * E + 4 * n
+        bytes_per_launch = F * (per_frame_first + (T - 1) * per_frame_later) / T
+    else:
+        name, (kms, kcount) = "fused", prof["fused"]
+        # frame-resident kernel: reads the channel LLRs and writes bits and the
+        # posterior once per frame; messages live in LDS
+        bytes_per_launch = F * (4 * n + n + 4 * n + 4)
+    avg_ms = kms / max(kcount, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if kcount else None
+    roofline = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "launch_ms": avg_ms, "launches": kcount, "bytes_per_launch": bytes_per_launch}
+    kernels = {k: {"ms_total": v[0], "launches": v[1]} for k, v in prof.items() if v[1]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(batches[2], T, args.cpu_seconds)
+
+    out = {
+        "metric": "decoded Mbit/s @10 iters n=1944 FP32",
+        "value": value,
+        "unit": "Mbit/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "qc1944: seeded QC code, 12x24 base, Z=81, n=1944, rate 1/2, 4096 frames/step, "
+                               "10 iterations (no early stop), BPSK/AWGN at 1.0/1.5/2.0/2.5 dB",
+                   "path": args.path, "frames": F, "n": n, "edges": E, "iterations": T},
+        "info_mbps": k_info * F * args.steps / elapsed / 1e6,
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(batch, T, seconds):
+    """The oracle (plain FP64 C, as committed) on the host cores, over as many
+    frames of the 2.0 dB batch as fit in about `seconds` of wall time."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS") or min(16, os.cpu_count() or 1))
+    code = batch.code
+    probe = 2 * threads
+    t0 = time.perf_counter()
+    oracle.decode(code, batch.llr[:probe], T, False, nthreads=threads, want_trace=False)
+    per_frame = (time.perf_counter() - t0) / probe
+    frames = int(min(batch.llr.shape[0], max(probe, seconds / max(per_frame, 1e-9))))
+    t0 = time.perf_counter()
+    oracle.decode(code, batch.llr[:frames], T, False, nthreads=threads, want_trace=False)
+    wall = time.perf_counter() - t0
+    return {"value": frames * code.n / wall / 1e6, "unit": "Mbit/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {frames} of 4096 frames of the 2.0 dB batch, {T} iterations, FP64, "
+                      f"{threads} OpenMP threads, {wall:.1f} s wall"}
+
+
+if __name__ == "__main__":
+    main()

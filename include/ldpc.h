@@ -45,6 +45,10 @@
 extern "C" {
 #endif
 
+#if defined(__GNUC__)
+#pragma GCC visibility push(default)
+#endif
+
 typedef enum {
     LDPC_OK = 0,
     LDPC_EINVAL = -1,       /* invalid argument; nothing was enqueued or written */
@@ -158,6 +162,32 @@ ldpc_status ldpc_batch_workspace_bytes(const ldpc_job *jobs, int32_t njobs, ldpc
  */
 ldpc_status ldpc_decode_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, void *workspace,
                               size_t workspace_bytes, void *stream);
+
+/*
+ * Per-kernel device timing, a measurement aid (not part of decoding).  While
+ * enabled, every kernel the library launches outside a stream capture is
+ * bracketed by a pair of HIP events on its own stream.  ldpc_profile_collect
+ * waits for the recorded events, writes for each kernel kind k the summed
+ * device duration ms[k] (milliseconds) and launch count counts[k] (arrays of
+ * LDPC_KERNEL_KINDS entries, either may be NULL), and clears the records.
+ * Enabling adds two event records per launch; it is off by default.
+ */
+typedef enum {
+    LDPC_KERNEL_INGEST = 0,    /* caller layout -> frame-interleaved layout */
+    LDPC_KERNEL_CHECK = 1,     /* check-node update, one iteration */
+    LDPC_KERNEL_VARIABLE = 2,  /* variable-node update + hard decision, one iteration */
+    LDPC_KERNEL_OUTPUT = 3,    /* frame-interleaved -> caller layout */
+    LDPC_KERNEL_FUSED = 4,     /* persistent frame-resident decoder (all iterations) */
+    LDPC_KERNEL_OTHER = 5,     /* small bookkeeping kernels */
+    LDPC_KERNEL_KINDS = 6
+} ldpc_kernel_kind;
+
+ldpc_status ldpc_profile_enable(int enable);
+ldpc_status ldpc_profile_collect(double *ms, int64_t *counts);
+
+#if defined(__GNUC__)
+#pragma GCC visibility pop
+#endif
 
 #ifdef __cplusplus
 }

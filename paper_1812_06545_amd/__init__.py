@@ -58,6 +58,10 @@ _sig("ldpc_decode", ctypes.c_int, [_P, ctypes.c_int, _I32, _I32, ctypes.c_uint32
 _sig("ldpc_batch_workspace_bytes", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int,
                                                   ctypes.POINTER(ctypes.c_size_t)])
 _sig("ldpc_decode_batch", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, _P, ctypes.c_size_t, _P])
+_sig("ldpc_profile_enable", ctypes.c_int, [ctypes.c_int])
+_sig("ldpc_profile_collect", ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)])
+
+KERNEL_KINDS = ("ingest", "check", "variable", "output", "fused", "other")
 
 
 class LdpcError(RuntimeError):
@@ -171,6 +175,18 @@ def ldpc_decode_batch(jobs, dtype, workspace, workspace_bytes, stream=None) -> i
     arr = _jobs_array(jobs)
     return _lib.ldpc_decode_batch(arr, len(jobs), _dtype_code(dtype), _ptr(workspace), int(workspace_bytes),
                                   _stream_handle(stream))
+
+
+def ldpc_profile_enable(enable: bool) -> int:
+    return _lib.ldpc_profile_enable(int(bool(enable)))
+
+
+def ldpc_profile_collect():
+    """{kind: (total_ms, launches)} since the last collect (waits for the events)."""
+    ms = (ctypes.c_double * len(KERNEL_KINDS))()
+    cnt = (ctypes.c_int64 * len(KERNEL_KINDS))()
+    _check(_lib.ldpc_profile_collect(ms, cnt), "ldpc_profile_collect")
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS)}
 
 
 # ------------------------------------------------------------ conveniences --

@@ -8,11 +8,14 @@
 // barrier the flooding schedule needs.
 //
 // Data layout (frame-interleaved, the idea of Section III-B's interleaving
-// kernels): every per-edge or per-variable array is stored [edge or
-// variable][frame] with frames innermost and padded to a multiple of 64, so a
-// wavefront holds one check row (or one variable) for 64 consecutive frames:
-// each lane is a frame, every load and store is a 256-byte (FP32) contiguous
-// segment, and the row's CSR indices are wave-uniform scalar loads.
+// kernels): frames are padded to a multiple of 64 and grouped in chunks of 64;
+// every per-edge or per-variable array is stored [chunk][edge or
+// variable][64 frames].  A wavefront holds one check row (or one variable)
+// for the 64 frames of a chunk: each lane is a frame, every load and store is
+// a 256-byte (FP32) contiguous segment, the row's CSR indices are
+// wave-uniform scalar loads, and all data of a chunk (E + 2n segments) is one
+// contiguous region, which keeps DRAM pages and address translations local
+// while an XCD works through the chunk.
 //
 // Stored state per frame: r (one message per edge), the posterior L (one per
 // variable) and the scaled channel values Lch.  The check kernel forms
@@ -28,109 +31,17 @@
 // leaves its posterior untouched.  No host synchronisation is needed.
 #include <algorithm>
 
-#include "ldpc_internal.h"
-#include "spa_math.h"
+#include "flood_kernels.h"
 
 namespace ldpc {
 namespace {
 
-constexpr int kWaves = 4;  // wavefronts (rows or columns) per 256-thread block
+using namespace flood;
 
-// Block -> (group of kWaves rows, frame chunk).  Workgroups are dispatched to
-// the 8 XCDs round-robin; when the chunk count allows it, XCD x gets chunks
-// x, x+8, ... and sweeps every row of one chunk before the next, so that the
-// chunk's posterior slice (n x 64 values) stays resident in that XCD's L2
-// while all rows gather from it.
-__device__ __forceinline__ void map_block(int b, int groups, int nchunk, int &group, int &chunk)
-{
-    if ((nchunk & 7) == 0) {
-        const int xcd = b & 7, j = b >> 3;
-        chunk = (j / groups) * 8 + xcd;
-        group = j % groups;
-    } else {
-        chunk = b / groups;
-        group = b % groups;
-    }
-}
-
-template <class A, int DMAX, bool FIRST, bool ES>
-__global__ __launch_bounds__(256) void k_check(const int32_t *__restrict__ row_ptr,
-                                               const int32_t *__restrict__ col_idx, int32_t m, int32_t groups,
-                                               int32_t nchunk, int64_t Fp, typename A::T *__restrict__ R,
-                                               const typename A::T *__restrict__ L, const int32_t *__restrict__ done,
-                                               int32_t *__restrict__ unsat)
-{
-    using T = typename A::T;
-    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-    const int lane = static_cast<int>(threadIdx.x & 63);
-    int group, chunk;
-    map_block(static_cast<int>(blockIdx.x), groups, nchunk, group, chunk);
-    const int row = group * kWaves + wave;
-    if (row >= m)
-        return;
-    const int64_t f = static_cast<int64_t>(chunk) * 64 + lane;
-    if (ES && done[f] >= 0)
-        return;
-    const int32_t e0 = row_ptr[row];
-    const int32_t d = row_ptr[row + 1] - e0;
-    T a[DMAX], pre[DMAX];
-    T acc = T(0);
-    uint32_t sign_total = 0, parity = 0;
-#pragma unroll
-    for (int k = 0; k < DMAX; ++k) {
-        if (k < d) {
-            const int32_t col = col_idx[e0 + k];
-            const T lv = L[static_cast<int64_t>(col) * Fp + f];
-            if (ES)
-                parity ^= static_cast<uint32_t>(lv < T(0));
-            const T q = FIRST ? lv : lv - R[static_cast<int64_t>(e0 + k) * Fp + f];
-            check_row_forward<A>(q, a[k], pre[k], acc, sign_total);
-        }
-    }
-    if (ES && parity)
-        unsat[f] = 1;
-    check_row_backward<A, DMAX>(a, pre, d, sign_total,
-                                [&](int k, T r) { R[static_cast<int64_t>(e0 + k) * Fp + f] = r; });
-}
-
-template <class A, bool ES>
-__global__ __launch_bounds__(256) void k_variable(const int32_t *__restrict__ col_ptr,
-                                                  const int32_t *__restrict__ col_edge, int32_t n, int32_t groups,
-                                                  int32_t nchunk, int64_t Fp, const typename A::T *__restrict__ R,
-                                                  const typename A::T *__restrict__ Lch, typename A::T *__restrict__ L,
-                                                  int32_t *__restrict__ done, const int32_t *__restrict__ unsat,
-                                                  int32_t t_prev)
-{
-    using T = typename A::T;
-    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-    const int lane = static_cast<int>(threadIdx.x & 63);
-    int group, chunk;
-    map_block(static_cast<int>(blockIdx.x), groups, nchunk, group, chunk);
-    const int col = group * kWaves + wave;
-    if (col >= n)
-        return;
-    const int64_t f = static_cast<int64_t>(chunk) * 64 + lane;
-    if (ES) {
-        if (done[f] >= 0)
-            return;
-        if (unsat[f] == 0) {  // x^(t-1) is a codeword: the frame stops at t-1
-            done[f] = t_prev;
-            return;
-        }
-    }
-    const int32_t k0 = col_ptr[col], k1 = col_ptr[col + 1];
-    T acc = Lch[static_cast<int64_t>(col) * Fp + f];
-#pragma unroll 4
-    for (int32_t k = k0; k < k1; ++k)
-        acc += R[static_cast<int64_t>(col_edge[k]) * Fp + f];
-    L[static_cast<int64_t>(col) * Fp + f] = acc;
-}
-
-// [frames][n] -> [n][Fp] through a 64x64 LDS tile; padding frames get LLR 1.
+// [frames][n] -> [chunk][n][64] through a 64x64 LDS tile; padding frames get LLR 1.
 template <class A>
 __global__ __launch_bounds__(256) void k_ingest(const typename A::T *__restrict__ llr, int32_t F, int32_t n,
-                                                int64_t Fp, typename A::T *__restrict__ Lch,
-                                                typename A::T *__restrict__ L)
+                                                typename A::T *__restrict__ Lch, typename A::T *__restrict__ L)
 {
     using T = typename A::T;
     __shared__ T tile[64][65];
@@ -148,7 +59,7 @@ __global__ __launch_bounds__(256) void k_ingest(const typename A::T *__restrict_
         const int c = c0 + i;
         if (c < n) {
             const T v = tile[tx][i];
-            const int64_t o = static_cast<int64_t>(c) * Fp + f0 + tx;
+            const int64_t o = (static_cast<int64_t>(blockIdx.y) * n + c) * kChunk + tx;
             Lch[o] = v;
             L[o] = v;
         }
@@ -168,12 +79,12 @@ __global__ __launch_bounds__(256) void k_frames_init(int64_t Fp, int32_t *__rest
     }
 }
 
-// [n][Fp] -> bits / posterior [frames][n]; iters.  A frame that ran no
+// [chunk][n][64] -> bits / posterior [frames][n]; iters.  A frame that ran no
 // iteration reports the caller's LLRs bit-exactly as its posterior.
 template <class A>
 __global__ __launch_bounds__(256) void k_output(const typename A::T *__restrict__ L,
                                                 const typename A::T *__restrict__ llr,
-                                                const int32_t *__restrict__ done, int32_t F, int32_t n, int64_t Fp,
+                                                const int32_t *__restrict__ done, int32_t F, int32_t n,
                                                 int32_t max_iter, int32_t es, uint8_t *__restrict__ bits,
                                                 int32_t *__restrict__ iters, typename A::T *__restrict__ posterior)
 {
@@ -191,7 +102,7 @@ __global__ __launch_bounds__(256) void k_output(const typename A::T *__restrict_
     }
     for (int i = ty; i < 64; i += 4) {
         const int c = c0 + i;
-        tile[i][tx] = c < n ? L[static_cast<int64_t>(c) * Fp + f0 + tx] : T(0);
+        tile[i][tx] = c < n ? L[(static_cast<int64_t>(blockIdx.y) * n + c) * kChunk + tx] : T(0);
     }
     __syncthreads();
     for (int i = ty; i < 64; i += 4) {
@@ -229,26 +140,40 @@ size_t ws_bytes(const ldpc_code_s *c, int64_t Fp, int32_t max_iter)
     return b;
 }
 
-template <class A, int DMAX>
-void launch_check(const ldpc_code_s *c, bool first, bool es, dim3 grid, hipStream_t s, int32_t groups,
-                  int32_t nchunk, int64_t Fp, typename A::T *R, const typename A::T *L, const int32_t *done,
-                  int32_t *unsat)
+// Smallest kernel bucket that holds every row of the code.
+template <class A>
+void launch_check(const ldpc_code_s *c, bool first, bool es, dim3 grid, hipStream_t s, const CheckArgs<A> &a);
+
+template <>
+void launch_check<ArithF32>(const ldpc_code_s *c, bool first, bool es, dim3 grid, hipStream_t s,
+                            const CheckArgs<ArithF32> &a)
 {
-#define LDPC_CHECK_LAUNCH(F_, E_)                                                                                \
-    hipLaunchKernelGGL((k_check<A, DMAX, F_, E_>), grid, dim3(256), 0, s, c->row_ptr, c->col_idx, c->m, groups, \
-                       nchunk, Fp, R, L, done, unsat)
-    if (first) {
-        if (es)
-            LDPC_CHECK_LAUNCH(true, true);
-        else
-            LDPC_CHECK_LAUNCH(true, false);
-    } else {
-        if (es)
-            LDPC_CHECK_LAUNCH(false, true);
-        else
-            LDPC_CHECK_LAUNCH(false, false);
-    }
-#undef LDPC_CHECK_LAUNCH
+    const int d = c->max_row_deg;
+    if (d <= 8)
+        launch_check_bucket<ArithF32, 8, true>(a, first, es, grid, s);
+    else if (d <= 16)
+        launch_check_bucket<ArithF32, 16, true>(a, first, es, grid, s);
+    else if (d <= 24)
+        launch_check_bucket<ArithF32, 24, true>(a, first, es, grid, s);
+    else if (d <= 32)
+        launch_check_bucket<ArithF32, 32, true>(a, first, es, grid, s);
+    else
+        launch_check_bucket<ArithF32, 64, false>(a, first, es, grid, s);
+}
+
+template <>
+void launch_check<ArithF64>(const ldpc_code_s *c, bool first, bool es, dim3 grid, hipStream_t s,
+                            const CheckArgs<ArithF64> &a)
+{
+    const int d = c->max_row_deg;
+    if (d <= 8)
+        launch_check_bucket<ArithF64, 8, false>(a, first, es, grid, s);
+    else if (d <= 16)
+        launch_check_bucket<ArithF64, 16, false>(a, first, es, grid, s);
+    else if (d <= 32)
+        launch_check_bucket<ArithF64, 32, false>(a, first, es, grid, s);
+    else
+        launch_check_bucket<ArithF64, 64, false>(a, first, es, grid, s);
 }
 
 template <class A>
@@ -271,36 +196,40 @@ ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, 
 
     const int64_t unsat_words = es ? static_cast<int64_t>(max_iter) * Fp : 0;
     const int init_blocks = static_cast<int>(std::min<int64_t>((Fp + unsat_words + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_frames_init, dim3(init_blocks), dim3(256), 0, s, Fp, done, unsat, unsat_words);
+    {
+        ProfScope ps(LDPC_KERNEL_OTHER, s);
+        hipLaunchKernelGGL(k_frames_init, dim3(init_blocks), dim3(256), 0, s, Fp, done, unsat, unsat_words);
+    }
     const dim3 tiles((c->n + 63) / 64, nchunk);
-    hipLaunchKernelGGL((k_ingest<A>), tiles, dim3(256), 0, s, llr, frames, c->n, Fp, Lch, L);
+    {
+        ProfScope ps(LDPC_KERNEL_INGEST, s);
+        hipLaunchKernelGGL((k_ingest<A>), tiles, dim3(256), 0, s, llr, frames, c->n, Lch, L);
+    }
 
     const int32_t rgroups = (c->m + kWaves - 1) / kWaves;
     const int32_t cgroups = (c->n + kWaves - 1) / kWaves;
     const dim3 rgrid(static_cast<unsigned>(rgroups) * nchunk), cgrid(static_cast<unsigned>(cgroups) * nchunk);
-    const int dmax = c->max_row_deg;
     for (int32_t t = 1; t <= max_iter; ++t) {
         const bool first = (t == 1);
         int32_t *unsat_t = unsat + static_cast<int64_t>(t - 1) * Fp;
-        if (dmax <= 8)
-            launch_check<A, 8>(c, first, es, rgrid, s, rgroups, nchunk, Fp, R, L, done, unsat_t);
-        else if (dmax <= 16)
-            launch_check<A, 16>(c, first, es, rgrid, s, rgroups, nchunk, Fp, R, L, done, unsat_t);
-        else if (dmax <= 24)
-            launch_check<A, 24>(c, first, es, rgrid, s, rgroups, nchunk, Fp, R, L, done, unsat_t);
-        else if (dmax <= 32)
-            launch_check<A, 32>(c, first, es, rgrid, s, rgroups, nchunk, Fp, R, L, done, unsat_t);
-        else
-            launch_check<A, 64>(c, first, es, rgrid, s, rgroups, nchunk, Fp, R, L, done, unsat_t);
+        {
+            ProfScope ps(LDPC_KERNEL_CHECK, s);
+            const CheckArgs<A> ca{c->row_ptr, c->col_idx, c->m, c->n, c->E, rgroups, nchunk, R, L, done, unsat_t};
+            launch_check<A>(c, first, es, rgrid, s, ca);
+        }
+        ProfScope ps(LDPC_KERNEL_VARIABLE, s);
         if (es)
-            hipLaunchKernelGGL((k_variable<A, true>), cgrid, dim3(256), 0, s, c->col_ptr, c->col_edge, c->n, cgroups,
-                               nchunk, Fp, R, Lch, L, done, unsat_t, t - 1);
+            hipLaunchKernelGGL((k_variable<A, true>), cgrid, dim3(256), 0, s, c->col_ptr, c->col_edge, c->n, c->E,
+                               cgroups, nchunk, R, Lch, L, done, unsat_t, t - 1);
         else
-            hipLaunchKernelGGL((k_variable<A, false>), cgrid, dim3(256), 0, s, c->col_ptr, c->col_edge, c->n,
-                               cgroups, nchunk, Fp, R, Lch, L, done, unsat_t, t - 1);
+            hipLaunchKernelGGL((k_variable<A, false>), cgrid, dim3(256), 0, s, c->col_ptr, c->col_edge, c->n, c->E,
+                               cgroups, nchunk, R, Lch, L, done, unsat_t, t - 1);
     }
-    hipLaunchKernelGGL((k_output<A>), tiles, dim3(256), 0, s, L, llr, done, frames, c->n, Fp, max_iter,
-                       static_cast<int32_t>(es), bits, iters, post);
+    {
+        ProfScope ps(LDPC_KERNEL_OUTPUT, s);
+        hipLaunchKernelGGL((k_output<A>), tiles, dim3(256), 0, s, L, llr, done, frames, c->n, max_iter,
+                           static_cast<int32_t>(es), bits, iters, post);
+    }
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EDEVICE;
 }
 

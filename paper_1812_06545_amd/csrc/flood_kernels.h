@@ -1,0 +1,266 @@
+// Device code of the plain flooding path: check-node and variable-node
+// kernels over the chunked frame-interleaved layout (flood.hip describes the
+// layout and the schedule).  Included by the check-kernel translation units (one per
+// dtype and degree bucket, compiled in parallel) and by flood.hip.
+#pragma once
+
+#include "ldpc_internal.h"
+#include "spa_math.h"
+
+namespace ldpc {
+namespace flood {
+
+constexpr int kWaves = 4;  // wavefronts (rows or columns) per 256-thread block
+
+// Block -> (group of kWaves rows, frame chunk).  Workgroups are dispatched to
+// the 8 XCDs round-robin; when the chunk count allows it, XCD x gets chunks
+// x, x+8, ... and sweeps every row of one chunk before the next, so that the
+// chunk's posterior slice (n x 64 values) stays resident in that XCD's L2
+// while all rows gather from it.
+__device__ __forceinline__ void map_block(int b, int groups, int nchunk, int &group, int &chunk)
+{
+    if ((nchunk & 7) == 0) {
+        const int xcd = b & 7, j = b >> 3;
+        chunk = (j / groups) * 8 + xcd;
+        group = j % groups;
+    } else {
+        chunk = b / groups;
+        group = b % groups;
+    }
+}
+
+// Access `lane_off` bytes past a wave-uniform base pointer: the base stays in
+// scalar registers and one 32-bit lane offset serves every access.
+template <class T>
+__device__ __forceinline__ T ld_lane(const T *base, uint32_t lane_off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + lane_off);
+}
+template <class T>
+__device__ __forceinline__ void st_lane(T *base, uint32_t lane_off, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + lane_off) = v;
+}
+
+// One check row of compile-time degree D: all 2D loads are issued before any
+// arithmetic (the wave waits once per row, and straight-line code lets each
+// edge start as soon as its own loads land).
+template <class A, int D, bool FIRST, bool ES>
+__device__ __forceinline__ void check_row(const int32_t *__restrict__ cols, const typename A::T *__restrict__ L,
+                                          typename A::T *__restrict__ Rrow, uint32_t off, uint32_t &parity)
+{
+    using T = typename A::T;
+    T lv[D], rv[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        lv[k] = ld_lane(L + cols[k] * kChunk, off);
+        rv[k] = FIRST ? T(0) : ld_lane(Rrow + k * kChunk, off);
+    }
+    T a[D], pre[D];
+    T acc = T(0);
+    uint32_t sign_total = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (ES)
+            parity ^= static_cast<uint32_t>(lv[k] < T(0));
+        const T q = FIRST ? lv[k] : lv[k] - rv[k];
+        check_row_forward<A>(q, a[k], pre[k], acc, sign_total);
+    }
+    check_row_backward<A, D>(a, pre, D, sign_total, [&](int k, T r) { st_lane(Rrow + k * kChunk, off, r); });
+}
+
+// The same row for a run-time degree d <= DMAX (guarded loops; used for FP64
+// and for degrees above the largest exact bucket).
+template <class A, int DMAX, bool FIRST, bool ES>
+__device__ __forceinline__ void check_row_guarded(const int32_t *__restrict__ cols, int d,
+                                                  const typename A::T *__restrict__ L, typename A::T *__restrict__ Rrow,
+                                                  uint32_t off, uint32_t &parity)
+{
+    using T = typename A::T;
+    T lv[DMAX], rv[DMAX];
+#pragma unroll
+    for (int k = 0; k < DMAX; ++k) {
+        if (k < d) {
+            lv[k] = ld_lane(L + cols[k] * kChunk, off);
+            rv[k] = FIRST ? T(0) : ld_lane(Rrow + k * kChunk, off);
+        }
+    }
+    T a[DMAX], pre[DMAX];
+    T acc = T(0);
+    uint32_t sign_total = 0;
+#pragma unroll
+    for (int k = 0; k < DMAX; ++k) {
+        if (k < d) {
+            if (ES)
+                parity ^= static_cast<uint32_t>(lv[k] < T(0));
+            const T q = FIRST ? lv[k] : lv[k] - rv[k];
+            check_row_forward<A>(q, a[k], pre[k], acc, sign_total);
+        }
+    }
+    check_row_backward<A, DMAX>(a, pre, d, sign_total, [&](int k, T r) { st_lane(Rrow + k * kChunk, off, r); });
+}
+
+// Exact-degree dispatch for d in [D, DB]: one straight-line body per degree,
+// so no unrolled loop carries guards (a guard makes every array element a
+// control-flow merge and inflates register use).  A kernel's register budget
+// is that of its largest body, hence one kernel per degree bucket DB.
+template <class A, int D, int DB, bool FIRST, bool ES>
+__device__ __forceinline__ void check_row_exact(int d, const int32_t *__restrict__ cols,
+                                                const typename A::T *__restrict__ L, typename A::T *__restrict__ Rrow,
+                                                uint32_t off, uint32_t &parity)
+{
+    if constexpr (D < DB) {
+        if (d == D)
+            check_row<A, D, FIRST, ES>(cols, L, Rrow, off, parity);
+        else
+            check_row_exact<A, D + 1, DB, FIRST, ES>(d, cols, L, Rrow, off, parity);
+    } else {
+        check_row<A, DB, FIRST, ES>(cols, L, Rrow, off, parity);
+    }
+}
+
+// Check-node kernel (Loop 2): one wavefront = one check row x 64 frames.
+// Rows must have degree <= DB.  EXACT selects straight-line bodies per degree.
+template <class A, int DB, bool EXACT, bool FIRST, bool ES>
+__global__ __launch_bounds__(256) void k_check(const int32_t *__restrict__ row_ptr,
+                                               const int32_t *__restrict__ col_idx, int32_t m, int32_t n, int64_t E,
+                                               int32_t groups, int32_t nchunk, typename A::T *__restrict__ R,
+                                               const typename A::T *__restrict__ L, const int32_t *__restrict__ done,
+                                               int32_t *__restrict__ unsat)
+{
+    using T = typename A::T;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    int group, chunk;
+    map_block(static_cast<int>(blockIdx.x), groups, nchunk, group, chunk);
+    const int row = group * kWaves + wave;
+    if (row >= m)
+        return;
+    const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
+    if (ES && done[f] >= 0)
+        return;
+    const uint32_t off = static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(T));
+    const int32_t e0 = row_ptr[row];
+    const int32_t d = __builtin_amdgcn_readfirstlane(row_ptr[row + 1] - e0);
+    uint32_t parity = 0;
+    T *Rrow = R + (static_cast<int64_t>(chunk) * E + e0) * kChunk;
+    const T *Lc = L + static_cast<int64_t>(chunk) * n * kChunk;
+    if (d > 0) {
+        if constexpr (EXACT)
+            check_row_exact<A, 1, DB, FIRST, ES>(d, col_idx + e0, Lc, Rrow, off, parity);
+        else
+            check_row_guarded<A, DB, FIRST, ES>(col_idx + e0, d, Lc, Rrow, off, parity);
+    }
+    if (ES && parity)
+        unsat[f] = 1;
+}
+
+// L = Lch + sum of the column's r in ascending row order, for a column of
+// compile-time degree D (loads first, then the ordered sum).
+template <class A, int D>
+__device__ __forceinline__ typename A::T column_sum(typename A::T acc, const int32_t *__restrict__ edges,
+                                                    const typename A::T *__restrict__ R, uint32_t off)
+{
+    using T = typename A::T;
+    T rv[D > 0 ? D : 1];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        rv[k] = ld_lane(R + edges[k] * kChunk, off);
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        acc += rv[k];
+    return acc;
+}
+
+template <class A, int D>
+__device__ __forceinline__ typename A::T column_sum_exact(int dv, typename A::T acc, const int32_t *__restrict__ edges,
+                                                          const typename A::T *__restrict__ R, uint32_t off)
+{
+    if constexpr (D <= 16) {
+        if (dv == D)
+            return column_sum<A, D>(acc, edges, R, off);
+        return column_sum_exact<A, D + 1>(dv, acc, edges, R, off);
+    } else {
+        for (int32_t k = 0; k < dv; ++k)  // rare high-degree columns
+            acc += ld_lane(R + edges[k] * kChunk, off);
+        return acc;
+    }
+}
+
+// Variable-node kernel (Loops 3 and 4): one wavefront = one variable x 64
+// frames.  The hard decision is the sign of the stored posterior.
+template <class A, bool ES>
+__global__ __launch_bounds__(256) void k_variable(const int32_t *__restrict__ col_ptr,
+                                                  const int32_t *__restrict__ col_edge, int32_t n, int64_t E,
+                                                  int32_t groups, int32_t nchunk, const typename A::T *__restrict__ R,
+                                                  const typename A::T *__restrict__ Lch, typename A::T *__restrict__ L,
+                                                  int32_t *__restrict__ done, const int32_t *__restrict__ unsat,
+                                                  int32_t t_prev)
+{
+    using T = typename A::T;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    int group, chunk;
+    map_block(static_cast<int>(blockIdx.x), groups, nchunk, group, chunk);
+    const int col = group * kWaves + wave;
+    if (col >= n)
+        return;
+    const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
+    if (ES) {
+        if (done[f] >= 0)
+            return;
+        if (unsat[f] == 0) {  // x^(t-1) is a codeword: the frame stops at t-1
+            done[f] = t_prev;
+            return;
+        }
+    }
+    const uint32_t off = static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(T));
+    const int32_t k0 = col_ptr[col];
+    const int32_t dv = __builtin_amdgcn_readfirstlane(col_ptr[col + 1] - k0);
+    const int64_t vo = (static_cast<int64_t>(chunk) * n + col) * kChunk;
+    const T *Rc = R + static_cast<int64_t>(chunk) * E * kChunk;
+    const T acc = ld_lane(Lch + vo, off);
+    st_lane(L + vo, off, column_sum_exact<A, 0>(dv, acc, col_edge + k0, Rc, off));
+}
+
+}  // namespace flood
+
+// Arguments of one check-node launch.
+template <class A>
+struct CheckArgs {
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    int32_t m, n;
+    int64_t E;
+    int32_t groups, nchunk;
+    typename A::T *R;
+    const typename A::T *L;
+    const int32_t *done;
+    int32_t *unsat;
+};
+
+// Launcher of the check kernel for rows of degree <= DB; each (dtype, bucket)
+// is defined in its own translation unit.
+template <class A, int DB, bool EXACT>
+void launch_check_bucket(const CheckArgs<A> &a, bool first, bool es, dim3 grid, hipStream_t s);
+
+#define LDPC_CHECK_LAUNCH_ONE(A_, DB_, EX_, F_, E_)                                                              \
+    hipLaunchKernelGGL((flood::k_check<A_, DB_, EX_, F_, E_>), grid, dim3(256), 0, s, a.row_ptr, a.col_idx, a.m, \
+                       a.n, a.E, a.groups, a.nchunk, a.R, a.L, a.done, a.unsat)
+
+#define LDPC_DEFINE_CHECK_BUCKET(A_, DB_, EX_)                                                                  \
+    template <>                                                                                                 \
+    void launch_check_bucket<A_, DB_, EX_>(const CheckArgs<A_> &a, bool first, bool es, dim3 grid,              \
+                                           hipStream_t s)                                                       \
+    {                                                                                                           \
+        if (first && es)                                                                                        \
+            LDPC_CHECK_LAUNCH_ONE(A_, DB_, EX_, true, true);                                                    \
+        else if (first)                                                                                         \
+            LDPC_CHECK_LAUNCH_ONE(A_, DB_, EX_, true, false);                                                   \
+        else if (es)                                                                                            \
+            LDPC_CHECK_LAUNCH_ONE(A_, DB_, EX_, false, true);                                                   \
+        else                                                                                                    \
+            LDPC_CHECK_LAUNCH_ONE(A_, DB_, EX_, false, false);                                                  \
+    }
+
+}  // namespace ldpc

@@ -57,6 +57,20 @@ inline int64_t frames_padded(int64_t frames) { return (frames + kChunk - 1) / kC
 
 bool code_on_current_device(const ldpc_code_s *c);
 
+// Brackets one kernel launch with profiling events when profiling is on.
+class ProfScope {
+  public:
+    ProfScope(ldpc_kernel_kind kind, hipStream_t stream);
+    ~ProfScope();
+    ProfScope(const ProfScope &) = delete;
+    ProfScope &operator=(const ProfScope &) = delete;
+
+  private:
+    int kind_ = -1;
+    hipStream_t stream_ = nullptr;
+    hipEvent_t start_ = nullptr;
+};
+
 // Streaming (per-iteration) path.
 size_t stream_workspace_bytes(const ldpc_code_s *c, ldpc_dtype dt, int32_t frames, int32_t max_iter);
 ldpc_status stream_decode(const ldpc_code_s *c, ldpc_dtype dt, int32_t frames, int32_t max_iter, uint32_t flags,

@@ -1,0 +1,114 @@
+// Per-kernel device timing with HIP events (measurement aid, off by default).
+#include <atomic>
+#include <mutex>
+#include <vector>
+
+#include "ldpc_internal.h"
+
+namespace {
+
+struct Record {
+    int kind;
+    hipEvent_t start, stop;
+};
+
+std::atomic<int> g_enabled{0};
+std::mutex g_mu;
+std::vector<Record> g_records;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t take_event()
+{
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_pool.empty()) {
+            hipEvent_t e = g_pool.back();
+            g_pool.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+}  // namespace
+
+ldpc::ProfScope::ProfScope(ldpc_kernel_kind kind, hipStream_t stream)
+{
+    if (!g_enabled.load(std::memory_order_relaxed) || capturing(stream))
+        return;
+    start_ = take_event();
+    if (!start_)
+        return;
+    if (hipEventRecord(start_, stream) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_pool.push_back(start_);
+        start_ = nullptr;
+        return;
+    }
+    kind_ = kind;
+    stream_ = stream;
+}
+
+ldpc::ProfScope::~ProfScope()
+{
+    if (!start_)
+        return;
+    hipEvent_t stop = take_event();
+    if (!stop || hipEventRecord(stop, stream_) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_pool.push_back(start_);
+        if (stop)
+            g_pool.push_back(stop);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_records.push_back({kind_, start_, stop});
+}
+
+extern "C" ldpc_status ldpc_profile_enable(int enable)
+{
+    g_enabled.store(enable ? 1 : 0);
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_profile_collect(double *ms, int64_t *counts)
+{
+    std::vector<Record> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        recs.swap(g_records);
+    }
+    double acc[LDPC_KERNEL_KINDS] = {0};
+    int64_t cnt[LDPC_KERNEL_KINDS] = {0};
+    ldpc_status st = LDPC_OK;
+    for (const Record &r : recs) {
+        float t = 0.f;
+        if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess)
+            st = LDPC_EDEVICE;
+        acc[r.kind] += t;
+        cnt[r.kind] += 1;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (const Record &r : recs) {
+            g_pool.push_back(r.start);
+            g_pool.push_back(r.stop);
+        }
+    }
+    for (int k = 0; k < LDPC_KERNEL_KINDS; ++k) {
+        if (ms)
+            ms[k] = acc[k];
+        if (counts)
+            counts[k] = cnt[k];
+    }
+    return st;
+}
