@@ -164,6 +164,22 @@ ldpc_status ldpc_decode_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt
                               size_t workspace_bytes, void *stream);
 
 /*
+ * Workgroup size (a multiple of 64, at most 512) of the fused frame-resident
+ * kernel used by ldpc_decode_batch; default 512.  EINVAL for other values.  Process-wide setting (the
+ * autotuner writes it); affects speed only, never results.
+ */
+ldpc_status ldpc_batch_set_threads(int32_t threads);
+
+/*
+ * Whether frames of `code` in `dtype` can run in the fused frame-resident
+ * kernel on the current device (row degree <= 32, n < 65536 and one frame's
+ * messages within one workgroup's LDS).  LDPC_OK if so, LDPC_EUNSUPPORTED if
+ * ldpc_decode_batch would route the code through the plain path; *lds_bytes
+ * (may be NULL) receives the LDS one frame needs.
+ */
+ldpc_status ldpc_batch_fits_fused(ldpc_code code, ldpc_dtype dtype, size_t *lds_bytes);
+
+/*
  * Per-kernel device timing, a measurement aid (not part of decoding).  While
  * enabled, every kernel the library launches outside a stream capture is
  * bracketed by a pair of HIP events on its own stream.  ldpc_profile_collect

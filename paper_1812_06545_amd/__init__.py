@@ -58,6 +58,8 @@ _sig("ldpc_decode", ctypes.c_int, [_P, ctypes.c_int, _I32, _I32, ctypes.c_uint32
 _sig("ldpc_batch_workspace_bytes", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int,
                                                   ctypes.POINTER(ctypes.c_size_t)])
 _sig("ldpc_decode_batch", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, _P, ctypes.c_size_t, _P])
+_sig("ldpc_batch_set_threads", ctypes.c_int, [_I32])
+_sig("ldpc_batch_fits_fused", ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)])
 _sig("ldpc_profile_enable", ctypes.c_int, [ctypes.c_int])
 _sig("ldpc_profile_collect", ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)])
 
@@ -92,6 +94,11 @@ def _ptr(t):
     if isinstance(t, int):
         return t
     return t.data_ptr()
+
+
+def _handle(code):
+    """A code handle from a Code (kept alive by the caller) or a raw handle."""
+    return code.handle if isinstance(code, Code) else code
 
 
 def _stream_handle(stream):
@@ -134,7 +141,7 @@ def ldpc_code_from_qc(mb, nb, Z, shifts) -> int:
 
 def ldpc_code_info(handle):
     m, n, e = _I32(), _I32(), ctypes.c_int64()
-    _check(_lib.ldpc_code_info(handle, ctypes.byref(m), ctypes.byref(n), ctypes.byref(e)), "ldpc_code_info")
+    _check(_lib.ldpc_code_info(_handle(handle), ctypes.byref(m), ctypes.byref(n), ctypes.byref(e)), "ldpc_code_info")
     return m.value, n.value, e.value
 
 
@@ -144,14 +151,14 @@ def ldpc_code_destroy(handle):
 
 def ldpc_workspace_bytes(handle, dtype, frames, max_iter) -> int:
     b = ctypes.c_size_t()
-    _check(_lib.ldpc_workspace_bytes(handle, _dtype_code(dtype), int(frames), int(max_iter), ctypes.byref(b)),
+    _check(_lib.ldpc_workspace_bytes(_handle(handle), _dtype_code(dtype), int(frames), int(max_iter), ctypes.byref(b)),
            "ldpc_workspace_bytes")
     return b.value
 
 
 def ldpc_decode(handle, dtype, frames, max_iter, flags, llr, bits, iters, posterior, workspace, workspace_bytes,
                 stream=None) -> int:
-    return _lib.ldpc_decode(handle, _dtype_code(dtype), int(frames), int(max_iter), int(flags), _ptr(llr),
+    return _lib.ldpc_decode(_handle(handle), _dtype_code(dtype), int(frames), int(max_iter), int(flags), _ptr(llr),
                             _ptr(bits), _ptr(iters), _ptr(posterior), _ptr(workspace), int(workspace_bytes),
                             _stream_handle(stream))
 
@@ -175,6 +182,19 @@ def ldpc_decode_batch(jobs, dtype, workspace, workspace_bytes, stream=None) -> i
     arr = _jobs_array(jobs)
     return _lib.ldpc_decode_batch(arr, len(jobs), _dtype_code(dtype), _ptr(workspace), int(workspace_bytes),
                                   _stream_handle(stream))
+
+
+def ldpc_batch_set_threads(threads: int) -> int:
+    return _lib.ldpc_batch_set_threads(int(threads))
+
+
+def ldpc_batch_fits_fused(handle, dtype):
+    """(fits, lds_bytes) for the fused frame-resident kernel."""
+    b = ctypes.c_size_t()
+    st = _lib.ldpc_batch_fits_fused(_handle(handle), _dtype_code(dtype), ctypes.byref(b))
+    if st not in (LDPC_OK, LDPC_EUNSUPPORTED):
+        raise LdpcError(st, "ldpc_batch_fits_fused")
+    return st == LDPC_OK, b.value
 
 
 def ldpc_profile_enable(enable: bool) -> int:

@@ -1,9 +1,123 @@
-// Batched decoding of jobs of different codes.
+// Batched decoding of jobs of different codes, lengths and rates.
+//
+// Jobs whose code fits the fused frame-resident kernel (row degree <= 32 and
+// one frame's messages within the LDS of one workgroup) are packed into as
+// few persistent launches as the kernel-argument table allows (<= 24 jobs and
+// <= 16 distinct codes per launch); the others run through the plain
+// per-iteration path on the same stream.  The batch table of each launch is
+// written on the device by a tiny kernel that receives it by value.
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
-#include "ldpc_internal.h"
+#include "fused_kernels.h"
 
+namespace ldpc {
 namespace {
+
+std::mutex g_mu;
+int g_threads = 512;  // workgroup size of the fused kernel (set by ldpc_batch_set_threads)
+
+size_t lds_limit()
+{
+    int dev = 0, bytes = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    return static_cast<size_t>(bytes);
+}
+
+struct FusedFit {
+    bool ok = false;
+    int bucket = 0;
+    size_t lds = 0;
+};
+
+FusedFit fused_fit(const ldpc_code_s *c, ldpc_dtype dt, size_t limit)
+{
+    FusedFit r;
+    const int d = c->max_row_deg;
+    if (dt == LDPC_F32)
+        r.bucket = d <= 8 ? 8 : d <= 16 ? 16 : d <= 24 ? 24 : d <= 32 ? 32 : 0;
+    else
+        r.bucket = d <= 8 ? 8 : d <= 16 ? 16 : d <= 32 ? 32 : 0;
+    if (r.bucket == 0 || c->n >= 65536)
+        return r;
+    const size_t tsize = dt == LDPC_F64 ? sizeof(double) : sizeof(float);
+    r.lds = fused::frame_lds_bytes(c->E, c->n, c->is_qc ? c->qc_words : 0, c->is_qc ? c->nblocks : 0,
+                                   c->is_qc ? c->mb : 0, tsize);
+    r.ok = r.lds <= limit;
+    return r;
+}
+
+struct Group {
+    std::vector<int32_t> jobs;
+    std::vector<const ldpc_code_s *> codes;
+    int bucket = 0;
+    // maxima over the group's codes: the LDS layout is sized by them
+    int64_t emax = 0;
+    int32_t nmax = 0, words = 0, nblocks = 0, mb = 0;
+    size_t lds(size_t tsize) const { return fused::frame_lds_bytes(emax, nmax, words, nblocks, mb, tsize); }
+    void add_code(const ldpc_code_s *c)
+    {
+        codes.push_back(c);
+        emax = std::max<int64_t>(emax, c->E);
+        nmax = std::max(nmax, c->n);
+        words = std::max(words, c->is_qc ? c->qc_words : 0);
+        nblocks = std::max(nblocks, c->is_qc ? c->nblocks : 0);
+        mb = std::max(mb, c->is_qc ? c->mb : 0);
+    }
+};
+
+// Greedy packing of the fusable jobs, in order, into launch groups.
+void plan(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, std::vector<Group> &groups,
+          std::vector<int32_t> &plain)
+{
+    const size_t limit = lds_limit();
+    for (int32_t i = 0; i < njobs; ++i) {
+        if (jobs[i].frames == 0)
+            continue;
+        const FusedFit fit = fused_fit(jobs[i].code, dt, limit);
+        if (!fit.ok) {
+            plain.push_back(i);
+            continue;
+        }
+        const size_t tsize = dt == LDPC_F64 ? sizeof(double) : sizeof(float);
+        bool need_new = groups.empty() || static_cast<int>(groups.back().jobs.size()) == fused::kMaxJobs;
+        if (!need_new) {
+            const Group &g = groups.back();
+            const bool new_code = std::find(g.codes.begin(), g.codes.end(), jobs[i].code) == g.codes.end();
+            if (new_code) {
+                Group trial = g;
+                trial.add_code(jobs[i].code);
+                need_new = static_cast<int>(g.codes.size()) == fused::kMaxCodes || trial.lds(tsize) > limit;
+            }
+        }
+        if (need_new)
+            groups.emplace_back();
+        Group &g = groups.back();
+        g.jobs.push_back(i);
+        if (std::find(g.codes.begin(), g.codes.end(), jobs[i].code) == g.codes.end())
+            g.add_code(jobs[i].code);
+        g.bucket = std::max(g.bucket, fit.bucket);
+    }
+}
+
+constexpr size_t kGroupBytes = (sizeof(fused::Batch) + 255) / 256 * 256 + 256;
+
+// Writes a launch's batch table (passed by value as the kernel argument, so
+// nothing on the host must outlive the call, and the launch sequence can be
+// captured in a graph) and resets the launch's work counter.
+__global__ __launch_bounds__(256) void k_store_batch(fused::Batch b, fused::Batch *__restrict__ dst,
+                                                     unsigned long long *counter)
+{
+    const int32_t *src = reinterpret_cast<const int32_t *>(&b);
+    int32_t *out = reinterpret_cast<int32_t *>(dst);
+    for (int w = threadIdx.x; w < static_cast<int>(sizeof(fused::Batch) / sizeof(int32_t)); w += blockDim.x)
+        out[w] = src[w];
+    if (threadIdx.x == 0)
+        *counter = 0ull;
+}
 
 ldpc_status validate_jobs(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype)
 {
@@ -22,16 +136,93 @@ ldpc_status validate_jobs(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype)
     return LDPC_OK;
 }
 
-size_t batch_bytes(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype)
+size_t batch_bytes(const ldpc_job *jobs, const std::vector<Group> &groups, const std::vector<int32_t> &plain,
+                   ldpc_dtype dtype)
 {
-    size_t b = 0;
-    for (int32_t i = 0; i < njobs; ++i)
-        if (jobs[i].frames > 0)
-            b = std::max(b, ldpc::stream_workspace_bytes(jobs[i].code, dtype, jobs[i].frames, jobs[i].max_iter));
-    return b;
+    size_t stream = 0;
+    for (int32_t i : plain)
+        stream = std::max(stream, stream_workspace_bytes(jobs[i].code, dtype, jobs[i].frames, jobs[i].max_iter));
+    return groups.size() * kGroupBytes + stream;
+}
+
+fused::Code code_entry(const ldpc_code_s *c)
+{
+    fused::Code e{};
+    e.m = c->m;
+    e.n = c->n;
+    e.Z = c->is_qc ? c->Z : 1;
+    e.nblocks = c->is_qc ? c->nblocks : 0;
+    e.mb = c->is_qc ? c->mb : 0;
+    e.nb = c->is_qc ? c->nb : 0;
+    e.qc = c->is_qc ? 1 : 0;
+    e.words = c->is_qc ? c->qc_words : 0;
+    e.tab = c->qc_tab;
+    e.row_ptr = c->row_ptr;
+    e.col_idx = c->col_idx;
+    e.col_ptr = c->col_ptr;
+    e.col_edge = c->col_edge;
+    e.brow_order = c->brow_order;
+    e.row_gmax = c->row_gmax;
+    e.col_gmax = c->col_gmax;
+    return e;
+}
+
+template <class A>
+ldpc_status launch_group(const ldpc_job *jobs, const Group &g, char *ws, int threads, hipStream_t s)
+{
+    fused::Batch b{};
+    b.njobs = static_cast<int32_t>(g.jobs.size());
+    b.ncodes = static_cast<int32_t>(g.codes.size());
+    int32_t nblocks_max = 0;
+    for (size_t k = 0; k < g.codes.size(); ++k) {
+        const ldpc_code_s *c = g.codes[k];
+        b.codes[k] = code_entry(c);
+        b.emax = std::max<int32_t>(b.emax, static_cast<int32_t>(c->E));
+        b.nmax = std::max(b.nmax, c->n);
+        b.words_max = std::max(b.words_max, c->is_qc ? c->qc_words : 0);
+        b.mb_max = std::max(b.mb_max, c->is_qc ? c->mb : 0);
+        nblocks_max = std::max(nblocks_max, c->is_qc ? c->nblocks : 0);
+    }
+    int64_t items = 0;
+    for (size_t k = 0; k < g.jobs.size(); ++k) {
+        const ldpc_job &j = jobs[g.jobs[k]];
+        fused::Job &e = b.jobs[k];
+        e.code = static_cast<int32_t>(std::find(g.codes.begin(), g.codes.end(), j.code) - g.codes.begin());
+        e.frames = j.frames;
+        e.max_iter = j.max_iter;
+        e.flags = j.flags;
+        e.item_begin = items;
+        e.llr = j.llr;
+        e.bits = j.bits;
+        e.iters = j.iters;
+        e.post = j.posterior;
+        items += j.frames;
+    }
+    b.nitems = items;
+    const size_t lds = fused::frame_lds_bytes(b.emax, b.nmax, b.words_max, nblocks_max, b.mb_max,
+                                              sizeof(typename A::T));
+    auto *d_batch = reinterpret_cast<fused::Batch *>(ws);
+    auto *counter = reinterpret_cast<unsigned long long *>(ws + kGroupBytes - 256);
+    {
+        ProfScope ps(LDPC_KERNEL_OTHER, s);
+        hipLaunchKernelGGL(k_store_batch, dim3(1), dim3(256), 0, s, b, d_batch, counter);
+    }
+    ProfScope ps(LDPC_KERNEL_FUSED, s);
+    switch (g.bucket) {
+    case 8: return launch_fused_bucket<A, 8>(b, d_batch, counter, lds, threads, s);
+    case 16: return launch_fused_bucket<A, 16>(b, d_batch, counter, lds, threads, s);
+    case 24:
+        if constexpr (std::is_same<A, ArithF32>::value)
+            return launch_fused_bucket<A, 24>(b, d_batch, counter, lds, threads, s);
+        return launch_fused_bucket<A, 32>(b, d_batch, counter, lds, threads, s);
+    default: return launch_fused_bucket<A, 32>(b, d_batch, counter, lds, threads, s);
+    }
 }
 
 }  // namespace
+}  // namespace ldpc
+
+using namespace ldpc;
 
 extern "C" ldpc_status ldpc_batch_workspace_bytes(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype,
                                                   size_t *bytes)
@@ -41,7 +232,10 @@ extern "C" ldpc_status ldpc_batch_workspace_bytes(const ldpc_job *jobs, int32_t 
     const ldpc_status st = validate_jobs(jobs, njobs, dtype);
     if (st != LDPC_OK)
         return st;
-    *bytes = batch_bytes(jobs, njobs, dtype);
+    std::vector<Group> groups;
+    std::vector<int32_t> plain;
+    plan(jobs, njobs, dtype, groups, plain);
+    *bytes = batch_bytes(jobs, groups, plain, dtype);
     return LDPC_OK;
 }
 
@@ -51,19 +245,55 @@ extern "C" ldpc_status ldpc_decode_batch(const ldpc_job *jobs, int32_t njobs, ld
     const ldpc_status st = validate_jobs(jobs, njobs, dtype);
     if (st != LDPC_OK)
         return st;
-    const size_t need = batch_bytes(jobs, njobs, dtype);
+    std::vector<Group> groups;
+    std::vector<int32_t> plain;
+    plan(jobs, njobs, dtype, groups, plain);
+    const size_t need = batch_bytes(jobs, groups, plain, dtype);
     if (need == 0)
         return LDPC_OK;
     if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return LDPC_EINVAL;
-    for (int32_t i = 0; i < njobs; ++i) {
+    int threads;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        threads = g_threads;
+    }
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    for (const Group &g : groups) {
+        const ldpc_status r = dtype == LDPC_F64 ? launch_group<ArithF64>(jobs, g, ws, threads, s)
+                                                : launch_group<ArithF32>(jobs, g, ws, threads, s);
+        if (r != LDPC_OK)
+            return r;
+        ws += kGroupBytes;
+    }
+    for (int32_t i : plain) {
         const ldpc_job &j = jobs[i];
-        if (j.frames == 0)
-            continue;
-        const ldpc_status s = ldpc::stream_decode(j.code, dtype, j.frames, j.max_iter, j.flags, j.llr, j.bits,
-                                                  j.iters, j.posterior, workspace, static_cast<hipStream_t>(stream));
-        if (s != LDPC_OK)
-            return s;
+        const ldpc_status r = stream_decode(j.code, dtype, j.frames, j.max_iter, j.flags, j.llr, j.bits, j.iters,
+                                            j.posterior, ws, s);
+        if (r != LDPC_OK)
+            return r;
     }
     return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_batch_set_threads(int32_t threads)
+{
+    if (threads < 64 || threads > 512 || threads % 64 != 0)
+        return LDPC_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_threads = threads;
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_batch_fits_fused(ldpc_code code, ldpc_dtype dtype, size_t *lds_bytes)
+{
+    if (!code || (dtype != LDPC_F32 && dtype != LDPC_F64))
+        return LDPC_EINVAL;
+    if (!code_on_current_device(code))
+        return LDPC_EINVAL;
+    const FusedFit f = fused_fit(code, dtype, lds_limit());
+    if (lds_bytes)
+        *lds_bytes = f.lds;
+    return f.ok ? LDPC_OK : LDPC_EUNSUPPORTED;
 }

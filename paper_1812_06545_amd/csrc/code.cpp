@@ -68,10 +68,42 @@ ldpc_status build_host_layout(int32_t m, int32_t n, const int32_t *row_ptr, cons
     return LDPC_OK;
 }
 
-ldpc_status upload(const HostLayout &h, const std::vector<int32_t> *qc_tab, ldpc_code_s *c)
+// Slot tables of the fused kernel (see ldpc_code_s).  brow_order is empty
+// for codes without a circulant-block structure.
+void slot_tables(const HostLayout &h, const std::vector<int32_t> &row_blk_start, int32_t Z,
+                 std::vector<int32_t> &brow_order, std::vector<int32_t> &row_gmax, std::vector<int32_t> &col_gmax)
 {
+    std::vector<int32_t> row_deg(h.m);
+    if (!row_blk_start.empty()) {
+        const int32_t mb = static_cast<int32_t>(row_blk_start.size()) - 1;
+        brow_order.resize(mb);
+        for (int32_t i = 0; i < mb; ++i)
+            brow_order[i] = i;
+        std::stable_sort(brow_order.begin(), brow_order.end(), [&](int32_t a, int32_t b) {
+            return row_blk_start[a + 1] - row_blk_start[a] > row_blk_start[b + 1] - row_blk_start[b];
+        });
+        for (int32_t si = 0; si < mb; ++si)
+            for (int32_t r = 0; r < Z; ++r)
+                row_deg[si * Z + r] = row_blk_start[brow_order[si] + 1] - row_blk_start[brow_order[si]];
+    } else {
+        for (int32_t i = 0; i < h.m; ++i)
+            row_deg[i] = h.row_ptr[i + 1] - h.row_ptr[i];
+    }
+    row_gmax.assign((h.m + 63) / 64, 0);
+    for (int32_t i = 0; i < h.m; ++i)
+        row_gmax[i / 64] = std::max(row_gmax[i / 64], row_deg[i]);
+    col_gmax.assign((h.n + 63) / 64, 0);
+    for (int32_t j = 0; j < h.n; ++j)
+        col_gmax[j / 64] = std::max(col_gmax[j / 64], h.col_ptr[j + 1] - h.col_ptr[j]);
+}
+
+ldpc_status upload(const HostLayout &h, const std::vector<int32_t> *qc_tab, const std::vector<int32_t> &row_blk_start,
+                   int32_t Z, ldpc_code_s *c)
+{
+    std::vector<int32_t> brow_order, row_gmax, col_gmax;
+    slot_tables(h, row_blk_start, Z, brow_order, row_gmax, col_gmax);
     const size_t words = h.row_ptr.size() + h.col_idx.size() + h.col_ptr.size() + h.col_edge.size() +
-                         (qc_tab ? qc_tab->size() : 0);
+                         (qc_tab ? qc_tab->size() : 0) + brow_order.size() + row_gmax.size() + col_gmax.size();
     std::vector<int32_t> blob;
     blob.reserve(words);
     auto put = [&](const std::vector<int32_t> &v) {
@@ -81,6 +113,7 @@ ldpc_status upload(const HostLayout &h, const std::vector<int32_t> *qc_tab, ldpc
     };
     const size_t o_rp = put(h.row_ptr), o_ci = put(h.col_idx), o_cp = put(h.col_ptr), o_ce = put(h.col_edge);
     const size_t o_qc = qc_tab ? put(*qc_tab) : 0;
+    const size_t o_bo = put(brow_order), o_rg = put(row_gmax), o_cg = put(col_gmax);
     void *d = nullptr;
     if (hipMalloc(&d, std::max<size_t>(blob.size(), 1) * sizeof(int32_t)) != hipSuccess)
         return LDPC_ENOMEM;
@@ -95,6 +128,9 @@ ldpc_status upload(const HostLayout &h, const std::vector<int32_t> *qc_tab, ldpc
     c->col_ptr = base + o_cp;
     c->col_edge = base + o_ce;
     c->qc_tab = qc_tab ? base + o_qc : nullptr;
+    c->brow_order = brow_order.empty() ? nullptr : base + o_bo;
+    c->row_gmax = base + o_rg;
+    c->col_gmax = base + o_cg;
     c->m = h.m;
     c->n = h.n;
     c->E = static_cast<int64_t>(h.col_idx.size());
@@ -140,7 +176,7 @@ extern "C" ldpc_status ldpc_code_from_csr(int32_t m, int32_t n, const int32_t *r
         delete c;
         return LDPC_EDEVICE;
     }
-    st = upload(h, nullptr, c);
+    st = upload(h, nullptr, {}, 0, c);
     if (st != LDPC_OK) {
         delete c;
         return st;
@@ -209,7 +245,7 @@ extern "C" ldpc_status ldpc_code_from_qc(int32_t mb, int32_t nb, int32_t Z, cons
         delete c;
         return LDPC_EDEVICE;
     }
-    st = upload(h, &tab, c);
+    st = upload(h, &tab, row_blk_start, Z, c);
     if (st != LDPC_OK) {
         delete c;
         return st;

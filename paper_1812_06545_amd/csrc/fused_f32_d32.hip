@@ -1,0 +1,8 @@
+// Fused frame-resident kernel, FP32, codes of row degree <= 32.
+#include <algorithm>
+
+#include "fused_kernels.h"
+
+namespace ldpc {
+LDPC_DEFINE_FUSED_BUCKET(ArithF32, 32)
+}  // namespace ldpc

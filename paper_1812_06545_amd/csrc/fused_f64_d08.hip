@@ -1,0 +1,8 @@
+// Fused frame-resident kernel, FP64, codes of row degree <= 8.
+#include <algorithm>
+
+#include "fused_kernels.h"
+
+namespace ldpc {
+LDPC_DEFINE_FUSED_BUCKET(ArithF64, 8)
+}  // namespace ldpc

@@ -1,0 +1,359 @@
+// Fused frame-resident decoder: one workgroup decodes one frame through all
+// of its iterations with the frame's messages held in LDS.
+//
+// Schedule (arxiv 1812.06545, Section II; Algorithm 1): the same flooding
+// two-phase iteration as the plain path, but the global barrier between the
+// check-node and variable-node phases becomes a workgroup barrier, because
+// the frames are independent (the frame-level parallelism of Section III-A)
+// and one workgroup owns a whole frame.  HBM traffic per frame is the channel
+// LLRs (read once per iteration, from L2 after the first) and the outputs.
+//
+// Persistent launch: workgroups pull (job, frame) items from a device counter
+// until the queue is empty, so one launch decodes a batch of jobs of
+// different codes, lengths and rates, and a frame that stops early frees its
+// workgroup for the next item.
+//
+// Thread mapping: check rows are visited in slot order (for QC codes
+// block-rows sorted by decreasing degree).  A wavefront's 64 rows may differ
+// in degree; the wave runs the straight-line body of its largest degree and
+// pads shorter rows with dummy edges carrying q = +inf, whose phi is exactly
+// 0 and whose sign is +, so every real message is computed with exactly the
+// operations and rounding of the plain path (bit-identical results).
+//
+// LDS per workgroup: r for every edge, the posterior L for every variable,
+// and the code's circulant-block tables (QC codes).
+#pragma once
+
+#include <type_traits>
+
+#include "ldpc_internal.h"
+#include "spa_math.h"
+
+namespace ldpc {
+namespace fused {
+
+constexpr int kMaxCodes = 16;
+constexpr int kMaxJobs = 24;
+
+// Kernel-argument copy of a code's device layout.
+struct Code {
+    int32_t m, n, Z, nblocks;
+    int32_t mb, nb, qc, words;  // words: QC table words (0 for CSR codes)
+    const int32_t *tab, *row_ptr, *col_idx, *col_ptr, *col_edge, *brow_order, *row_gmax, *col_gmax;
+};
+
+struct Job {
+    int32_t code, frames, max_iter;
+    uint32_t flags;
+    int64_t item_begin;
+    const void *llr;
+    uint8_t *bits;
+    int32_t *iters;
+    void *post;
+};
+
+struct Batch {
+    int32_t njobs, ncodes;
+    int64_t nitems;
+    int32_t emax, nmax, words_max, mb_max;
+    Code codes[kMaxCodes];
+    Job jobs[kMaxJobs];
+};
+
+// LDS bytes a workgroup needs for one frame of this code.
+__host__ __device__ inline size_t frame_lds_bytes(int64_t E, int32_t n, int32_t words, int32_t nblocks, int32_t mb,
+                                                  size_t tsize)
+{
+    const size_t msg = (static_cast<size_t>(E) + static_cast<size_t>(n)) * tsize;
+    return (msg + 15) / 16 * 16 + static_cast<size_t>(words + nblocks + mb) * sizeof(int32_t);
+}
+
+// Index view of one check row in slot order.
+//   QC:  ridx(k) = (rbs + k) * Z + r   (block order),  col(k) from the packed block table
+//   CSR: ridx(k) = e0 + k,             col(k) = col_idx[e0 + k]
+struct RowQC {
+    int32_t first_block, r, Z;
+    const int32_t *pack;  // LDS: (j * Z) | (shift << 16) per block
+    __device__ int32_t ridx(int k) const { return (first_block + k) * Z + r; }
+    __device__ int32_t col(int k) const
+    {
+        const int32_t w = pack[first_block + k];
+        int32_t c = r + (w >> 16);
+        c = c >= Z ? c - Z : c;
+        return (w & 0xffff) + c;
+    }
+};
+
+struct RowCSR {
+    int32_t e0;
+    const int32_t *col_idx;
+    __device__ int32_t ridx(int k) const { return e0 + k; }
+    __device__ int32_t col(int k) const { return col_idx[e0 + k]; }
+};
+
+// One check row with run-time degree d <= D, as the straight-line body of
+// degree D.  Edges k >= d are dummies: they read slot 0 (valid for any code
+// with an edge) and enter as q = +inf, r = 0, which adds exact zeros to the
+// exclusive sums and + to the sign; nothing is written for them.
+// The forward pass parks a_k = sign(q_k) phi(|q_k|) in the edge's own r slot
+// (free once q_k is formed, and owned by this row alone) instead of a
+// register array; the backward pass reads it back and overwrites it with the
+// new message.  Only the prefix sums stay in registers.
+template <class A, int D, class Row>
+__device__ __forceinline__ void fused_row(const Row &row, int d, typename A::T *__restrict__ sR,
+                                          const typename A::T *__restrict__ sL, bool first, uint32_t &parity)
+{
+    using T = typename A::T;
+    T pre[D];
+    T acc = T(0);
+    uint32_t sign_total = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const bool real = k < d;
+        const int32_t ri = real ? row.ridx(k) : 0;
+        const T l = sL[real ? row.col(k) : 0];
+        const T rr = first ? T(0) : sR[ri];
+        const T lv = real ? l : T(__builtin_huge_val());
+        parity ^= static_cast<uint32_t>(real && lv < T(0));
+        const T q = first ? lv : lv - (real ? rr : T(0));
+        T a_k;
+        check_row_forward<A>(q, a_k, pre[k], acc, sign_total);
+        if (real)
+            sR[ri] = a_k;
+    }
+    T suf = T(0);
+#pragma unroll
+    for (int k = D - 1; k >= 0; --k) {
+        const bool real = k < d;
+        const int32_t ri = real ? row.ridx(k) : 0;
+        const T a_k = real ? sR[ri] : T(0);
+        const T ex = pre[k] + suf;
+        suf += fabs(a_k);
+        T mag = A::phi(ex);
+        mag = mag < A::kRmax ? mag : A::kRmax;
+        if (real)
+            sR[ri] = A::with_sign(mag, sign_total ^ A::sign_bit(a_k));
+    }
+}
+
+// Body selection: exact-degree bodies (chosen by the wave's largest degree)
+// for FP32 circulant codes, the hot case; one padded body of degree DB for
+// FP64 and for CSR codes (fewer instantiations, same results).
+template <class A, int D, int DB, class Row>
+__device__ __forceinline__ void fused_row_dispatch(int dwave, const Row &row, int d, typename A::T *__restrict__ sR,
+                                                   const typename A::T *__restrict__ sL, bool first, uint32_t &parity)
+{
+    constexpr bool exact = std::is_same<A, ArithF32>::value && std::is_same<Row, RowQC>::value;
+    if constexpr (!exact) {
+        fused_row<A, DB>(row, d, sR, sL, first, parity);
+    } else if constexpr (D < DB) {
+        if (dwave == D)
+            fused_row<A, D>(row, d, sR, sL, first, parity);
+        else
+            fused_row_dispatch<A, D + 1, DB>(dwave, row, d, sR, sL, first, parity);
+    } else {
+        fused_row<A, DB>(row, d, sR, sL, first, parity);
+    }
+}
+
+// Column sum L = Lch + sum of r in ascending row order, run-time degree dv <= D
+// (dummy edges read slot 0 and are not added).
+template <class A, int D, class Edge>
+__device__ __forceinline__ typename A::T fused_col(const Edge &edge, int dv, typename A::T acc,
+                                                   const typename A::T *__restrict__ sR)
+{
+    using T = typename A::T;
+    T rv[D > 0 ? D : 1];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        rv[k] = sR[k < dv ? edge(k) : 0];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        acc = k < dv ? acc + rv[k] : acc;
+    return acc;
+}
+
+template <class A, int D, class Edge>
+__device__ __forceinline__ typename A::T fused_col_dispatch(int dwave, const Edge &edge, int dv, typename A::T acc,
+                                                            const typename A::T *__restrict__ sR)
+{
+    if constexpr (!std::is_same<A, ArithF32>::value) {
+        for (int k = 0; k < dv; ++k)
+            acc += sR[edge(k)];
+        return acc;
+    } else if constexpr (D <= 16) {
+        if (dwave == D)
+            return fused_col<A, D>(edge, dv, acc, sR);
+        return fused_col_dispatch<A, D + 1>(dwave, edge, dv, acc, sR);
+    } else {
+        for (int k = 0; k < dv; ++k)
+            acc += sR[edge(k)];
+        return acc;
+    }
+}
+
+template <class A, int DB>
+__device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int64_t f, typename A::T *__restrict__ sR,
+                             typename A::T *__restrict__ sL, const int32_t *__restrict__ sTab)
+{
+    using T = typename A::T;
+    const int tid = static_cast<int>(threadIdx.x), NT = static_cast<int>(blockDim.x);
+    const int32_t m = c.m, n = c.n, Z = c.Z;
+    const T *llr = static_cast<const T *>(job.llr) + f * n;
+    // QC tables in LDS: [row_blk_start mb+1][blk_col][blk_shift][col_blk_start nb+1][col_blk][pack][brow_order]
+    const int32_t *rbs = sTab;
+    const int32_t *bshift = sTab + (c.mb + 1) + c.nblocks;
+    const int32_t *cbs = bshift + c.nblocks;
+    const int32_t *cblk = cbs + (c.nb + 1);
+    const int32_t *pack = sTab + c.words;
+    const int32_t *border = pack + c.nblocks;
+
+    for (int j = tid; j < n; j += NT)
+        sL[j] = llr[j] * T(A::kIn);
+    __syncthreads();
+
+    const bool es = (job.flags & LDPC_EARLY_STOP) != 0;
+    int32_t it = job.max_iter;
+    for (int32_t t = 1; t <= job.max_iter; ++t) {
+        const bool first = (t == 1);
+        uint32_t parity = 0;
+        for (int s = tid; s < m; s += NT) {
+            const int dwave = c.row_gmax[__builtin_amdgcn_readfirstlane(s) >> 6];
+            if (dwave == 0)
+                continue;
+            if (c.qc) {
+                const int32_t si = s / Z;
+                const int32_t r = s - si * Z;
+                const int32_t i = border[si];
+                const RowQC row{rbs[i], r, Z, pack};
+                fused_row_dispatch<A, 1, DB>(dwave, row, rbs[i + 1] - rbs[i], sR, sL, first, parity);
+            } else {
+                const int32_t e0 = c.row_ptr[s];
+                const RowCSR row{e0, c.col_idx};
+                fused_row_dispatch<A, 1, DB>(dwave, row, c.row_ptr[s + 1] - e0, sR, sL, first, parity);
+            }
+        }
+        const int unsat = __syncthreads_or(static_cast<int>(parity));
+        if (es && !unsat) {  // x^(t-1) is a codeword: stop at t-1, keep L^(t-1)
+            it = t - 1;
+            break;
+        }
+        for (int j = tid; j < n; j += NT) {
+            const int dwave = c.col_gmax[__builtin_amdgcn_readfirstlane(j) >> 6];
+            const T acc = llr[j] * T(A::kIn);
+            T v;
+            if (c.qc) {
+                const int32_t bj = j / Z;
+                const int32_t cc = j - bj * Z;
+                const int32_t k0 = cbs[bj];
+                auto edge = [&](int k) {
+                    const int32_t b = cblk[k0 + k];
+                    int32_t r = cc - bshift[b];
+                    r = r < 0 ? r + Z : r;
+                    return b * Z + r;
+                };
+                v = fused_col_dispatch<A, 0>(dwave, edge, cbs[bj + 1] - k0, acc, sR);
+            } else {
+                const int32_t k0 = c.col_ptr[j];
+                auto edge = [&](int k) { return c.col_edge[k0 + k]; };
+                v = fused_col_dispatch<A, 0>(dwave, edge, c.col_ptr[j + 1] - k0, acc, sR);
+            }
+            sL[j] = v;
+        }
+        __syncthreads();
+    }
+    uint8_t *bits = job.bits + f * n;
+    T *post = job.post ? static_cast<T *>(job.post) + f * n : nullptr;
+    for (int j = tid; j < n; j += NT) {
+        const T v = sL[j];
+        bits[j] = static_cast<uint8_t>(v < T(0));
+        if (post)
+            post[j] = it == 0 ? llr[j] : v * T(A::kOut);
+    }
+    if (tid == 0)
+        job.iters[f] = it;
+}
+
+// Persistent batch kernel: workgroups take (job, frame) items from *counter.
+// 512-thread workgroups, two per CU for n = 1944 (LDS bound): FP32 bodies are
+// held to 128 VGPRs so both fit (4 waves per SIMD); FP64 bodies get 256.
+template <class A>
+constexpr int kFusedWavesPerEU = std::is_same<A, ArithF32>::value ? 4 : 2;
+
+template <class A, int DB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWavesPerEU<A>))) void k_fused(const Batch *__restrict__ batch, unsigned long long *counter)
+{
+    using T = typename A::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ long long s_item;
+    const Batch &b = *batch;
+    T *sR = reinterpret_cast<T *>(smem);
+    T *sL = sR + b.emax;
+    int32_t *sTab = reinterpret_cast<int32_t *>(smem + (static_cast<size_t>(b.emax + b.nmax) * sizeof(T) + 15) / 16 * 16);
+    int cur_code = -1;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = static_cast<long long>(atomicAdd(counter, 1ull));
+        __syncthreads();
+        const int64_t item = s_item;
+        __syncthreads();
+        if (item >= b.nitems)
+            break;
+        int j = 0;
+        while (j + 1 < b.njobs && b.jobs[j + 1].item_begin <= item)
+            ++j;
+        const Job &job = b.jobs[j];
+        const Code &c = b.codes[job.code];
+        if (job.code != cur_code) {
+            cur_code = job.code;
+            for (int w = threadIdx.x; w < c.words; w += blockDim.x)
+                sTab[w] = c.tab[w];
+            if (c.qc) {
+                const int32_t *bcol = c.tab + (c.mb + 1);
+                const int32_t *bsh = bcol + c.nblocks;
+                for (int w = threadIdx.x; w < c.nblocks; w += blockDim.x)
+                    sTab[c.words + w] = (bcol[w] * c.Z) | (bsh[w] << 16);
+                for (int w = threadIdx.x; w < c.mb; w += blockDim.x)
+                    sTab[c.words + c.nblocks + w] = c.brow_order[w];
+            }
+            __syncthreads();
+        }
+        decode_frame<A, DB>(c, job, item - job.item_begin, sR, sL, sTab);
+        __syncthreads();
+    }
+}
+
+}  // namespace fused
+
+// Launcher of the fused kernel for codes of row degree <= DB (one
+// translation unit per dtype and bucket).
+// The caller has already written the batch table to d_batch and reset *counter.
+template <class A, int DB>
+ldpc_status launch_fused_bucket(const fused::Batch &batch, fused::Batch *d_batch, unsigned long long *counter,
+                                size_t lds_bytes, int threads, hipStream_t s);
+
+#define LDPC_DEFINE_FUSED_BUCKET(A_, DB_)                                                                        \
+    template <>                                                                                                  \
+    ldpc_status launch_fused_bucket<A_, DB_>(const fused::Batch &batch, fused::Batch *d_batch,                  \
+                                             unsigned long long *counter, size_t lds_bytes, int threads,        \
+                                             hipStream_t s)                                                      \
+    {                                                                                                            \
+        auto kern = fused::k_fused<A_, DB_>;                                                                     \
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                                            \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes)) !=      \
+            hipSuccess)                                                                                          \
+            return LDPC_EUNSUPPORTED;                                                                            \
+        int per_cu = 0, dev = 0, cus = 0;                                                                        \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds_bytes) != hipSuccess ||     \
+            per_cu < 1)                                                                                          \
+            return LDPC_EUNSUPPORTED;                                                                            \
+        if (hipGetDevice(&dev) != hipSuccess ||                                                                  \
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)              \
+            return LDPC_EDEVICE;                                                                                 \
+        const int64_t grid = std::min<int64_t>(batch.nitems, static_cast<int64_t>(per_cu) * cus);               \
+        hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(threads), lds_bytes, s, d_batch,        \
+                           counter);                                                                             \
+        return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EDEVICE;                                         \
+    }
+
+}  // namespace ldpc

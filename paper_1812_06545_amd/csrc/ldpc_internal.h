@@ -46,6 +46,15 @@ struct ldpc_code_s {
     const int32_t *qc_tab = nullptr;
     int32_t qc_words = 0;
     std::vector<int32_t> h_qc_tab;
+    // Thread-slot tables of the fused kernel (every code).  Check rows are
+    // visited in "slot" order: for QC codes block-rows sorted by decreasing
+    // degree (rows of one block-row consecutive), otherwise natural order;
+    // brow_order[i] is the block-row in sorted position i (QC only).
+    // row_gmax[g] / col_gmax[g]: largest row / column degree among slots
+    // 64g .. 64g+63 (one wavefront's rows or columns).
+    const int32_t *brow_order = nullptr;
+    const int32_t *row_gmax = nullptr;
+    const int32_t *col_gmax = nullptr;
 };
 
 namespace ldpc {

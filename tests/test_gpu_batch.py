@@ -1,0 +1,181 @@
+"""GPU tests of ldpc_decode_batch: the fused frame-resident persistent kernel
+(and the plain-path route for codes that do not fit it).
+
+Bars: every job's outputs equal the oracle's within the parity rule, and
+equal the plain per-iteration path bit for bit (both paths evaluate each
+message with the same operations in the same order); a job decoded inside a
+mixed batch equals the same job decoded alone, bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import compare
+from workloads import channel, codes, configs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1812_06545_amd as lib
+    return lib
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _batch(L, items, es=True, T=10):
+    """items: list of (code handle, llr ndarray) -> list of Job (decoded)."""
+    import torch
+    jobs = [L.Job(h, torch.from_numpy(np.ascontiguousarray(llr)).cuda(), T, early_stop=es) for h, llr in items]
+    L.decode_batch(jobs)
+    torch.cuda.synchronize()
+    return jobs
+
+
+def _plain(L, h, llr, T, es):
+    import torch
+    b, i, p = L.decode(h, torch.from_numpy(np.ascontiguousarray(llr)).cuda(), T, early_stop=es)
+    torch.cuda.synchronize()
+    return b.cpu().numpy(), i.cpu().numpy(), p.cpu().numpy()
+
+
+def _np(job):
+    return job.bits.cpu().numpy(), job.iters.cpu().numpy(), job.posterior.cpu().numpy()
+
+
+def test_fused_fit_reporting(L):
+    import torch
+    qc = L.Code.from_workload(configs.qc1944(2.0, frames=1).code)
+    ok, lds = L.ldpc_batch_fits_fused(qc, torch.float32)
+    _log(f"[gpu] qc1944 fused fit={ok} lds={lds}")
+    assert ok and 60000 < lds < 100000
+    props = torch.cuda.get_device_properties(0)
+    _log(f"[gpu] device {props.name} CUs={props.multi_processor_count}")
+    stair = L.Code.from_workload(configs.stair64800(frames=1).code)
+    assert L.ldpc_batch_fits_fused(stair, torch.float32)[0] is False
+
+
+@pytest.mark.parametrize("snr", [1.0, 2.5])
+def test_fused_qc1944_vs_oracle_and_plain(L, snr):
+    b = configs.qc1944(snr, frames=130)
+    h = L.Code.from_workload(b.code)
+    _log(f"[gpu] fused qc1944 {snr} dB x130")
+    job = _batch(L, [(h, b.llr)], es=False)[0]
+    bits, iters, post = _np(job)
+    ref = oracle.decode(b.code, b.llr, 10, False, nthreads=8)
+    _log(f"[gpu]   {compare(ref, bits, iters, post, np.float32, 'fused qc1944')}")
+    pb, pi, pp = _plain(L, h, b.llr, 10, False)
+    assert np.array_equal(bits, pb) and np.array_equal(iters, pi) and np.array_equal(post, pp)
+
+
+def test_fused_early_stop_high_snr(L):
+    b = configs.qc1944(2.0, frames=100)
+    llr = channel.bpsk_awgn_llr(b.codewords, 4.0, 0.5, 905, dtype=np.float32)
+    h = L.Code.from_workload(b.code)
+    _log("[gpu] fused qc1944 4 dB early stop")
+    job = _batch(L, [(h, llr)], es=True)[0]
+    bits, iters, post = _np(job)
+    ref = oracle.decode(b.code, llr, 10, True, nthreads=8)
+    compare(ref, bits, iters, post, np.float32, "fused es")
+    assert iters.min() < 10
+    pb, pi, pp = _plain(L, h, llr, 10, True)
+    assert np.array_equal(bits, pb) and np.array_equal(iters, pi) and np.array_equal(post, pp)
+
+
+def test_fused_mix_isolation_and_oracle(L):
+    """The 12-code QC mix in one batch: each job equals the oracle (sampled
+    frames), the plain path and the same job decoded alone, bit for bit."""
+    mix = configs.qc_mix(total=1200)
+    handles = [L.Code.from_workload(m.code) for m in mix]
+    _log(f"[gpu] fused mix: {[m.llr.shape[0] for m in mix]}")
+    jobs = _batch(L, list(zip(handles, [m.llr for m in mix])), es=True)
+    for k, (m, h, j) in enumerate(zip(mix, handles, jobs)):
+        bits, iters, post = _np(j)
+        alone = _np(_batch(L, [(h, m.llr)], es=True)[0])
+        for x, y in zip((bits, iters, post), alone):
+            assert np.array_equal(x, y), f"job {k} differs alone vs in the mix"
+        pb, pi, pp = _plain(L, h, m.llr, 10, True)
+        assert np.array_equal(bits, pb) and np.array_equal(iters, pi) and np.array_equal(post, pp)
+        idx = np.unique(np.r_[0, m.llr.shape[0] - 1, np.arange(0, m.llr.shape[0], 17)])
+        ref = oracle.decode(m.code, m.llr[idx], 10, True, nthreads=8)
+        compare(ref, bits[idx], iters[idx], post[idx], np.float32, f"mix job {k}")
+
+
+def test_fused_f64_gallager(L):
+    b = configs.gallager504(frames=300)
+    h = L.Code.from_workload(b.code)
+    _log("[gpu] fused gallager504 f64")
+    job = _batch(L, [(h, b.llr)], es=True, T=20)[0]
+    bits, iters, post = _np(job)
+    ref = oracle.decode(b.code, b.llr, 20, True, nthreads=8)
+    compare(ref, bits, iters, post, np.float64, "fused f64")
+    pb, pi, pp = _plain(L, h, b.llr, 20, True)
+    assert np.array_equal(bits, pb) and np.array_equal(iters, pi) and np.array_equal(post, pp)
+
+
+def test_batch_routes_large_code_through_plain(L):
+    """A batch holding a code too large for LDS next to fused jobs."""
+    stair = configs.stair64800(frames=8)
+    qc = configs.qc1944(1.5, frames=70)
+    hs, hq = L.Code.from_workload(stair.code), L.Code.from_workload(qc.code)
+    _log("[gpu] batch with stair64800 + qc1944")
+    jobs = _batch(L, [(hq, qc.llr), (hs, stair.llr)], es=True, T=50)
+    for (bt, h), j in zip(((qc, hq), (stair, hs)), jobs):
+        bits, iters, post = _np(j)
+        pb, pi, pp = _plain(L, h, bt.llr, 50, True)
+        assert np.array_equal(bits, pb) and np.array_equal(iters, pi) and np.array_equal(post, pp)
+    ref = oracle.decode(stair.code, stair.llr[:2], 50, True)
+    bits, iters, post = _np(jobs[1])
+    compare(ref, bits[:2], iters[:2], post[:2], np.float32, "stair in batch")
+
+
+def test_fused_small_and_degenerate_codes(L):
+    rng = np.random.default_rng(3)
+    rows = [[], [0], [1, 2, 3], list(range(4, 28)), [2, 5, 9]]
+    degenerate = codes.Code.from_row_lists(len(rows), 30, rows, "degenerate")
+    cases = [codes.single_parity_check(5), codes.hamming74(), codes.random_tree_code(12, 3), degenerate]
+    for code in cases:
+        h = L.Code.from_csr(code.m, code.n, code.row_ptr, code.col_idx)
+        llr = rng.normal(0.5, 2.0, size=(67, code.n)).astype(np.float32)
+        for es in (False, True):
+            for T in (0, 1, 7):
+                _log(f"[gpu] fused {code.name} T={T} es={es}")
+                bits, iters, post = _np(_batch(L, [(h, llr)], es=es, T=T)[0])
+                ref = oracle.decode(code, llr, T, es)
+                compare(ref, bits, iters, post, np.float32, f"fused {code.name}")
+                pb, pi, pp = _plain(L, h, llr, T, es)
+                assert np.array_equal(bits, pb) and np.array_equal(iters, pi) and np.array_equal(post, pp)
+
+
+def test_fused_noiseless_zero_iterations(L):
+    b = configs.qc1944(2.0, frames=40)
+    h = L.Code.from_workload(b.code)
+    llr = channel.noiseless_llr(b.codewords, 3.0, np.float32)
+    bits, iters, post = _np(_batch(L, [(h, llr)], es=True, T=10)[0])
+    assert (iters == 0).all() and (bits == b.codewords).all() and np.array_equal(post, llr)
+    bits, iters, post = _np(_batch(L, [(h, b.llr)], es=False, T=0)[0])
+    assert (iters == 0).all() and (bits == (b.llr < 0)).all() and np.array_equal(post, b.llr)
+
+
+@pytest.mark.parametrize("threads", [64, 192, 256, 512])
+def test_fused_threads_do_not_change_results(L, threads):
+    b = configs.qc_mix(total=200)
+    items = [(L.Code.from_workload(m.code), m.llr) for m in b[:4]]
+    assert L.ldpc_batch_set_threads(threads) == 0
+    try:
+        got = [_np(j) for j in _batch(L, items)]
+    finally:
+        L.ldpc_batch_set_threads(512)
+    want = [_np(j) for j in _batch(L, items)]
+    for g, w in zip(got, want):
+        for x, y in zip(g, w):
+            assert np.array_equal(x, y)
