@@ -30,6 +30,9 @@ def parse():
                     help="plain: per-iteration kernels (ldpc_decode); batch: ldpc_decode_batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="length of the open-loop serving run (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=20000.0, help="offered requests per second")
     return ap.parse_args()
 
 
@@ -121,6 +124,8 @@ def main():
                 "launch_ms": avg_ms, "launches": kcount, "bytes_per_launch": bytes_per_launch}
     kernels = {k: {"ms_total": v[0], "launches": v[1]} for k, v in prof.items() if v[1]}
 
+    serving = serve_run(args.serve_seconds, args.serve_rate) if args.serve_seconds > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(batches[2], T, args.cpu_seconds)
@@ -144,9 +149,59 @@ def main():
         "info_mbps": k_info * F * args.steps / elapsed / 1e6,
         "roofline": roofline,
         "kernels": kernels,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def serve_run(seconds, rate):
+    """Open-loop serving run: Poisson arrivals of decode requests (1-64 frames
+    of one of the 12 QC codes, Eb/N0 uniform in [1, 3] dB per frame, 10
+    iterations with early stop) submitted at their scheduled times; latency is
+    completion minus scheduled arrival, so a backlog is not hidden."""
+    import numpy as np
+
+    import paper_1812_06545_amd as L
+    from workloads import configs
+
+    pool = configs.ServePool(per_code=512)
+    handles = [L.Code.from_workload(c) for c in pool.codes]
+    llr = [pool.llr_pool(i) for i in range(12)]
+    outs = [(np.zeros((64, c.n), np.uint8), np.zeros(64, np.int32)) for c in pool.codes]
+    sched = configs.serve_schedule(seconds, rate)
+    srv = L.ldpc_server_create(handles, 512 << 20, max_inflight=3, max_group_frames=2048)
+    try:
+        # warm-up: one request per code
+        for cid in range(12):
+            st, t = L.ldpc_server_submit(srv, cid, 8, 10, 1, llr[cid][:8], outs[cid][0][:8], outs[cid][1][:8])
+            L.ldpc_server_wait(srv, t)
+        L.ldpc_server_stats_get(srv, reset=True)
+        t0 = time.monotonic_ns() + 2_000_000
+        rejected = 0
+        for k, rq in enumerate(sched):
+            at = t0 + int(rq.t_arrival * 1e9)
+            while time.monotonic_ns() < at:
+                pass
+            start = (k * 37) % (512 - rq.frames + 1)
+            src = llr[rq.code_id][start:start + rq.frames]
+            st, _ = L.ldpc_server_submit(srv, rq.code_id, rq.frames, 10, 1, src, outs[rq.code_id][0][:rq.frames],
+                                         outs[rq.code_id][1][:rq.frames], None, at)
+            rejected += st != 0
+        while True:
+            s = L.ldpc_server_stats_get(srv)
+            if s["completed"] + s["failed"] >= s["submitted"]:
+                break
+            time.sleep(0.001)
+        wall = (time.monotonic_ns() - t0) / 1e9
+    finally:
+        L.ldpc_server_destroy(srv)
+    return {"workload": "serve: Poisson arrivals, 1-64 frames of one of 12 QC codes (Z 27/54/81 x rate 1/2..5/6), "
+                        "Eb/N0 U[1,3] dB, 10 iterations with early stop",
+            "offered_req_per_s": rate, "duration_s": seconds, "requests": s["completed"], "rejected": rejected,
+            "failed": s["failed"], "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "p999_ms": s["p999_ms"],
+            "max_ms": s["max_ms"], "mbps": s["bits_completed"] / wall / 1e6, "launches": s["launches"],
+            "mean_group_frames": s["mean_group_frames"], "max_queue_depth": s["max_queue_depth"]}
 
 
 def cpu_baseline(batch, T, seconds):

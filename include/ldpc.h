@@ -164,6 +164,74 @@ ldpc_status ldpc_decode_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt
                               size_t workspace_bytes, void *stream);
 
 /*
+ * Serving: continuous batching of decode requests (one request = 1 or more
+ * frames of one code).  A scheduler thread owned by the server admits queued
+ * requests, first come first served, whenever device memory (a fixed arena
+ * sized by mem_budget_bytes) and one of max_inflight launch slots are free;
+ * each admitted group is packed contiguously, copied to the device in one
+ * transfer, decoded by one ldpc_decode_batch call on the slot's own stream
+ * (so a group admitted while others run overlaps with them on the device),
+ * and copied back; the scheduler then fills the requester's host buffers and
+ * marks the request done.  Every frame's result equals decoding it alone.
+ * Codes must fit the fused kernel (ldpc_batch_fits_fused), all FP32.
+ */
+typedef struct ldpc_server_s *ldpc_server;
+
+typedef struct {
+    int32_t ncodes;            /* number of codes served (<= 64) */
+    const ldpc_code *codes;    /* request code_id indexes this array; handles must outlive the server */
+    size_t mem_budget_bytes;   /* device bytes for in-flight request buffers (LLR, bits, posterior, iters) */
+    int32_t max_inflight;      /* concurrent launch groups (streams), 1 .. 8 */
+    int32_t max_group_frames;  /* cap on frames per launch group (bounds latency), >= 1 */
+    int32_t max_queue;         /* queued requests beyond which submit returns LDPC_EBUSY, >= 1 */
+} ldpc_server_cfg;
+
+typedef struct {
+    int64_t submitted, completed, cancelled, failed, launches;
+    int64_t frames_completed, bits_completed; /* coded bits = frames * n */
+    double p50_ms, p99_ms, p999_ms, max_ms;    /* latency: completion - arrival, over completed requests */
+    double mean_group_frames;
+    int64_t max_queue_depth;
+} ldpc_server_stats;
+
+/* Create a server on the current device.  EINVAL for bad sizes or NULL
+ * arguments, EUNSUPPORTED if a code does not fit the fused kernel, ENOMEM if
+ * the arena cannot be allocated. */
+ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_server *out);
+
+/*
+ * Queue a request: `frames` frames of codes[code_id], LLRs llr[frames][n]
+ * (host memory, float), decoded with max_iter / flags as in ldpc_decode.
+ * Outputs go to host memory bits[frames][n], iters[frames] and, if non-NULL,
+ * posterior[frames][n]; every buffer must stay valid and untouched until the
+ * request is done.  arrival_ns: the request's arrival time on the
+ * CLOCK_MONOTONIC scale for latency accounting (0 = now).  *ticket receives
+ * an id for poll/wait/cancel.  EINVAL for bad arguments or a request larger
+ * than the arena / group cap; EBUSY when max_queue requests are waiting.
+ * If the device launch of a request's group fails, the request still
+ * completes, with every iteration count set to -1 (counted in stats.failed).
+ * Tickets stay valid until the server is destroyed.
+ */
+ldpc_status ldpc_server_submit(ldpc_server server, int32_t code_id, int32_t frames, int32_t max_iter, uint32_t flags,
+                               const float *llr, uint8_t *bits, int32_t *iters, float *posterior, int64_t arrival_ns,
+                               uint64_t *ticket);
+
+/* *done = 1 when the request's outputs are complete (0 otherwise).  EINVAL for an unknown ticket. */
+ldpc_status ldpc_server_poll(ldpc_server server, uint64_t ticket, int32_t *done);
+
+/* Block until the request is done or timeout_ms elapses (LDPC_EBUSY on timeout). */
+ldpc_status ldpc_server_wait(ldpc_server server, uint64_t ticket, double timeout_ms);
+
+/* Remove a request that is still queued (LDPC_OK); LDPC_EBUSY if it is already on the device or done. */
+ldpc_status ldpc_server_cancel(ldpc_server server, uint64_t ticket);
+
+/* Counters and latency percentiles since creation or the last reset. */
+ldpc_status ldpc_server_stats_get(ldpc_server server, ldpc_server_stats *out, int reset);
+
+/* Finish every admitted and queued request, stop the scheduler, free everything. */
+void ldpc_server_destroy(ldpc_server server);
+
+/*
  * Workgroup size (a multiple of 64, at most 512) of the fused frame-resident
  * kernel used by ldpc_decode_batch; default 512.  EINVAL for other values.  Process-wide setting (the
  * autotuner writes it); affects speed only, never results.

@@ -58,6 +58,27 @@ _sig("ldpc_decode", ctypes.c_int, [_P, ctypes.c_int, _I32, _I32, ctypes.c_uint32
 _sig("ldpc_batch_workspace_bytes", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int,
                                                   ctypes.POINTER(ctypes.c_size_t)])
 _sig("ldpc_decode_batch", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, _P, ctypes.c_size_t, _P])
+class ldpc_server_cfg(ctypes.Structure):
+    _fields_ = [("ncodes", _I32), ("codes", ctypes.POINTER(_P)), ("mem_budget_bytes", ctypes.c_size_t),
+                ("max_inflight", _I32), ("max_group_frames", _I32), ("max_queue", _I32)]
+
+
+class ldpc_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("launches", ctypes.c_int64), ("frames_completed", ctypes.c_int64),
+                ("bits_completed", ctypes.c_int64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("p999_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("mean_group_frames", ctypes.c_double),
+                ("max_queue_depth", ctypes.c_int64)]
+
+
+_sig("ldpc_server_create", ctypes.c_int, [ctypes.POINTER(ldpc_server_cfg), ctypes.POINTER(_P)])
+_sig("ldpc_server_submit", ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_uint32, _P, _P, _P, _P, ctypes.c_int64,
+                                          ctypes.POINTER(ctypes.c_uint64)])
+_sig("ldpc_server_poll", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_I32)])
+_sig("ldpc_server_wait", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_double])
+_sig("ldpc_server_cancel", ctypes.c_int, [_P, ctypes.c_uint64])
+_sig("ldpc_server_stats_get", ctypes.c_int, [_P, ctypes.POINTER(ldpc_server_stats), ctypes.c_int])
+_sig("ldpc_server_destroy", None, [_P])
 _sig("ldpc_batch_set_threads", ctypes.c_int, [_I32])
 _sig("ldpc_batch_fits_fused", ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)])
 _sig("ldpc_profile_enable", ctypes.c_int, [ctypes.c_int])
@@ -300,3 +321,51 @@ def decode_batch(jobs, stream=None, workspace: torch.Tensor = None):
         workspace = _workspace(need, jobs[0].llr.device)
     _check(ldpc_decode_batch(cj, dt, workspace, workspace.numel(), stream), "ldpc_decode_batch")
     return jobs
+
+
+# ------------------------------------------------------------------ serving --
+
+def ldpc_server_create(codes, mem_budget_bytes, max_inflight=3, max_group_frames=1024, max_queue=1 << 20):
+    arr = (_P * len(codes))(*[_handle(c) for c in codes])
+    cfg = ldpc_server_cfg(len(codes), arr, int(mem_budget_bytes), int(max_inflight), int(max_group_frames),
+                          int(max_queue))
+    out = _P()
+    _check(_lib.ldpc_server_create(ctypes.byref(cfg), ctypes.byref(out)), "ldpc_server_create")
+    return out.value
+
+
+def ldpc_server_submit(server, code_id, frames, max_iter, flags, llr, bits, iters, posterior=None, arrival_ns=0):
+    """Host pointers (ints) or contiguous numpy arrays.  Returns (status, ticket)."""
+    def hp(a):
+        if a is None or isinstance(a, int):
+            return a
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    t = ctypes.c_uint64()
+    st = _lib.ldpc_server_submit(server, int(code_id), int(frames), int(max_iter), int(flags), hp(llr), hp(bits),
+                                 hp(iters), hp(posterior), int(arrival_ns), ctypes.byref(t))
+    return st, t.value
+
+
+def ldpc_server_poll(server, ticket):
+    d = _I32()
+    _check(_lib.ldpc_server_poll(server, ctypes.c_uint64(ticket), ctypes.byref(d)), "ldpc_server_poll")
+    return bool(d.value)
+
+
+def ldpc_server_wait(server, ticket, timeout_ms=60000.0) -> int:
+    return _lib.ldpc_server_wait(server, ctypes.c_uint64(ticket), float(timeout_ms))
+
+
+def ldpc_server_cancel(server, ticket) -> int:
+    return _lib.ldpc_server_cancel(server, ctypes.c_uint64(ticket))
+
+
+def ldpc_server_stats_get(server, reset=False):
+    s = ldpc_server_stats()
+    _check(_lib.ldpc_server_stats_get(server, ctypes.byref(s), int(bool(reset))), "ldpc_server_stats_get")
+    return {name: getattr(s, name) for name, _ in s._fields_}
+
+
+def ldpc_server_destroy(server):
+    _lib.ldpc_server_destroy(server)

@@ -1,0 +1,512 @@
+// Serving: continuous batching of decode requests over the fused batch path.
+//
+// One scheduler thread per server.  Requests wait in a FIFO queue; whenever
+// one of the launch slots (each with its own stream) is free and the device
+// arena has room, the scheduler takes the longest prefix of the queue that
+// fits the group cap and the free memory, packs the group's LLRs contiguously
+// in pinned host staging, and enqueues on the slot's stream: one host-to-device
+// copy, ldpc_decode_batch over the group's jobs, the device-to-host copies of
+// bits / iteration counts (/ posteriors), and an event.  Groups admitted while
+// others are still running use other slots, so their kernels overlap with the
+// running ones on the device.  Completed slots are reaped by polling their
+// events; results are copied into the requesters' buffers and the memory is
+// returned to the arena.  Arithmetic is per frame, so a request's result does
+// not depend on what it was batched with.
+#include <time.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "ldpc_internal.h"
+
+namespace {
+
+int64_t now_ns()
+{
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return static_cast<int64_t>(ts.tv_sec) * 1000000000LL + ts.tv_nsec;
+}
+
+// First-fit allocator of contiguous ranges in [0, capacity).
+class RangeAlloc {
+  public:
+    explicit RangeAlloc(int64_t cap = 0) : cap_(cap)
+    {
+        if (cap > 0)
+            free_.push_back({0, cap});
+    }
+    int64_t alloc(int64_t len)
+    {
+        for (size_t i = 0; i < free_.size(); ++i)
+            if (free_[i].second >= len) {
+                const int64_t b = free_[i].first;
+                free_[i].first += len;
+                free_[i].second -= len;
+                if (free_[i].second == 0)
+                    free_.erase(free_.begin() + static_cast<long>(i));
+                return b;
+            }
+        return -1;
+    }
+    void release(int64_t begin, int64_t len)
+    {
+        auto it = std::lower_bound(free_.begin(), free_.end(), std::make_pair(begin, int64_t(0)));
+        it = free_.insert(it, {begin, len});
+        size_t i = static_cast<size_t>(it - free_.begin());
+        if (i + 1 < free_.size() && free_[i].first + free_[i].second == free_[i + 1].first) {
+            free_[i].second += free_[i + 1].second;
+            free_.erase(free_.begin() + static_cast<long>(i) + 1);
+        }
+        if (i > 0 && free_[i - 1].first + free_[i - 1].second == free_[i].first) {
+            free_[i - 1].second += free_[i].second;
+            free_.erase(free_.begin() + static_cast<long>(i));
+        }
+    }
+    int64_t capacity() const { return cap_; }
+
+  private:
+    int64_t cap_;
+    std::vector<std::pair<int64_t, int64_t>> free_;  // (begin, length), sorted by begin
+};
+
+enum ReqState { kQueued = 0, kInFlight = 1, kDone = 2, kCancelled = 3 };
+
+struct Request {
+    uint64_t ticket = 0;
+    int32_t code_id = 0, frames = 0, max_iter = 0;
+    uint32_t flags = 0;
+    const float *llr = nullptr;
+    uint8_t *bits = nullptr;
+    int32_t *iters = nullptr;
+    float *post = nullptr;
+    int64_t arrival_ns = 0, done_ns = 0;
+    int state = kQueued;
+    int64_t elem_off = 0, frame_off = 0;  // offsets inside the group's ranges
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    std::vector<Request *> reqs;
+    int64_t elem_begin = 0, elem_len = 0, frame_begin = 0, frame_len = 0;
+    bool want_post = false;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+}  // namespace
+
+struct ldpc_server_s {
+    int device = 0;
+    std::vector<ldpc_code> codes;
+    std::vector<int32_t> code_n;
+    int32_t max_group_frames = 0, max_queue = 0;
+    // device arena and its pinned host mirror (same offsets)
+    float *d_llr = nullptr, *d_post = nullptr, *h_llr = nullptr, *h_post = nullptr;
+    uint8_t *d_bits = nullptr, *h_bits = nullptr;
+    int32_t *d_iters = nullptr, *h_iters = nullptr;
+    RangeAlloc elems, frames;
+    std::vector<Slot> slots;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queue;
+    std::unordered_map<uint64_t, Request *> by_ticket;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread sched;
+
+    // statistics (guarded by mu)
+    ldpc_server_stats st{};
+    std::vector<double> lat_ms;
+    int64_t group_frames_sum = 0;
+
+    void run();
+    bool reap();
+    bool admit();
+    void free_all();
+};
+
+bool ldpc_server_s::reap()
+{
+    bool any = false;
+    for (Slot &s : slots) {
+        if (!s.busy || hipEventQuery(s.done) != hipSuccess)
+            continue;
+        const int64_t t = now_ns();
+        for (Request *r : s.reqs) {
+            const int64_t n = code_n[r->code_id];
+            const int64_t e = s.elem_begin + r->elem_off;
+            std::memcpy(r->bits, h_bits + e, static_cast<size_t>(r->frames * n));
+            std::memcpy(r->iters, h_iters + s.frame_begin + r->frame_off, sizeof(int32_t) * r->frames);
+            if (r->post)
+                std::memcpy(r->post, h_post + e, sizeof(float) * static_cast<size_t>(r->frames * n));
+            r->done_ns = t;
+            r->state = kDone;
+            lat_ms.push_back(static_cast<double>(t - r->arrival_ns) * 1e-6);
+            st.completed += 1;
+            st.frames_completed += r->frames;
+            st.bits_completed += r->frames * n;
+        }
+        s.reqs.clear();
+        elems.release(s.elem_begin, s.elem_len);
+        frames.release(s.frame_begin, s.frame_len);
+        s.busy = false;
+        any = true;
+    }
+    if (any)
+        cv_done.notify_all();
+    return any;
+}
+
+bool ldpc_server_s::admit()
+{
+    bool any = false;
+    for (Slot &s : slots) {
+        if (s.busy || queue.empty())
+            continue;
+        // longest FIFO prefix within the group cap ...
+        size_t k = 0;
+        int64_t f = 0, e = 0;
+        while (k < queue.size() && f + queue[k]->frames <= max_group_frames) {
+            f += queue[k]->frames;
+            e += static_cast<int64_t>(queue[k]->frames) * code_n[queue[k]->code_id];
+            ++k;
+        }
+        // ... that the arena can hold right now
+        int64_t eb = -1, fb = -1;
+        while (k > 0) {
+            eb = elems.alloc(e);
+            if (eb >= 0) {
+                fb = frames.alloc(f);
+                if (fb >= 0)
+                    break;
+                elems.release(eb, e);
+                eb = -1;
+            }
+            --k;
+            f -= queue[k]->frames;
+            e -= static_cast<int64_t>(queue[k]->frames) * code_n[queue[k]->code_id];
+        }
+        if (k == 0)
+            break;  // the head of the queue waits for memory (first come, first served)
+        s.reqs.assign(queue.begin(), queue.begin() + static_cast<long>(k));
+        queue.erase(queue.begin(), queue.begin() + static_cast<long>(k));
+        s.elem_begin = eb;
+        s.elem_len = e;
+        s.frame_begin = fb;
+        s.frame_len = f;
+        s.want_post = false;
+        std::vector<ldpc_job> jobs;
+        jobs.reserve(k);
+        int64_t eo = 0, fo = 0;
+        for (Request *r : s.reqs) {
+            const int64_t n = code_n[r->code_id];
+            r->elem_off = eo;
+            r->frame_off = fo;
+            r->state = kInFlight;
+            std::memcpy(h_llr + eb + eo, r->llr, sizeof(float) * static_cast<size_t>(r->frames * n));
+            ldpc_job j{};
+            j.code = codes[r->code_id];
+            j.frames = r->frames;
+            j.max_iter = r->max_iter;
+            j.flags = r->flags;
+            j.llr = d_llr + eb + eo;
+            j.bits = d_bits + eb + eo;
+            j.iters = d_iters + fb + fo;
+            j.posterior = r->post ? d_post + eb + eo : nullptr;
+            s.want_post |= r->post != nullptr;
+            jobs.push_back(j);
+            eo += r->frames * n;
+            fo += r->frames;
+        }
+        (void)hipMemcpyAsync(d_llr + eb, h_llr + eb, sizeof(float) * static_cast<size_t>(e), hipMemcpyHostToDevice,
+                             s.stream);
+        const ldpc_status rc = ldpc_decode_batch(jobs.data(), static_cast<int32_t>(jobs.size()), LDPC_F32, s.ws,
+                                                 s.ws_bytes, s.stream);
+        if (rc != LDPC_OK) {
+            // the group could not be launched: its requests complete with iteration count -1
+            (void)hipStreamSynchronize(s.stream);
+            const int64_t t = now_ns();
+            for (Request *r : s.reqs) {
+                std::fill(r->iters, r->iters + r->frames, -1);
+                r->done_ns = t;
+                r->state = kDone;
+                st.failed += 1;
+            }
+            s.reqs.clear();
+            elems.release(eb, e);
+            frames.release(fb, f);
+            cv_done.notify_all();
+            any = true;
+            continue;
+        }
+        (void)hipMemcpyAsync(h_bits + eb, d_bits + eb, static_cast<size_t>(e), hipMemcpyDeviceToHost, s.stream);
+        (void)hipMemcpyAsync(h_iters + fb, d_iters + fb, sizeof(int32_t) * static_cast<size_t>(f),
+                             hipMemcpyDeviceToHost, s.stream);
+        if (s.want_post)
+            (void)hipMemcpyAsync(h_post + eb, d_post + eb, sizeof(float) * static_cast<size_t>(e),
+                                 hipMemcpyDeviceToHost, s.stream);
+        (void)hipEventRecord(s.done, s.stream);
+        s.busy = true;
+        st.launches += 1;
+        group_frames_sum += f;
+        any = true;
+    }
+    return any;
+}
+
+void ldpc_server_s::run()
+{
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        reap();
+        admit();
+        const bool busy = std::any_of(slots.begin(), slots.end(), [](const Slot &s) { return s.busy; });
+        if (stop && queue.empty() && !busy)
+            break;
+        if (busy)
+            cv_work.wait_for(lk, std::chrono::microseconds(20));
+        else
+            cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+    }
+}
+
+void ldpc_server_s::free_all()
+{
+    for (Slot &s : slots) {
+        if (s.stream)
+            (void)hipStreamSynchronize(s.stream);
+        if (s.done)
+            (void)hipEventDestroy(s.done);
+        if (s.stream)
+            (void)hipStreamDestroy(s.stream);
+        if (s.ws)
+            (void)hipFree(s.ws);
+    }
+    if (d_llr)
+        (void)hipFree(d_llr);
+    if (h_llr)
+        (void)hipHostFree(h_llr);
+    for (auto &kv : by_ticket)
+        delete kv.second;
+    by_ticket.clear();
+}
+
+using namespace ldpc;
+
+extern "C" ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_server *out)
+{
+    if (!cfg || !out || cfg->ncodes < 1 || cfg->ncodes > 64 || !cfg->codes || cfg->max_inflight < 1 ||
+        cfg->max_inflight > 8 || cfg->max_group_frames < 1 || cfg->max_queue < 1 || cfg->mem_budget_bytes == 0)
+        return LDPC_EINVAL;
+    auto *sv = new (std::nothrow) ldpc_server_s();
+    if (!sv)
+        return LDPC_ENOMEM;
+    if (hipGetDevice(&sv->device) != hipSuccess) {
+        delete sv;
+        return LDPC_EDEVICE;
+    }
+    int32_t nmin = INT32_MAX;
+    for (int32_t i = 0; i < cfg->ncodes; ++i) {
+        ldpc_code c = cfg->codes[i];
+        if (!c || !code_on_current_device(c)) {
+            delete sv;
+            return LDPC_EINVAL;
+        }
+        if (ldpc_batch_fits_fused(c, LDPC_F32, nullptr) != LDPC_OK) {
+            delete sv;
+            return LDPC_EUNSUPPORTED;
+        }
+        sv->codes.push_back(c);
+        sv->code_n.push_back(c->n);
+        nmin = std::min(nmin, c->n);
+    }
+    sv->max_group_frames = cfg->max_group_frames;
+    sv->max_queue = cfg->max_queue;
+    // arena: per element 4 (LLR) + 1 (bit) + 4 (posterior) bytes; per frame 4 (iteration count)
+    const int64_t elems_cap = static_cast<int64_t>(cfg->mem_budget_bytes / 10);
+    const int64_t frames_cap = elems_cap / nmin + 1;
+    const size_t bytes = static_cast<size_t>(elems_cap) * 9 + static_cast<size_t>(frames_cap) * 4 + 1024;
+    void *d = nullptr, *h = nullptr;
+    if (elems_cap < 1 || hipMalloc(&d, bytes) != hipSuccess) {
+        delete sv;
+        return LDPC_ENOMEM;
+    }
+    if (hipHostMalloc(&h, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(d);
+        delete sv;
+        return LDPC_ENOMEM;
+    }
+    auto carve = [&](void *base, float *&llr, float *&post, uint8_t *&bits, int32_t *&it) {
+        char *p = static_cast<char *>(base);
+        llr = reinterpret_cast<float *>(p);
+        post = reinterpret_cast<float *>(p + align_up(static_cast<size_t>(elems_cap) * 4, 256));
+        it = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(post) + align_up(static_cast<size_t>(elems_cap) * 4, 256));
+        bits = reinterpret_cast<uint8_t *>(reinterpret_cast<char *>(it) + align_up(static_cast<size_t>(frames_cap) * 4, 256));
+    };
+    carve(d, sv->d_llr, sv->d_post, sv->d_bits, sv->d_iters);
+    carve(h, sv->h_llr, sv->h_post, sv->h_bits, sv->h_iters);
+    if (reinterpret_cast<char *>(sv->d_bits) + elems_cap > static_cast<char *>(d) + bytes) {
+        // the 256-byte alignment padding exceeded the slack; never expected with 1024 bytes of slack
+        (void)hipFree(d);
+        (void)hipHostFree(h);
+        delete sv;
+        return LDPC_EDEVICE;
+    }
+    sv->elems = RangeAlloc(elems_cap);
+    sv->frames = RangeAlloc(frames_cap);
+    sv->slots.resize(cfg->max_inflight);
+    const size_t ws_bytes = (static_cast<size_t>(cfg->max_group_frames) / 24 + 2) * 8192;
+    for (Slot &s : sv->slots) {
+        s.ws_bytes = ws_bytes;
+        if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
+            hipMalloc(&s.ws, ws_bytes) != hipSuccess) {
+            sv->free_all();
+            delete sv;
+            return LDPC_ENOMEM;
+        }
+    }
+    sv->sched = std::thread([sv] { sv->run(); });
+    *out = sv;
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_server_submit(ldpc_server sv, int32_t code_id, int32_t frames, int32_t max_iter,
+                                          uint32_t flags, const float *llr, uint8_t *bits, int32_t *iters,
+                                          float *posterior, int64_t arrival_ns, uint64_t *ticket)
+{
+    if (!sv || !ticket || code_id < 0 || code_id >= static_cast<int32_t>(sv->codes.size()) || frames < 1 ||
+        max_iter < 0 || (flags & ~LDPC_EARLY_STOP) != 0 || !llr || !bits || !iters)
+        return LDPC_EINVAL;
+    const int64_t need = static_cast<int64_t>(frames) * sv->code_n[code_id];
+    if (frames > sv->max_group_frames || need > sv->elems.capacity())
+        return LDPC_EINVAL;
+    auto *r = new (std::nothrow) Request();
+    if (!r)
+        return LDPC_ENOMEM;
+    r->code_id = code_id;
+    r->frames = frames;
+    r->max_iter = max_iter;
+    r->flags = flags;
+    r->llr = llr;
+    r->bits = bits;
+    r->iters = iters;
+    r->post = posterior;
+    r->arrival_ns = arrival_ns > 0 ? arrival_ns : now_ns();
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->stop || static_cast<int32_t>(sv->queue.size()) >= sv->max_queue) {
+            delete r;
+            return LDPC_EBUSY;
+        }
+        r->ticket = sv->next_ticket++;
+        sv->by_ticket[r->ticket] = r;
+        sv->queue.push_back(r);
+        sv->st.submitted += 1;
+        sv->st.max_queue_depth = std::max<int64_t>(sv->st.max_queue_depth, static_cast<int64_t>(sv->queue.size()));
+        *ticket = r->ticket;
+    }
+    sv->cv_work.notify_one();
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_server_poll(ldpc_server sv, uint64_t ticket, int32_t *done)
+{
+    if (!sv || !done)
+        return LDPC_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->by_ticket.find(ticket);
+    if (it == sv->by_ticket.end())
+        return LDPC_EINVAL;
+    const int s = it->second->state;
+    *done = (s == kDone || s == kCancelled) ? 1 : 0;
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_server_wait(ldpc_server sv, uint64_t ticket, double timeout_ms)
+{
+    if (!sv)
+        return LDPC_EINVAL;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->by_ticket.find(ticket);
+    if (it == sv->by_ticket.end())
+        return LDPC_EINVAL;
+    Request *r = it->second;
+    const bool ok = sv->cv_done.wait_for(lk, std::chrono::microseconds(static_cast<int64_t>(timeout_ms * 1e3)),
+                                         [&] { return r->state == kDone || r->state == kCancelled; });
+    return ok ? LDPC_OK : LDPC_EBUSY;
+}
+
+extern "C" ldpc_status ldpc_server_cancel(ldpc_server sv, uint64_t ticket)
+{
+    if (!sv)
+        return LDPC_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->by_ticket.find(ticket);
+    if (it == sv->by_ticket.end())
+        return LDPC_EINVAL;
+    Request *r = it->second;
+    if (r->state != kQueued)
+        return LDPC_EBUSY;
+    sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), r));
+    r->state = kCancelled;
+    sv->st.cancelled += 1;
+    sv->cv_done.notify_all();
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_server_stats_get(ldpc_server sv, ldpc_server_stats *out, int reset)
+{
+    if (!sv || !out)
+        return LDPC_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    ldpc_server_stats s = sv->st;
+    std::vector<double> v = sv->lat_ms;
+    auto pct = [&](double q) {
+        if (v.empty())
+            return 0.0;
+        const size_t k = std::min(v.size() - 1, static_cast<size_t>(q * static_cast<double>(v.size())));
+        std::nth_element(v.begin(), v.begin() + static_cast<long>(k), v.end());
+        return v[k];
+    };
+    s.p50_ms = pct(0.50);
+    s.p99_ms = pct(0.99);
+    s.p999_ms = pct(0.999);
+    s.max_ms = v.empty() ? 0.0 : *std::max_element(v.begin(), v.end());
+    s.mean_group_frames = s.launches ? static_cast<double>(sv->group_frames_sum) / static_cast<double>(s.launches) : 0.0;
+    *out = s;
+    if (reset) {
+        sv->st = ldpc_server_stats{};
+        sv->lat_ms.clear();
+        sv->group_frames_sum = 0;
+    }
+    return LDPC_OK;
+}
+
+extern "C" void ldpc_server_destroy(ldpc_server sv)
+{
+    if (!sv)
+        return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv_work.notify_all();
+    if (sv->sched.joinable())
+        sv->sched.join();
+    sv->free_all();
+    delete sv;
+}

@@ -146,6 +146,18 @@ class ServePool:
             self.cw.append(_codewords(_qc_mix_key(idx), per_code, 360 + idx)[1])
         self.per_code = per_code
 
+    def llr_pool(self, code_id: int) -> np.ndarray:
+        """All pre-drawn frames of one code as LLRs, each frame at its own
+        Eb/N0 drawn uniformly from [1, 3] dB (seeded); for load generation."""
+        if not hasattr(self, "_llr"):
+            self._llr = {}
+        if code_id not in self._llr:
+            rng = np.random.Generator(np.random.PCG64(405 + code_id))
+            snr = rng.uniform(1.0, 3.0, size=self.per_code)
+            rate = RATE_OF_MB[QC_MIX_MB[code_id % 4]]
+            self._llr[code_id] = channel.bpsk_awgn_llr(self.cw[code_id], snr, rate, 420 + code_id, np.float32)
+        return self._llr[code_id]
+
     def request_llr(self, req_index: int, req: ServeRequest) -> np.ndarray:
         cw_all = self.cw[req.code_id]
         start = (req_index * 37) % (self.per_code - req.frames + 1)
