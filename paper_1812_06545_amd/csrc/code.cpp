@@ -89,9 +89,9 @@ void slot_tables(const HostLayout &h, const std::vector<int32_t> &row_blk_start,
         for (int32_t i = 0; i < h.m; ++i)
             row_deg[i] = h.row_ptr[i + 1] - h.row_ptr[i];
     }
-    row_gmax.assign((h.m + 63) / 64, 0);
+    row_gmax.assign((h.m + 31) / 32, 0);
     for (int32_t i = 0; i < h.m; ++i)
-        row_gmax[i / 64] = std::max(row_gmax[i / 64], row_deg[i]);
+        row_gmax[i / 32] = std::max(row_gmax[i / 32], row_deg[i]);
     col_gmax.assign((h.n + 63) / 64, 0);
     for (int32_t j = 0; j < h.n; ++j)
         col_gmax[j / 64] = std::max(col_gmax[j / 64], h.col_ptr[j + 1] - h.col_ptr[j]);

@@ -44,29 +44,36 @@ __device__ __forceinline__ void st_lane(T *base, uint32_t lane_off, T v)
 
 // One check row of compile-time degree D: all 2D loads are issued before any
 // arithmetic (the wave waits once per row, and straight-line code lets each
-// edge start as soon as its own loads land).
+// edge start as soon as its own loads land).  Both halves of the row are
+// evaluated here (two independent chains).
 template <class A, int D, bool FIRST, bool ES>
 __device__ __forceinline__ void check_row(const int32_t *__restrict__ cols, const typename A::T *__restrict__ L,
                                           typename A::T *__restrict__ Rrow, uint32_t off, uint32_t &parity)
 {
     using T = typename A::T;
+    constexpr int H = (D + 1) / 2;
     T lv[D], rv[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         lv[k] = ld_lane(L + cols[k] * kChunk, off);
         rv[k] = FIRST ? T(0) : ld_lane(Rrow + k * kChunk, off);
     }
-    T a[D], pre[D];
-    T acc = T(0);
-    uint32_t sign_total = 0;
+    T a[D], p[D];
+    T acc0 = T(0), acc1 = T(0);
+    uint32_t sign = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         if (ES)
             parity ^= static_cast<uint32_t>(lv[k] < T(0));
         const T q = FIRST ? lv[k] : lv[k] - rv[k];
-        check_row_forward<A>(q, a[k], pre[k], acc, sign_total);
+        check_forward<A>(q, a[k], p[k], k < H ? acc0 : acc1, sign);
     }
-    check_row_backward<A, D>(a, pre, D, sign_total, [&](int k, T r) { st_lane(Rrow + k * kChunk, off, r); });
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int k = D - 1; k >= 0; --k) {
+        const T r = k < H ? check_backward<A>(a[k], p[k], s0, acc1, sign) : check_backward<A>(a[k], p[k], s1, acc0, sign);
+        st_lane(Rrow + k * kChunk, off, r);
+    }
 }
 
 // The same row for a run-time degree d <= DMAX (guarded loops; used for FP64
@@ -77,6 +84,7 @@ __device__ __forceinline__ void check_row_guarded(const int32_t *__restrict__ co
                                                   uint32_t off, uint32_t &parity)
 {
     using T = typename A::T;
+    const int h = (d + 1) / 2;
     T lv[DMAX], rv[DMAX];
 #pragma unroll
     for (int k = 0; k < DMAX; ++k) {
@@ -85,19 +93,30 @@ __device__ __forceinline__ void check_row_guarded(const int32_t *__restrict__ co
             rv[k] = FIRST ? T(0) : ld_lane(Rrow + k * kChunk, off);
         }
     }
-    T a[DMAX], pre[DMAX];
-    T acc = T(0);
-    uint32_t sign_total = 0;
+    T a[DMAX], p[DMAX];
+    T acc0 = T(0), acc1 = T(0);
+    uint32_t sign = 0;
 #pragma unroll
     for (int k = 0; k < DMAX; ++k) {
         if (k < d) {
             if (ES)
                 parity ^= static_cast<uint32_t>(lv[k] < T(0));
             const T q = FIRST ? lv[k] : lv[k] - rv[k];
-            check_row_forward<A>(q, a[k], pre[k], acc, sign_total);
+            if (k < h)
+                check_forward<A>(q, a[k], p[k], acc0, sign);
+            else
+                check_forward<A>(q, a[k], p[k], acc1, sign);
         }
     }
-    check_row_backward<A, DMAX>(a, pre, d, sign_total, [&](int k, T r) { st_lane(Rrow + k * kChunk, off, r); });
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int k = DMAX - 1; k >= 0; --k) {
+        if (k < d) {
+            const T r = k < h ? check_backward<A>(a[k], p[k], s0, acc1, sign)
+                              : check_backward<A>(a[k], p[k], s1, acc0, sign);
+            st_lane(Rrow + k * kChunk, off, r);
+        }
+    }
 }
 
 // Exact-degree dispatch for d in [D, DB]: one straight-line body per degree,

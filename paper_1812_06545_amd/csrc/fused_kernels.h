@@ -91,68 +91,83 @@ struct RowCSR {
     __device__ int32_t col(int k) const { return col_idx[e0 + k]; }
 };
 
-// One check row with run-time degree d <= D, as the straight-line body of
-// degree D.  Edges k >= d are dummies: they read slot 0 (valid for any code
-// with an edge) and enter as q = +inf, r = 0, which adds exact zeros to the
-// exclusive sums and + to the sign; nothing is written for them.
-// The forward pass parks a_k = sign(q_k) phi(|q_k|) in the edge's own r slot
-// (free once q_k is formed, and owned by this row alone) instead of a
-// register array; the backward pass reads it back and overwrites it with the
-// new message.  Only the prefix sums stay in registers.
+// Value of the partner lane (lane ^ 1): the other half of the same row.
+__device__ __forceinline__ uint32_t pair_swap(uint32_t v)
+{
+    return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float pair_swap(float v) { return __uint_as_float(pair_swap(__float_as_uint(v))); }
+__device__ __forceinline__ double pair_swap(double v)
+{
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
+    const uint64_t lo = pair_swap(static_cast<uint32_t>(b)), hi = pair_swap(static_cast<uint32_t>(b >> 32));
+    return __longlong_as_double(static_cast<long long>(lo | (hi << 32)));
+}
+
+// One half of a check row, run-time length dh <= D, as the straight-line
+// body of length D: this lane owns edges k0 .. k0+dh-1 of the row (the first
+// half, or the second), its partner lane the other half.  Edges j >= dh are
+// dummies: they read slot 0 (valid for any code with an edge) and enter as
+// q = +inf, r = 0, adding exact zeros and a + sign; nothing is written for
+// them.  The forward pass parks a_k in the edge's own r slot (free once q_k
+// is formed, owned by this lane alone) instead of a register array; after
+// the partner's half total and sign are exchanged, the backward pass reads
+// a_k back and overwrites the slot with the new message.
 template <class A, int D, class Row>
-__device__ __forceinline__ void fused_row(const Row &row, int d, typename A::T *__restrict__ sR,
-                                          const typename A::T *__restrict__ sL, bool first, uint32_t &parity)
+__device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, typename A::T *__restrict__ sR,
+                                               const typename A::T *__restrict__ sL, bool first, uint32_t &parity)
 {
     using T = typename A::T;
-    T pre[D];
+    T p[D];
     T acc = T(0);
-    uint32_t sign_total = 0;
+    uint32_t sign = 0, par = 0;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const bool real = k < d;
-        const int32_t ri = real ? row.ridx(k) : 0;
-        const T l = sL[real ? row.col(k) : 0];
+    for (int j = 0; j < D; ++j) {
+        const bool real = j < dh;
+        const int32_t ri = real ? row.ridx(k0 + j) : 0;
+        const T l = sL[real ? row.col(k0 + j) : 0];
         const T rr = first ? T(0) : sR[ri];
         const T lv = real ? l : T(__builtin_huge_val());
-        parity ^= static_cast<uint32_t>(real && lv < T(0));
+        par ^= static_cast<uint32_t>(real && lv < T(0));
         const T q = first ? lv : lv - (real ? rr : T(0));
         T a_k;
-        check_row_forward<A>(q, a_k, pre[k], acc, sign_total);
+        check_forward<A>(q, a_k, p[j], acc, sign);
         if (real)
             sR[ri] = a_k;
     }
-    T suf = T(0);
+    const T s_other = pair_swap(acc);
+    const uint32_t sign_total = sign ^ pair_swap(sign);
+    parity ^= par ^ pair_swap(par);
+    T s = T(0);
 #pragma unroll
-    for (int k = D - 1; k >= 0; --k) {
-        const bool real = k < d;
-        const int32_t ri = real ? row.ridx(k) : 0;
+    for (int j = D - 1; j >= 0; --j) {
+        const bool real = j < dh;
+        const int32_t ri = real ? row.ridx(k0 + j) : 0;
         const T a_k = real ? sR[ri] : T(0);
-        const T ex = pre[k] + suf;
-        suf += fabs(a_k);
-        T mag = A::phi(ex);
-        mag = mag < A::kRmax ? mag : A::kRmax;
+        const T r = check_backward<A>(a_k, p[j], s, s_other, sign_total);
         if (real)
-            sR[ri] = A::with_sign(mag, sign_total ^ A::sign_bit(a_k));
+            sR[ri] = r;
     }
 }
 
-// Body selection: exact-degree bodies (chosen by the wave's largest degree)
-// for FP32 circulant codes, the hot case; one padded body of degree DB for
-// FP64 and for CSR codes (fewer instantiations, same results).
+// Body selection by the wave's largest half length: exact-length bodies for
+// FP32 circulant codes, the hot case; one padded body of length DB for FP64
+// and for CSR codes (fewer instantiations, same results).
 template <class A, int D, int DB, class Row>
-__device__ __forceinline__ void fused_row_dispatch(int dwave, const Row &row, int d, typename A::T *__restrict__ sR,
-                                                   const typename A::T *__restrict__ sL, bool first, uint32_t &parity)
+__device__ __forceinline__ void fused_row_dispatch(int hwave, const Row &row, int k0, int dh,
+                                                   typename A::T *__restrict__ sR, const typename A::T *__restrict__ sL,
+                                                   bool first, uint32_t &parity)
 {
     constexpr bool exact = std::is_same<A, ArithF32>::value && std::is_same<Row, RowQC>::value;
     if constexpr (!exact) {
-        fused_row<A, DB>(row, d, sR, sL, first, parity);
+        fused_half_row<A, DB>(row, k0, dh, sR, sL, first, parity);
     } else if constexpr (D < DB) {
-        if (dwave == D)
-            fused_row<A, D>(row, d, sR, sL, first, parity);
+        if (hwave == D)
+            fused_half_row<A, D>(row, k0, dh, sR, sL, first, parity);
         else
-            fused_row_dispatch<A, D + 1, DB>(dwave, row, d, sR, sL, first, parity);
+            fused_row_dispatch<A, D + 1, DB>(hwave, row, k0, dh, sR, sL, first, parity);
     } else {
-        fused_row<A, DB>(row, d, sR, sL, first, parity);
+        fused_half_row<A, DB>(row, k0, dh, sR, sL, first, parity);
     }
 }
 
@@ -217,20 +232,28 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
     for (int32_t t = 1; t <= job.max_iter; ++t) {
         const bool first = (t == 1);
         uint32_t parity = 0;
-        for (int s = tid; s < m; s += NT) {
-            const int dwave = c.row_gmax[__builtin_amdgcn_readfirstlane(s) >> 6];
+        // two lanes per check row: lane 2i takes the first half of slot i, lane 2i+1 the second
+        for (int s2 = tid; s2 < 2 * m; s2 += NT) {
+            const int s = s2 >> 1, half = s2 & 1;
+            const int dwave = c.row_gmax[__builtin_amdgcn_readfirstlane(s) >> 5];
             if (dwave == 0)
                 continue;
+            const int hwave = (dwave + 1) >> 1;
+            int32_t d;
             if (c.qc) {
                 const int32_t si = s / Z;
                 const int32_t r = s - si * Z;
                 const int32_t i = border[si];
+                d = rbs[i + 1] - rbs[i];
+                const int32_t h = (d + 1) >> 1;
                 const RowQC row{rbs[i], r, Z, pack};
-                fused_row_dispatch<A, 1, DB>(dwave, row, rbs[i + 1] - rbs[i], sR, sL, first, parity);
+                fused_row_dispatch<A, 1, DB / 2>(hwave, row, half ? h : 0, half ? d - h : h, sR, sL, first, parity);
             } else {
                 const int32_t e0 = c.row_ptr[s];
+                d = c.row_ptr[s + 1] - e0;
+                const int32_t h = (d + 1) >> 1;
                 const RowCSR row{e0, c.col_idx};
-                fused_row_dispatch<A, 1, DB>(dwave, row, c.row_ptr[s + 1] - e0, sR, sL, first, parity);
+                fused_row_dispatch<A, 1, DB / 2>(hwave, row, half ? h : 0, half ? d - h : h, sR, sL, first, parity);
             }
         }
         const int unsat = __syncthreads_or(static_cast<int>(parity));

@@ -50,8 +50,9 @@ struct ldpc_code_s {
     // visited in "slot" order: for QC codes block-rows sorted by decreasing
     // degree (rows of one block-row consecutive), otherwise natural order;
     // brow_order[i] is the block-row in sorted position i (QC only).
-    // row_gmax[g] / col_gmax[g]: largest row / column degree among slots
-    // 64g .. 64g+63 (one wavefront's rows or columns).
+    // row_gmax[g]: largest row degree among slots 32g .. 32g+31 (one
+    // wavefront's rows: the fused kernel gives each row two lanes);
+    // col_gmax[g]: largest column degree among columns 64g .. 64g+63.
     const int32_t *brow_order = nullptr;
     const int32_t *row_gmax = nullptr;
     const int32_t *col_gmax = nullptr;

@@ -90,40 +90,43 @@ struct ArithF64 {
     }
 };
 
-// Forward half of one check row, for its k-th edge with incoming message q:
-// a[k] = sign(q) * phi(|q|) (the sign rides in the sign bit of the magnitude),
-// pre[k] = sum of the earlier edges' phi, acc += phi, sign_total ^= sign(q).
+// Exclusive sums of one check row.  The row's d edges are split at
+// h = ceil(d/2) into halves H0 = [0, h) and H1 = [h, d); for edge k in half
+// H, with p_k the sum of the earlier edges of H (left to right), s_k the sum
+// of the later edges of H (right to left) and S_other the total of the other
+// half (left to right),
+//     excl_k = (p_k + s_k) + S_other.
+// Every term is non-negative, so the order costs no accuracy; fixing it lets
+// the fused kernel spread a row over two lanes (one half each, exchanging
+// S and the sign) while the streaming kernel evaluates the same expression in
+// one lane, bit for bit.
+
+// Forward step for an edge with incoming message q: a_k = sign(q) phi(|q|)
+// (sign in the sign bit), p_k = the half's running sum, which then grows.
 template <class A>
-__device__ __forceinline__ void check_row_forward(typename A::T q, typename A::T &a_k, typename A::T &pre_k,
-                                                  typename A::T &acc, uint32_t &sign_total)
+__device__ __forceinline__ void check_forward(typename A::T q, typename A::T &a_k, typename A::T &p_k,
+                                              typename A::T &acc, uint32_t &sign)
 {
     const typename A::T mag = A::phi(fabs(q));
     a_k = A::mag_with_sign_of(mag, q);
-    pre_k = acc;
+    p_k = acc;
     acc += mag;
-    sign_total ^= A::sign_bit(q);
+    sign ^= A::sign_bit(q);
 }
 
-// One check row: given the d incoming magnitudes-with-sign a[k] = sign(q_k) * phi(|q_k|)
-// and their exclusive prefix sums pre[k], produce the outgoing r_k via `emit(k, r_k)`.
-// The suffix is accumulated from the last edge backwards; pre/suf orders are fixed
-// so every kernel gets bit-identical messages for the same row.
-template <class A, int DMAX, class Emit>
-__device__ __forceinline__ void check_row_backward(const typename A::T (&a)[DMAX], const typename A::T (&pre)[DMAX],
-                                                   int d, uint32_t sign_total, Emit emit)
+// Backward step: outgoing message of an edge from its a_k, p_k, the half's
+// running suffix s (which then grows), the other half's total and the row's
+// total sign.
+template <class A>
+__device__ __forceinline__ typename A::T check_backward(typename A::T a_k, typename A::T p_k, typename A::T &s,
+                                                        typename A::T s_other, uint32_t sign_total)
 {
     using T = typename A::T;
-    T suf = T(0);
-#pragma unroll
-    for (int k = DMAX - 1; k >= 0; --k) {
-        if (k < d) {
-            const T ex = pre[k] + suf;
-            suf += fabs(a[k]);
-            T mag = A::phi(ex);
-            mag = mag < A::kRmax ? mag : A::kRmax;
-            emit(k, A::with_sign(mag, sign_total ^ A::sign_bit(a[k])));
-        }
-    }
+    const T ex = (p_k + s) + s_other;
+    s += fabs(a_k);
+    T mag = A::phi(ex);
+    mag = mag < A::kRmax ? mag : A::kRmax;
+    return A::with_sign(mag, sign_total ^ A::sign_bit(a_k));
 }
 
 }  // namespace ldpc
