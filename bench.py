@@ -33,10 +33,33 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of the open-loop serving run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="offered requests per second")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batch-path and other-workload timings")
+    ap.add_argument("--copy-probe-mb", type=int, default=512,
+                    help="size of the streaming copy that measures achievable HBM bandwidth (0 = skip)")
     return ap.parse_args()
 
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per check-kernel launch on this workload, from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE; reads scaled by 2.0 and writes by 1.0,
+# the ratios of true bytes to counter readings for the library's copy
+# kernel), averaged over one first-iteration and nine later launches.  Valid
+# only for the kernel source they were taken on (hash below); otherwise null.
+CHECK_TRAFFIC = {
+    "bytes_per_launch": 555.2e6,
+    "source_sha256": "7457961639e8122b8b43542a3d4a4d065f337f229b38c491f74e1a2b08627287",
+    "profile": "profiles/hbm_traffic_check_qc1944.md",
+}
+CHECK_SOURCES = ("flood_kernels.h", "spa_math.h", "check_f32_d24.hip")
+
+
+def check_source_hash():
+    import hashlib
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1812_06545_amd", "csrc")
+    lines = "".join(f"{hashlib.sha256(open(os.path.join(here, f), 'rb').read()).hexdigest()}  "
+                    f"paper_1812_06545_amd/csrc/{f}\n" for f in CHECK_SOURCES)
+    return hashlib.sha256(lines.encode()).hexdigest()
 
 
 def main():
@@ -119,10 +142,23 @@ def main():
         bytes_per_launch = F * (4 * n + n + 4 * n + 4)
     avg_ms = kms / max(kcount, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if kcount else None
+    traffic = None
+    if args.path == "plain" and check_source_hash() == CHECK_TRAFFIC["source_sha256"]:
+        traffic = CHECK_TRAFFIC["bytes_per_launch"]
     roofline = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "traffic_unit": "bytes per launch", "traffic_profile": CHECK_TRAFFIC["profile"] if traffic else None,
                 "launch_ms": avg_ms, "launches": kcount, "bytes_per_launch": bytes_per_launch}
     kernels = {k: {"ms_total": v[0], "launches": v[1]} for k, v in prof.items() if v[1]}
+
+    other_path = None
+    if args.path == "plain" and not args.no_extra:
+        other_path = batch_path_run(h, llrs, bits, iters, post, F, n, T, args.steps)
+    extra = None if args.no_extra else extra_workloads()
+
+    copy = copy_probe(args.copy_probe_mb) if args.copy_probe_mb > 0 else None
+    if copy and achieved:
+        roofline["frac_of_copy"] = achieved / copy["gbs"]
 
     serving = serve_run(args.serve_seconds, args.serve_rate) if args.serve_seconds > 0 else None
 
@@ -149,10 +185,121 @@ def main():
         "info_mbps": k_info * F * args.steps / elapsed / 1e6,
         "roofline": roofline,
         "kernels": kernels,
+        "batch_path": other_path,
+        "other_workloads": extra,
+        "copy_probe": copy,
         "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def _time_ms(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batch_path_run(h, llrs, bits, iters, post, F, n, T, steps):
+    """The same workload through ldpc_decode_batch (the fused frame-resident
+    persistent kernel), timed on its own after the headline region."""
+    import torch
+
+    import paper_1812_06545_amd as L
+    jobs = [[L.ldpc_job(h.handle, F, T, 0, llrs[i].data_ptr(), bits.data_ptr(), iters.data_ptr(), post.data_ptr())]
+            for i in range(4)]
+    wsb = L.ldpc_batch_workspace_bytes(jobs[0], torch.float32)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+    k = [0]
+
+    def step():
+        if L.ldpc_decode_batch(jobs[k[0] % 4], torch.float32, ws, wsb) != 0:
+            raise RuntimeError("ldpc_decode_batch failed")
+        k[0] += 1
+    ms = _time_ms(step, steps)
+    return {"entry": "ldpc_decode_batch (fused frame-resident persistent kernel)", "ms_per_step": ms,
+            "mbps": F * n / (ms * 1e-3) / 1e6}
+
+
+def extra_workloads():
+    """The other seeded workloads, each timed with HIP events on the device:
+    - gallager504 (FP64, 1000 frames, 20 iterations, early stop): plain and batch;
+    - qc_mix (12 codes, 16384 frames, 10 iterations, early stop): one batched
+      launch vs twelve plain per-code launches (identical outputs);
+    - stair64800 (256 frames, 50 iterations, early stop): plain path."""
+    import torch
+
+    import paper_1812_06545_amd as L
+    from workloads import configs
+    out = {}
+
+    def plain_and_batch(batches, dtype, reps):
+        hs = [L.Code.from_workload(b.code) for b in batches]
+        jobs = [L.Job(hh, torch.from_numpy(b.llr).cuda(), b.max_iter, early_stop=b.early_stop)
+                for hh, b in zip(hs, batches)]
+        wsz = max(L.ldpc_workspace_bytes(hh, dtype, b.llr.shape[0], b.max_iter) for hh, b in zip(hs, batches))
+        ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+
+        def plain():
+            for hh, j in zip(hs, jobs):
+                L.decode(hh, j.llr, j.max_iter, early_stop=j.early_stop, workspace=ws)
+        cj = [j.c_struct() for j in jobs]
+        bw = L.ldpc_batch_workspace_bytes(cj, dtype)
+        bws = torch.empty(max(bw, 1), dtype=torch.uint8, device="cuda")
+
+        def batched():
+            if L.ldpc_decode_batch(cj, dtype, bws, bw) != 0:
+                raise RuntimeError("ldpc_decode_batch failed")
+        bits = sum(b.llr.shape[0] * b.code.n for b in batches)
+        tp, tb = _time_ms(plain, reps), _time_ms(batched, reps)
+        mean_it = float(sum(j.iters.float().sum().item() for j in jobs) / sum(b.llr.shape[0] for b in batches))
+        return {"plain_ms": tp, "plain_mbps": bits / (tp * 1e-3) / 1e6, "batch_ms": tb,
+                "batch_mbps": bits / (tb * 1e-3) / 1e6, "mean_iters": mean_it}
+
+    out["gallager504_f64"] = plain_and_batch([configs.gallager504()], torch.float64, 5)
+    out["qc_mix_16384"] = plain_and_batch(configs.qc_mix(), torch.float32, 5)
+    st = configs.stair64800()
+    hs = L.Code.from_workload(st.code)
+    llr = torch.from_numpy(st.llr).cuda()
+    ws = torch.empty(L.ldpc_workspace_bytes(hs, torch.float32, 256, 50), dtype=torch.uint8, device="cuda")
+    res = {}
+
+    def run():
+        res["out"] = L.decode(hs, llr, 50, early_stop=True, workspace=ws)
+    ms = _time_ms(run, 3)
+    out["stair64800"] = {"plain_ms": ms, "plain_mbps": 256 * st.code.n / (ms * 1e-3) / 1e6,
+                         "mean_iters": float(res["out"][1].float().mean().item())}
+    return out
+
+
+def copy_probe(mb):
+    """Achievable HBM bandwidth: the library's streaming copy kernel over `mb`
+    MiB (read + write bytes per second), median of 5 HIP-event timings."""
+    import torch
+
+    import paper_1812_06545_amd as L
+    nbytes = mb << 20
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    times = []
+    for rep in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        if L.ldpc_copy_probe(dst, src, nbytes) != 0:
+            raise RuntimeError("ldpc_copy_probe failed")
+        e1.record()
+        torch.cuda.synchronize()
+        if rep:
+            times.append(e0.elapsed_time(e1))
+    ms = sorted(times)[len(times) // 2]
+    return {"bytes": 2 * nbytes, "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
 def serve_run(seconds, rate):

@@ -164,6 +164,21 @@ ldpc_status ldpc_decode_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt
                               size_t workspace_bytes, void *stream);
 
 /*
+ * Plans: the launch sequence of ldpc_decode_batch for these jobs, captured
+ * once in a HIP graph (kernel nodes only) and replayed by ldpc_plan_launch.
+ * The job buffers and the workspace are fixed at creation and must outlive
+ * the plan; each launch decodes whatever the LLR buffers hold when it runs,
+ * with results identical to ldpc_decode_batch on the same inputs.  Creation
+ * captures on a private stream and enqueues nothing.  Errors as
+ * ldpc_decode_batch; EDEVICE if capture or instantiation fails.
+ */
+typedef struct ldpc_plan_s *ldpc_plan;
+ldpc_status ldpc_plan_create(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, void *workspace,
+                             size_t workspace_bytes, ldpc_plan *out);
+ldpc_status ldpc_plan_launch(ldpc_plan plan, void *stream);
+void ldpc_plan_destroy(ldpc_plan plan);
+
+/*
  * Serving: continuous batching of decode requests (one request = 1 or more
  * frames of one code).  A scheduler thread owned by the server admits queued
  * requests, first come first served, whenever device memory (a fixed arena
@@ -239,6 +254,20 @@ void ldpc_server_destroy(ldpc_server server);
 ldpc_status ldpc_batch_set_threads(int32_t threads);
 
 /*
+ * Autotuner of the batch path.  Decodes the given batch (its output buffers
+ * are overwritten, inputs untouched) once per candidate workgroup size of
+ * the fused kernel (128, 256, 384, 512), checks that every candidate gives
+ * bit-identical outputs, times each (HIP events, 3 runs after a warm-up) and
+ * records the fastest for this batch shape (codes, frame counts rounded up
+ * to a power of two, iteration caps, flags, dtype); later ldpc_decode_batch
+ * calls of the same shape use it.  Blocks until done.  *best_threads and
+ * *best_ms (may be NULL) receive the choice and its time.  LDPC_EDEVICE if
+ * candidates disagree (then nothing is recorded).
+ */
+ldpc_status ldpc_autotune_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, void *workspace,
+                                size_t workspace_bytes, void *stream, int32_t *best_threads, double *best_ms);
+
+/*
  * Whether frames of `code` in `dtype` can run in the fused frame-resident
  * kernel on the current device (row degree <= 32, n < 65536 and one frame's
  * messages within one workgroup's LDS).  LDPC_OK if so, LDPC_EUNSUPPORTED if
@@ -268,6 +297,13 @@ typedef enum {
 
 ldpc_status ldpc_profile_enable(int enable);
 ldpc_status ldpc_profile_collect(double *ms, int64_t *counts);
+
+/*
+ * Streaming copy of `bytes` (a multiple of 16; both pointers 16-byte aligned,
+ * device memory) on `stream`: a yardstick for achievable HBM bandwidth and
+ * for scaling hardware byte counters.  Not part of decoding.
+ */
+ldpc_status ldpc_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
 
 #if defined(__GNUC__)
 #pragma GCC visibility pop

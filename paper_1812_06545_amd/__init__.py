@@ -79,9 +79,16 @@ _sig("ldpc_server_wait", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_double])
 _sig("ldpc_server_cancel", ctypes.c_int, [_P, ctypes.c_uint64])
 _sig("ldpc_server_stats_get", ctypes.c_int, [_P, ctypes.POINTER(ldpc_server_stats), ctypes.c_int])
 _sig("ldpc_server_destroy", None, [_P])
+_sig("ldpc_plan_create", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, _P, ctypes.c_size_t,
+                                        ctypes.POINTER(_P)])
+_sig("ldpc_plan_launch", ctypes.c_int, [_P, _P])
+_sig("ldpc_plan_destroy", None, [_P])
 _sig("ldpc_batch_set_threads", ctypes.c_int, [_I32])
+_sig("ldpc_autotune_batch", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, _P, ctypes.c_size_t, _P,
+                                           ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double)])
 _sig("ldpc_batch_fits_fused", ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)])
 _sig("ldpc_profile_enable", ctypes.c_int, [ctypes.c_int])
+_sig("ldpc_copy_probe", ctypes.c_int, [_P, _P, ctypes.c_size_t, _P])
 _sig("ldpc_profile_collect", ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)])
 
 KERNEL_KINDS = ("ingest", "check", "variable", "output", "fused", "other")
@@ -205,6 +212,40 @@ def ldpc_decode_batch(jobs, dtype, workspace, workspace_bytes, stream=None) -> i
                                   _stream_handle(stream))
 
 
+def ldpc_plan_create(jobs, dtype, workspace, workspace_bytes) -> int:
+    arr = _jobs_array(jobs)
+    out = _P()
+    _check(_lib.ldpc_plan_create(arr, len(jobs), _dtype_code(dtype), _ptr(workspace), int(workspace_bytes),
+                                 ctypes.byref(out)), "ldpc_plan_create")
+    return out.value
+
+
+def ldpc_plan_launch(plan, stream=None) -> int:
+    return _lib.ldpc_plan_launch(plan, _stream_handle(stream))
+
+
+def ldpc_plan_destroy(plan):
+    _lib.ldpc_plan_destroy(plan)
+
+
+def ldpc_autotune_batch(jobs, dtype, workspace, workspace_bytes, stream=None):
+    """-> (best_threads, best_ms)."""
+    arr = _jobs_array(jobs)
+    t, ms = _I32(), ctypes.c_double()
+    _check(_lib.ldpc_autotune_batch(arr, len(jobs), _dtype_code(dtype), _ptr(workspace), int(workspace_bytes),
+                                    _stream_handle(stream), ctypes.byref(t), ctypes.byref(ms)), "ldpc_autotune_batch")
+    return t.value, ms.value
+
+
+def autotune_batch(jobs, stream=None):
+    """Autotune ldpc_decode_batch for these Jobs; returns (threads, ms)."""
+    cj = [j.c_struct() for j in jobs]
+    dt = jobs[0].llr.dtype
+    need = ldpc_batch_workspace_bytes(cj, dt)
+    ws = _workspace(need, jobs[0].llr.device)
+    return ldpc_autotune_batch(cj, dt, ws, ws.numel(), stream)
+
+
 def ldpc_batch_set_threads(threads: int) -> int:
     return _lib.ldpc_batch_set_threads(int(threads))
 
@@ -216,6 +257,10 @@ def ldpc_batch_fits_fused(handle, dtype):
     if st not in (LDPC_OK, LDPC_EUNSUPPORTED):
         raise LdpcError(st, "ldpc_batch_fits_fused")
     return st == LDPC_OK, b.value
+
+
+def ldpc_copy_probe(dst, src, nbytes, stream=None) -> int:
+    return _lib.ldpc_copy_probe(_ptr(dst), _ptr(src), int(nbytes), _stream_handle(stream))
 
 
 def ldpc_profile_enable(enable: bool) -> int:
@@ -309,6 +354,32 @@ class Job:
         return ldpc_job(self.code.handle, self.llr.shape[0], self.max_iter,
                         LDPC_EARLY_STOP if self.early_stop else 0, _ptr(self.llr), _ptr(self.bits),
                         _ptr(self.iters), _ptr(self.posterior))
+
+
+class Plan:
+    """A captured ldpc_decode_batch over fixed Job buffers (replay with launch())."""
+
+    def __init__(self, jobs):
+        self.jobs = jobs
+        dt = jobs[0].llr.dtype
+        cj = [j.c_struct() for j in jobs]
+        need = ldpc_batch_workspace_bytes(cj, dt)
+        self.workspace = _workspace(need, jobs[0].llr.device)
+        self.handle = ldpc_plan_create(cj, dt, self.workspace, self.workspace.numel())
+
+    def launch(self, stream=None):
+        _check(ldpc_plan_launch(self.handle, stream), "ldpc_plan_launch")
+
+    def close(self):
+        if self.handle:
+            ldpc_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def decode_batch(jobs, stream=None, workspace: torch.Tensor = None):

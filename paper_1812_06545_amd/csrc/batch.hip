@@ -7,7 +7,11 @@
 // per-iteration path on the same stream.  The batch table of each launch is
 // written on the device by a tiny kernel that receives it by value.
 #include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "fused_kernels.h"
@@ -16,7 +20,34 @@ namespace ldpc {
 namespace {
 
 std::mutex g_mu;
-int g_threads = 512;  // workgroup size of the fused kernel (set by ldpc_batch_set_threads)
+int g_threads = 512;                // workgroup size of the fused kernel (set by ldpc_batch_set_threads)
+std::map<std::string, int> g_tuned;  // batch shape -> workgroup size chosen by ldpc_autotune_batch
+
+// Shape of a batch for the tuning table: dtype and, per job, the code (by
+// address), frames rounded up to a power of two, iteration cap and flags.
+std::string shape_key(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt)
+{
+    std::string k = std::to_string(static_cast<int>(dt));
+    for (int32_t i = 0; i < njobs; ++i) {
+        int64_t f = 1;
+        while (f < jobs[i].frames)
+            f <<= 1;
+        k += ':' + std::to_string(reinterpret_cast<uintptr_t>(jobs[i].code)) + ',' + std::to_string(f) + ',' +
+             std::to_string(jobs[i].max_iter) + ',' + std::to_string(jobs[i].flags);
+    }
+    return k;
+}
+
+int threads_for(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_tuned.empty()) {
+        auto it = g_tuned.find(shape_key(jobs, njobs, dt));
+        if (it != g_tuned.end())
+            return it->second;
+    }
+    return g_threads;
+}
 
 size_t lds_limit()
 {
@@ -253,11 +284,7 @@ extern "C" ldpc_status ldpc_decode_batch(const ldpc_job *jobs, int32_t njobs, ld
         return LDPC_OK;
     if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return LDPC_EINVAL;
-    int threads;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        threads = g_threads;
-    }
+    const int threads = threads_for(jobs, njobs, dtype);
     const hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
     for (const Group &g : groups) {
@@ -296,4 +323,94 @@ extern "C" ldpc_status ldpc_batch_fits_fused(ldpc_code code, ldpc_dtype dtype, s
     if (lds_bytes)
         *lds_bytes = f.lds;
     return f.ok ? LDPC_OK : LDPC_EUNSUPPORTED;
+}
+
+namespace {
+
+// Outputs of every job copied to the host (for the candidates' bitwise check).
+ldpc_status snapshot(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, hipStream_t s, std::vector<char> &out)
+{
+    out.clear();
+    const size_t ts = dt == LDPC_F64 ? 8 : 4;
+    for (int32_t i = 0; i < njobs; ++i) {
+        const ldpc_job &j = jobs[i];
+        const size_t fn = static_cast<size_t>(j.frames) * static_cast<size_t>(j.code->n);
+        const size_t at = out.size();
+        out.resize(at + fn + 4 * static_cast<size_t>(j.frames) + (j.posterior ? fn * ts : 0));
+        if (hipMemcpyAsync(out.data() + at, j.bits, fn, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(out.data() + at + fn, j.iters, 4 * static_cast<size_t>(j.frames), hipMemcpyDeviceToHost,
+                           s) != hipSuccess)
+            return LDPC_EDEVICE;
+        if (j.posterior && hipMemcpyAsync(out.data() + at + fn + 4 * static_cast<size_t>(j.frames), j.posterior,
+                                          fn * ts, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return LDPC_EDEVICE;
+    }
+    return hipStreamSynchronize(s) == hipSuccess ? LDPC_OK : LDPC_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" ldpc_status ldpc_autotune_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, void *workspace,
+                                           size_t workspace_bytes, void *stream, int32_t *best_threads,
+                                           double *best_ms)
+{
+    const ldpc_status st = validate_jobs(jobs, njobs, dtype);
+    if (st != LDPC_OK)
+        return st;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    static const int kCandidates[] = {128, 256, 384, 512};
+    const std::string key = shape_key(jobs, njobs, dtype);
+    std::vector<char> ref, cur;
+    int best = 0;
+    double best_t = 0.0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return LDPC_EDEVICE;
+    ldpc_status rc = LDPC_OK;
+    for (int threads : kCandidates) {
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_tuned[key] = threads;
+        }
+        rc = ldpc_decode_batch(jobs, njobs, dtype, workspace, workspace_bytes, stream);  // warm-up
+        if (rc != LDPC_OK)
+            break;
+        rc = snapshot(jobs, njobs, dtype, s, cur);
+        if (rc != LDPC_OK)
+            break;
+        if (ref.empty())
+            ref = cur;
+        else if (ref.size() != cur.size() || std::memcmp(ref.data(), cur.data(), ref.size()) != 0) {
+            rc = LDPC_EDEVICE;  // a schedule changed the results: never expected, refuse to tune
+            break;
+        }
+        constexpr int kReps = 3;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < kReps && rc == LDPC_OK; ++r)
+            rc = ldpc_decode_batch(jobs, njobs, dtype, workspace, workspace_bytes, stream);
+        (void)hipEventRecord(e1, s);
+        float ms = 0.f;
+        if (rc != LDPC_OK || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = rc == LDPC_OK ? LDPC_EDEVICE : rc;
+            break;
+        }
+        const double t = ms / kReps;
+        if (best == 0 || t < best_t) {
+            best = threads;
+            best_t = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (rc != LDPC_OK || best == 0) {
+        g_tuned.erase(key);
+        return rc != LDPC_OK ? rc : LDPC_EDEVICE;
+    }
+    g_tuned[key] = best;
+    if (best_threads)
+        *best_threads = best;
+    if (best_ms)
+        *best_ms = best_t;
+    return LDPC_OK;
 }

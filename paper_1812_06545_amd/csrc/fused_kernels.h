@@ -91,18 +91,16 @@ struct RowCSR {
     __device__ int32_t col(int k) const { return col_idx[e0 + k]; }
 };
 
-// Value of the partner lane (lane ^ 1): the other half of the same row.
+// Value of the partner lane (lane ^ 32): the other half of the same row.
+// Rows are laid out so that lanes 0..31 of a wavefront hold the first halves
+// of 32 consecutive rows and lanes 32..63 their second halves; each half
+// wavefront then touches 32 consecutive LDS words (no bank conflicts).
 __device__ __forceinline__ uint32_t pair_swap(uint32_t v)
 {
-    return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), 0xB1, 0xF, 0xF, false));
+    return static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), 32));
 }
-__device__ __forceinline__ float pair_swap(float v) { return __uint_as_float(pair_swap(__float_as_uint(v))); }
-__device__ __forceinline__ double pair_swap(double v)
-{
-    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
-    const uint64_t lo = pair_swap(static_cast<uint32_t>(b)), hi = pair_swap(static_cast<uint32_t>(b >> 32));
-    return __longlong_as_double(static_cast<long long>(lo | (hi << 32)));
-}
+__device__ __forceinline__ float pair_swap(float v) { return __shfl_xor(v, 32); }
+__device__ __forceinline__ double pair_swap(double v) { return __shfl_xor(v, 32); }
 
 // One half of a check row, run-time length dh <= D, as the straight-line
 // body of length D: this lane owns edges k0 .. k0+dh-1 of the row (the first
@@ -232,11 +230,13 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
     for (int32_t t = 1; t <= job.max_iter; ++t) {
         const bool first = (t == 1);
         uint32_t parity = 0;
-        // two lanes per check row: lane 2i takes the first half of slot i, lane 2i+1 the second
-        for (int s2 = tid; s2 < 2 * m; s2 += NT) {
-            const int s = s2 >> 1, half = s2 & 1;
-            const int dwave = c.row_gmax[__builtin_amdgcn_readfirstlane(s) >> 5];
-            if (dwave == 0)
+        // two lanes per check row: in each wavefront, lane l < 32 takes the
+        // first half of slot rb + l and lane l + 32 its second half
+        const int lane = tid & 63, half = lane >> 5;
+        for (int rb = (tid >> 6) * 32; rb < m; rb += (NT >> 6) * 32) {
+            const int dwave = c.row_gmax[__builtin_amdgcn_readfirstlane(rb) >> 5];
+            const int s = rb + (lane & 31);
+            if (dwave == 0 || s >= m)
                 continue;
             const int hwave = (dwave + 1) >> 1;
             int32_t d;

@@ -179,3 +179,49 @@ def test_fused_threads_do_not_change_results(L, threads):
     for g, w in zip(got, want):
         for x, y in zip(g, w):
             assert np.array_equal(x, y)
+
+
+def test_plan_replays_match_eager(L):
+    """A captured plan replayed several times, with eager work and
+    synchronisations between replays and new LLRs in place, matches the eager
+    ldpc_decode_batch on the same inputs every time."""
+    import torch
+    mix = configs.qc_mix(total=600)
+    stair = configs.stair64800(frames=4)
+    items = [(L.Code.from_workload(m.code), m.llr) for m in mix[:5]] + [(L.Code.from_workload(stair.code), stair.llr)]
+    jobs = [L.Job(h, torch.from_numpy(np.ascontiguousarray(llr)).cuda(), 12, early_stop=True) for h, llr in items]
+    plan = L.Plan(jobs)
+    rng = np.random.default_rng(9)
+    try:
+        for rep in range(4):
+            if rep:
+                for j in jobs:  # new inputs in the same buffers
+                    j.llr.copy_(torch.from_numpy((rng.normal(1.5, 2.0, size=tuple(j.llr.shape))).astype(np.float32)))
+            _log(f"[gpu] plan replay {rep}")
+            plan.launch()
+            torch.cuda.synchronize()
+            got = [_np(j) for j in jobs]
+            _ = torch.ones(1024, device="cuda").sum().item()  # eager work between replays
+            eager = [L.Job(j.code, j.llr.clone(), 12, early_stop=True) for j in jobs]
+            L.decode_batch(eager)
+            torch.cuda.synchronize()
+            for g, e in zip(got, eager):
+                for x, y in zip(g, _np(e)):
+                    assert np.array_equal(x, y), f"replay {rep} differs from eager"
+    finally:
+        plan.close()
+
+
+def test_autotune_keeps_results(L):
+    import torch
+    mix = configs.qc_mix(total=2000)
+    items = [(L.Code.from_workload(m.code), m.llr) for m in mix]
+    before = [_np(j) for j in _batch(L, items)]
+    jobs = [L.Job(h, torch.from_numpy(llr).cuda(), 10, early_stop=True) for h, llr in items]
+    threads, ms = L.autotune_batch(jobs)
+    _log(f"[gpu] autotune: threads={threads} ms={ms:.3f}")
+    assert threads in (128, 256, 384, 512) and ms > 0
+    after = [_np(j) for j in _batch(L, items)]
+    for b, a in zip(before, after):
+        for x, y in zip(b, a):
+            assert np.array_equal(x, y)
