@@ -181,13 +181,16 @@ void ldpc_plan_destroy(ldpc_plan plan);
 /*
  * Serving: continuous batching of decode requests (one request = 1 or more
  * frames of one code).  A scheduler thread owned by the server admits queued
- * requests, first come first served, whenever device memory (a fixed arena
- * sized by mem_budget_bytes) and one of max_inflight launch slots are free;
- * each admitted group is packed contiguously, copied to the device in one
- * transfer, decoded by one ldpc_decode_batch call on the slot's own stream
- * (so a group admitted while others run overlaps with them on the device),
- * and copied back; the scheduler then fills the requester's host buffers and
- * marks the request done.  Every frame's result equals decoding it alone.
+ * requests, first come first served, whenever arena memory (fixed at
+ * creation, sized by mem_budget_bytes) and one of max_inflight launch slots
+ * are free; each admitted group's LLRs are packed contiguously in pinned host
+ * memory, moved to the device by one copy kernel and decoded by one
+ * ldpc_decode_batch call on the slot's own stream (so a group admitted while
+ * others run overlaps with them on the device); the decode kernel writes the
+ * results into pinned host memory, from which the scheduler fills the
+ * requester's buffers and marks the request done.  The requester's LLRs are
+ * read when the group is admitted, so they must stay valid until the request
+ * completes.  Every frame's result equals decoding it alone.
  * Codes must fit the fused kernel (ldpc_batch_fits_fused), all FP32.
  */
 typedef struct ldpc_server_s *ldpc_server;
@@ -195,7 +198,8 @@ typedef struct ldpc_server_s *ldpc_server;
 typedef struct {
     int32_t ncodes;            /* number of codes served (<= 64) */
     const ldpc_code *codes;    /* request code_id indexes this array; handles must outlive the server */
-    size_t mem_budget_bytes;   /* device bytes for in-flight request buffers (LLR, bits, posterior, iters) */
+    size_t mem_budget_bytes;   /* arena for in-flight requests: about budget/10 coded bits (frames x n) at once,
+                                  each 4 bytes of device memory (LLR) and 9 of pinned host memory */
     int32_t max_inflight;      /* concurrent launch groups (streams), 1 .. 8 */
     int32_t max_group_frames;  /* cap on frames per launch group (bounds latency), >= 1 */
     int32_t max_queue;         /* queued requests beyond which submit returns LDPC_EBUSY, >= 1 */
@@ -209,9 +213,12 @@ typedef struct {
     int64_t max_queue_depth;
 } ldpc_server_stats;
 
-/* Create a server on the current device.  EINVAL for bad sizes or NULL
- * arguments, EUNSUPPORTED if a code does not fit the fused kernel, ENOMEM if
- * the arena cannot be allocated. */
+/* Create a server on the current device.  Before returning it decodes one
+ * frame of every code on every launch stream (synchronously), so that stream
+ * set-up and kernel loading, which happen on first use, are not charged to
+ * the first requests.  EINVAL for bad sizes or NULL arguments, EUNSUPPORTED
+ * if a code does not fit the fused kernel, ENOMEM if the arena cannot be
+ * allocated, EDEVICE (or the failing call's status) if the warm-up fails. */
 ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_server *out);
 
 /*

@@ -1,5 +1,6 @@
-// Streaming copy kernel of known size: the yardstick for achievable HBM
-// bandwidth and for scaling hardware byte counters (a measurement aid).
+// Streaming copy kernel: the yardstick for achievable HBM bandwidth and for
+// scaling hardware byte counters, and the serving loop's host-to-device
+// staging copy (it reads pinned host memory across the link).
 #include <algorithm>
 
 #include "ldpc_internal.h"
@@ -28,20 +29,28 @@ __global__ __launch_bounds__(256) void k_copy(const float4 *__restrict__ src, fl
 
 }  // namespace
 
-extern "C" ldpc_status ldpc_copy_probe(void *dst, const void *src, size_t bytes, void *stream)
+namespace ldpc {
+
+ldpc_status launch_copy16(void *dst, const void *src, size_t bytes, int cus, hipStream_t stream)
 {
     if (!dst || !src || bytes == 0 || bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(dst) & 15) ||
-        (reinterpret_cast<uintptr_t>(src) & 15))
+        (reinterpret_cast<uintptr_t>(src) & 15) || cus < 1)
         return LDPC_EINVAL;
     const int64_t n = static_cast<int64_t>(bytes / 16);
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, static_cast<int64_t>(cus) * 32);
+    ProfScope ps(LDPC_KERNEL_OTHER, stream);
+    hipLaunchKernelGGL(k_copy, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                       static_cast<const float4 *>(src), static_cast<float4 *>(dst), n);
+    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EDEVICE;
+}
+
+}  // namespace ldpc
+
+extern "C" ldpc_status ldpc_copy_probe(void *dst, const void *src, size_t bytes, void *stream)
+{
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return LDPC_EDEVICE;
-    const int64_t blocks = std::min<int64_t>((n + 255) / 256, static_cast<int64_t>(cus) * 32);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    ldpc::ProfScope ps(LDPC_KERNEL_OTHER, s);
-    hipLaunchKernelGGL(k_copy, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                       static_cast<const float4 *>(src), static_cast<float4 *>(dst), n);
-    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EDEVICE;
+    return ldpc::launch_copy16(dst, src, bytes, cus, static_cast<hipStream_t>(stream));
 }

@@ -4,14 +4,17 @@
 // one of the launch slots (each with its own stream) is free and the device
 // arena has room, the scheduler takes the longest prefix of the queue that
 // fits the group cap and the free memory, packs the group's LLRs contiguously
-// in pinned host staging, and enqueues on the slot's stream: one host-to-device
-// copy, ldpc_decode_batch over the group's jobs, the device-to-host copies of
-// bits / iteration counts (/ posteriors), and an event.  Groups admitted while
+// in pinned host staging, and enqueues on the slot's stream: a copy kernel that
+// moves them into the device arena, ldpc_decode_batch over the group's jobs
+// (which writes bits, iteration counts and posteriors straight into pinned
+// host memory), and an event.  Groups admitted while
 // others are still running use other slots, so their kernels overlap with the
 // running ones on the device.  Completed slots are reaped by polling their
 // events; results are copied into the requesters' buffers and the memory is
-// returned to the arena.  Arithmetic is per frame, so a request's result does
-// not depend on what it was batched with.
+// returned to the arena.  The lock is held only to move requests between the
+// queue and the slots: the staging copies, launches and result copies run
+// without it, so a large group never holds up submitters.  Arithmetic is per
+// frame, so a request's result does not depend on what it was batched with.
 #include <time.h>
 
 #include <algorithm>
@@ -78,6 +81,10 @@ class RangeAlloc {
     std::vector<std::pair<int64_t, int64_t>> free_;  // (begin, length), sorted by begin
 };
 
+// LLR ranges are kept in multiples of 4 elements so that every range starts
+// 16-byte aligned, as the copy kernel needs.
+inline int64_t align4(int64_t e) { return (e + 3) & ~int64_t(3); }
+
 enum ReqState { kQueued = 0, kInFlight = 1, kDone = 2, kCancelled = 3 };
 
 struct Request {
@@ -112,9 +119,13 @@ struct ldpc_server_s {
     std::vector<int32_t> code_n;
     int32_t max_group_frames = 0, max_queue = 0;
     // device arena and its pinned host mirror (same offsets)
-    float *d_llr = nullptr, *d_post = nullptr, *h_llr = nullptr, *h_post = nullptr;
-    uint8_t *d_bits = nullptr, *h_bits = nullptr;
-    int32_t *d_iters = nullptr, *h_iters = nullptr;
+    // device arena of LLRs; pinned host memory for staged LLRs and results,
+    // by its host (h_) and device (dh_) addresses; all share element offsets
+    int cus = 0;
+    float *d_llr = nullptr;
+    float *h_llr = nullptr, *h_post = nullptr, *dh_llr = nullptr, *dh_post = nullptr;
+    uint8_t *h_bits = nullptr, *dh_bits = nullptr;
+    int32_t *h_iters = nullptr, *dh_iters = nullptr;
     RangeAlloc elems, frames;
     std::vector<Slot> slots;
 
@@ -132,18 +143,21 @@ struct ldpc_server_s {
     int64_t group_frames_sum = 0;
 
     void run();
-    bool reap();
-    bool admit();
+    bool reap(std::unique_lock<std::mutex> &lk);
+    bool admit(std::unique_lock<std::mutex> &lk);
     void free_all();
 };
 
-bool ldpc_server_s::reap()
+bool ldpc_server_s::reap(std::unique_lock<std::mutex> &lk)
 {
     bool any = false;
     for (Slot &s : slots) {
+        // slots belong to the scheduler thread: their events are queried and
+        // their results copied out without holding the lock, so submitters
+        // are never held up by a large group's copies
         if (!s.busy || hipEventQuery(s.done) != hipSuccess)
             continue;
-        const int64_t t = now_ns();
+        lk.unlock();
         for (Request *r : s.reqs) {
             const int64_t n = code_n[r->code_id];
             const int64_t e = s.elem_begin + r->elem_off;
@@ -151,12 +165,16 @@ bool ldpc_server_s::reap()
             std::memcpy(r->iters, h_iters + s.frame_begin + r->frame_off, sizeof(int32_t) * r->frames);
             if (r->post)
                 std::memcpy(r->post, h_post + e, sizeof(float) * static_cast<size_t>(r->frames * n));
+        }
+        const int64_t t = now_ns();
+        lk.lock();
+        for (Request *r : s.reqs) {
             r->done_ns = t;
             r->state = kDone;
             lat_ms.push_back(static_cast<double>(t - r->arrival_ns) * 1e-6);
             st.completed += 1;
             st.frames_completed += r->frames;
-            st.bits_completed += r->frames * n;
+            st.bits_completed += r->frames * code_n[r->code_id];
         }
         s.reqs.clear();
         elems.release(s.elem_begin, s.elem_len);
@@ -169,7 +187,7 @@ bool ldpc_server_s::reap()
     return any;
 }
 
-bool ldpc_server_s::admit()
+bool ldpc_server_s::admit(std::unique_lock<std::mutex> &lk)
 {
     bool any = false;
     for (Slot &s : slots) {
@@ -186,12 +204,12 @@ bool ldpc_server_s::admit()
         // ... that the arena can hold right now
         int64_t eb = -1, fb = -1;
         while (k > 0) {
-            eb = elems.alloc(e);
+            eb = elems.alloc(align4(e));
             if (eb >= 0) {
                 fb = frames.alloc(f);
                 if (fb >= 0)
                     break;
-                elems.release(eb, e);
+                elems.release(eb, align4(e));
                 eb = -1;
             }
             --k;
@@ -203,10 +221,14 @@ bool ldpc_server_s::admit()
         s.reqs.assign(queue.begin(), queue.begin() + static_cast<long>(k));
         queue.erase(queue.begin(), queue.begin() + static_cast<long>(k));
         s.elem_begin = eb;
-        s.elem_len = e;
+        s.elem_len = align4(e);
         s.frame_begin = fb;
         s.frame_len = f;
         s.want_post = false;
+        for (Request *r : s.reqs)
+            r->state = kInFlight;  // from here on cancel() refuses these requests
+        // staging copies and launches run without the lock
+        lk.unlock();
         std::vector<ldpc_job> jobs;
         jobs.reserve(k);
         int64_t eo = 0, fo = 0;
@@ -214,7 +236,6 @@ bool ldpc_server_s::admit()
             const int64_t n = code_n[r->code_id];
             r->elem_off = eo;
             r->frame_off = fo;
-            r->state = kInFlight;
             std::memcpy(h_llr + eb + eo, r->llr, sizeof(float) * static_cast<size_t>(r->frames * n));
             ldpc_job j{};
             j.code = codes[r->code_id];
@@ -222,42 +243,45 @@ bool ldpc_server_s::admit()
             j.max_iter = r->max_iter;
             j.flags = r->flags;
             j.llr = d_llr + eb + eo;
-            j.bits = d_bits + eb + eo;
-            j.iters = d_iters + fb + fo;
-            j.posterior = r->post ? d_post + eb + eo : nullptr;
+            j.bits = dh_bits + eb + eo;
+            j.iters = dh_iters + fb + fo;
+            j.posterior = r->post ? dh_post + eb + eo : nullptr;
             s.want_post |= r->post != nullptr;
             jobs.push_back(j);
             eo += r->frames * n;
             fo += r->frames;
         }
-        (void)hipMemcpyAsync(d_llr + eb, h_llr + eb, sizeof(float) * static_cast<size_t>(e), hipMemcpyHostToDevice,
-                             s.stream);
-        const ldpc_status rc = ldpc_decode_batch(jobs.data(), static_cast<int32_t>(jobs.size()), LDPC_F32, s.ws,
-                                                 s.ws_bytes, s.stream);
+        // The copy kernel moves the staged LLRs into the device arena (the
+        // decode kernel reads them every iteration); the decode kernel writes
+        // bits, iteration counts and posteriors straight into pinned host
+        // memory (each once).  The runtime's copy calls are not used here:
+        // they have been seen to block the calling thread for milliseconds.
+        ldpc_status rc = ldpc::launch_copy16(d_llr + eb, dh_llr + eb, sizeof(float) * static_cast<size_t>(align4(e)), cus,
+                                       s.stream);
+        if (rc == LDPC_OK)
+            rc = ldpc_decode_batch(jobs.data(), static_cast<int32_t>(jobs.size()), LDPC_F32, s.ws, s.ws_bytes,
+                                   s.stream);
         if (rc != LDPC_OK) {
             // the group could not be launched: its requests complete with iteration count -1
             (void)hipStreamSynchronize(s.stream);
-            const int64_t t = now_ns();
-            for (Request *r : s.reqs) {
+            for (Request *r : s.reqs)
                 std::fill(r->iters, r->iters + r->frames, -1);
+            const int64_t t = now_ns();
+            lk.lock();
+            for (Request *r : s.reqs) {
                 r->done_ns = t;
                 r->state = kDone;
                 st.failed += 1;
             }
             s.reqs.clear();
-            elems.release(eb, e);
+            elems.release(eb, align4(e));
             frames.release(fb, f);
             cv_done.notify_all();
             any = true;
             continue;
         }
-        (void)hipMemcpyAsync(h_bits + eb, d_bits + eb, static_cast<size_t>(e), hipMemcpyDeviceToHost, s.stream);
-        (void)hipMemcpyAsync(h_iters + fb, d_iters + fb, sizeof(int32_t) * static_cast<size_t>(f),
-                             hipMemcpyDeviceToHost, s.stream);
-        if (s.want_post)
-            (void)hipMemcpyAsync(h_post + eb, d_post + eb, sizeof(float) * static_cast<size_t>(e),
-                                 hipMemcpyDeviceToHost, s.stream);
         (void)hipEventRecord(s.done, s.stream);
+        lk.lock();
         s.busy = true;
         st.launches += 1;
         group_frames_sum += f;
@@ -271,8 +295,8 @@ void ldpc_server_s::run()
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
-        reap();
-        admit();
+        reap(lk);
+        admit(lk);
         const bool busy = std::any_of(slots.begin(), slots.end(), [](const Slot &s) { return s.busy; });
         if (stop && queue.empty() && !busy)
             break;
@@ -335,36 +359,47 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_serve
     }
     sv->max_group_frames = cfg->max_group_frames;
     sv->max_queue = cfg->max_queue;
-    // arena: per element 4 (LLR) + 1 (bit) + 4 (posterior) bytes; per frame 4 (iteration count)
-    const int64_t elems_cap = static_cast<int64_t>(cfg->mem_budget_bytes / 10);
+    // Budget per element: 4 bytes of device LLR + 9 of pinned host memory
+    // (staged LLR, bit, posterior), rounded as 10; per frame 4 (iteration count).
+    const int64_t elems_cap = static_cast<int64_t>(cfg->mem_budget_bytes / 10) & ~int64_t(3);
     const int64_t frames_cap = elems_cap / nmin + 1;
-    const size_t bytes = static_cast<size_t>(elems_cap) * 9 + static_cast<size_t>(frames_cap) * 4 + 1024;
-    void *d = nullptr, *h = nullptr;
-    if (elems_cap < 1 || hipMalloc(&d, bytes) != hipSuccess) {
+    const size_t llr_bytes = align_up(static_cast<size_t>(elems_cap) * 4, 256);
+    const size_t host_bytes = 2 * llr_bytes + align_up(static_cast<size_t>(frames_cap) * 4, 256) +
+                              static_cast<size_t>(elems_cap);
+    void *d = nullptr, *h = nullptr, *dh = nullptr;
+    if (elems_cap < 4) {
         delete sv;
-        return LDPC_ENOMEM;
+        return LDPC_EINVAL;
     }
-    if (hipHostMalloc(&h, bytes, hipHostMallocDefault) != hipSuccess) {
-        (void)hipFree(d);
-        delete sv;
-        return LDPC_ENOMEM;
-    }
-    auto carve = [&](void *base, float *&llr, float *&post, uint8_t *&bits, int32_t *&it) {
-        char *p = static_cast<char *>(base);
-        llr = reinterpret_cast<float *>(p);
-        post = reinterpret_cast<float *>(p + align_up(static_cast<size_t>(elems_cap) * 4, 256));
-        it = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(post) + align_up(static_cast<size_t>(elems_cap) * 4, 256));
-        bits = reinterpret_cast<uint8_t *>(reinterpret_cast<char *>(it) + align_up(static_cast<size_t>(frames_cap) * 4, 256));
-    };
-    carve(d, sv->d_llr, sv->d_post, sv->d_bits, sv->d_iters);
-    carve(h, sv->h_llr, sv->h_post, sv->h_bits, sv->h_iters);
-    if (reinterpret_cast<char *>(sv->d_bits) + elems_cap > static_cast<char *>(d) + bytes) {
-        // the 256-byte alignment padding exceeded the slack; never expected with 1024 bytes of slack
-        (void)hipFree(d);
-        (void)hipHostFree(h);
+    if (hipDeviceGetAttribute(&sv->cus, hipDeviceAttributeMultiprocessorCount, sv->device) != hipSuccess) {
         delete sv;
         return LDPC_EDEVICE;
     }
+    if (hipMalloc(&d, llr_bytes) != hipSuccess) {
+        delete sv;
+        return LDPC_ENOMEM;
+    }
+    if (hipHostMalloc(&h, host_bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(d);
+        delete sv;
+        return LDPC_ENOMEM;
+    }
+    sv->d_llr = static_cast<float *>(d);
+    sv->h_llr = static_cast<float *>(h);  // owns the pinned block (freed through it)
+    if (hipHostGetDevicePointer(&dh, h, 0) != hipSuccess) {
+        sv->free_all();
+        delete sv;
+        return LDPC_EDEVICE;
+    }
+    auto carve = [&](void *base, float *&llr, float *&post, int32_t *&it, uint8_t *&bits) {
+        char *p = static_cast<char *>(base);
+        llr = reinterpret_cast<float *>(p);
+        post = reinterpret_cast<float *>(p + llr_bytes);
+        it = reinterpret_cast<int32_t *>(p + 2 * llr_bytes);
+        bits = reinterpret_cast<uint8_t *>(p + 2 * llr_bytes + align_up(static_cast<size_t>(frames_cap) * 4, 256));
+    };
+    carve(h, sv->h_llr, sv->h_post, sv->h_iters, sv->h_bits);
+    carve(dh, sv->dh_llr, sv->dh_post, sv->dh_iters, sv->dh_bits);
     sv->elems = RangeAlloc(elems_cap);
     sv->frames = RangeAlloc(frames_cap);
     sv->slots.resize(cfg->max_inflight);
@@ -377,6 +412,45 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_serve
             sv->free_all();
             delete sv;
             return LDPC_ENOMEM;
+        }
+    }
+    // Warm-up: on every slot's stream, the staging copy at a small and a large
+    // size, then one frame of every code for one iteration.  The runtime sets
+    // up the hardware queue behind a stream and loads kernel variants on first
+    // use, which takes milliseconds each time; paying for it here keeps it out
+    // of the first requests' latency.  A code's degree bucket is the largest
+    // one any group holding it can need, so these launches touch every kernel
+    // variant later groups use.
+    const size_t big = std::min<size_t>(static_cast<size_t>(elems_cap) * sizeof(float), size_t(4) << 20);
+    std::memset(sv->h_llr, 0, big);  // the copies below leave zero LLRs for the warm-up decodes
+    for (Slot &s : sv->slots) {
+        for (const size_t len : {std::min<size_t>(big, 4096), big})
+            if (launch_copy16(sv->d_llr, sv->dh_llr, len, sv->cus, s.stream) != LDPC_OK) {
+                sv->free_all();
+                delete sv;
+                return LDPC_EDEVICE;
+            }
+        for (size_t i = 0; i < sv->codes.size(); ++i) {
+            if (sv->code_n[i] > std::min<int64_t>(elems_cap, 1 << 16))
+                continue;  // requests for such a code are refused at submit anyway
+            ldpc_job j{};
+            j.code = sv->codes[i];
+            j.frames = 1;
+            j.max_iter = 1;
+            j.llr = sv->d_llr;
+            j.bits = sv->dh_bits;
+            j.iters = sv->dh_iters;
+            const ldpc_status rc = ldpc_decode_batch(&j, 1, LDPC_F32, s.ws, s.ws_bytes, s.stream);
+            if (rc != LDPC_OK) {
+                sv->free_all();
+                delete sv;
+                return rc;
+            }
+        }
+        if (hipStreamSynchronize(s.stream) != hipSuccess) {
+            sv->free_all();
+            delete sv;
+            return LDPC_EDEVICE;
         }
     }
     sv->sched = std::thread([sv] { sv->run(); });
@@ -392,7 +466,7 @@ extern "C" ldpc_status ldpc_server_submit(ldpc_server sv, int32_t code_id, int32
         max_iter < 0 || (flags & ~LDPC_EARLY_STOP) != 0 || !llr || !bits || !iters)
         return LDPC_EINVAL;
     const int64_t need = static_cast<int64_t>(frames) * sv->code_n[code_id];
-    if (frames > sv->max_group_frames || need > sv->elems.capacity())
+    if (frames > sv->max_group_frames || align4(need) > sv->elems.capacity())
         return LDPC_EINVAL;
     auto *r = new (std::nothrow) Request();
     if (!r)
