@@ -1,4 +1,5 @@
-"""Oracle: a plain, slow FP64 flooding sum-product decoder on the CPU.
+"""Oracle: plain, slow FP64 sum-product decoders on the CPU (flooding and
+layered schedules).
 
 TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
 benchmark's CPU-baseline leg may import this package; the decoder library and
@@ -6,7 +7,9 @@ its Python binding never do.  It shares no code with the GPU path.
 
 ``decode`` follows Section II of arxiv 1812.06545 (Tanner graph of H, two-phase
 message passing, Algorithm 1's loop order) with the sum-product check rule of
-Section I; see spa_oracle.c for the exact definition and readings.
+Section I; see spa_oracle.c for the exact definition and readings.  With
+``schedule="layered"`` it runs the serial check-node schedule of the paper's
+layered algorithm (Algorithm 2, Section II) instead; see layered_oracle.c.
 """
 from __future__ import annotations
 
@@ -28,11 +31,14 @@ def _load(path: str = LIB):
         if not os.path.exists(path):
             compile_oracle(out=path) if path == LIB else None
         lib = ctypes.CDLL(path)
-        f = lib.oracle_spa_decode
         P = ctypes.c_void_p
-        f.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int,
-                      ctypes.c_double, P, P, P, P, P, ctypes.c_int]
-        f.restype = ctypes.c_int
+        for name in ("oracle_spa_decode", "oracle_spa_layered_decode"):
+            if not hasattr(lib, name):  # a test build may hold only one of the two
+                continue
+            f = getattr(lib, name)
+            f.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_double, P, P, P, P, P, ctypes.c_int]
+            f.restype = ctypes.c_int
         if path != LIB:
             return lib
         _lib = lib
@@ -44,8 +50,12 @@ def _ptr(a):
 
 
 def decode(code, llr, max_iter: int, early_stop: bool, r_max: float = R_MAX, nthreads: int = 1,
-           want_trace: bool = True, lib=None):
+           want_trace: bool = True, lib=None, schedule: str = "flooding"):
     """Decode frames ``llr`` (F, n) -> dict(bits, iters, posterior, cond, min_abs).
+
+    ``schedule`` is "flooding" (all checks, then all variables, per iteration)
+    or "layered" (check rows one at a time in ascending order, each updating
+    its variables at once; one iteration = one pass over the rows).
 
     float32 input is upcast to float64 unchanged, so both sides see the same
     values.  ``lib`` lets the tests point at a deliberately broken build.
@@ -61,9 +71,11 @@ def decode(code, llr, max_iter: int, early_stop: bool, r_max: float = R_MAX, nth
     cond = np.zeros((F, n), dtype=np.float64)
     mabs = np.zeros((F, max_iter + 1), dtype=np.float64) if want_trace else None
     L = lib if lib is not None else _load()
-    st = L.oracle_spa_decode(code.m, n, _ptr(rp), _ptr(ci), F, _ptr(llr), int(max_iter),
-                             int(bool(early_stop)), float(r_max), _ptr(bits), _ptr(iters), _ptr(post),
-                             _ptr(cond), _ptr(mabs), int(nthreads))
+    if schedule not in ("flooding", "layered"):
+        raise ValueError(f"unknown schedule {schedule!r}")
+    fn = L.oracle_spa_decode if schedule == "flooding" else L.oracle_spa_layered_decode
+    st = fn(code.m, n, _ptr(rp), _ptr(ci), F, _ptr(llr), int(max_iter), int(bool(early_stop)), float(r_max),
+            _ptr(bits), _ptr(iters), _ptr(post), _ptr(cond), _ptr(mabs), int(nthreads))
     if st != 0:
-        raise ValueError(f"oracle_spa_decode failed with status {st}")
+        raise ValueError(f"oracle ({schedule}) failed with status {st}")
     return {"bits": bits, "iters": iters, "posterior": post, "cond": cond, "min_abs": mabs}

@@ -19,6 +19,10 @@ Pins (each names what it fixes):
                     is clamped to R_MAX = 20, so the posterior is 30 + 20.
   noiseless         L = A(1-2c) for a codeword c: iters 0, bits c, posterior = L.
   zero_iter         max_iter = 0: bits = [L < 0] (+0 and -0 give 0), posterior = L.
+  zero_posterior    a three-bit parity check with two zero LLRs: every message
+                    into those two bits is 2 atanh(0) = 0 exactly, so their
+                    posteriors are exactly +0 or -0 after any iteration and the
+                    decision [L < 0] gives 0 (the tie reading).
   symmetry          decoding L*(1-2c) gives bits xor c, the same iters and the
                     same |posterior| (tanh/atanh odd, signs exact).
   zero_syndrome     early stop: every frame that stopped before max_iter has
@@ -127,6 +131,15 @@ def zero_iter(dec):
     assert list(out["bits"][0, :4]) == [0, 0, 1, 0]
 
 
+def zero_posterior(dec):
+    code = codes.single_parity_check(3)
+    llr = np.array([[1.5, 0.0, 0.0], [-1.5, -0.0, -0.0], [0.7, 0.0, -0.0]])
+    for T in (1, 2):
+        out = dec(code, llr, T, False)
+        assert (out["posterior"][:, 1:] == 0.0).all(), out["posterior"]
+        assert (out["bits"][:, 1:] == 0).all(), f"a zero posterior decided as 1 after {T} iterations"
+
+
 def symmetry(dec):
     code, cw, llr = _gallager_noisy(12, 33, ebn0=1.5)
     base = dec(code, llr, 20, True)
@@ -176,5 +189,5 @@ def stop_iteration(dec):
     assert (es["iters"] == first).all()
 
 
-ALL = [spc_map, repetition_sum, tree_map, clamp, noiseless, zero_iter, symmetry, zero_syndrome,
+ALL = [spc_map, repetition_sum, tree_map, clamp, noiseless, zero_iter, zero_posterior, symmetry, zero_syndrome,
        prefix, fixed_iters, stop_iteration]
