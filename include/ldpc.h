@@ -19,6 +19,17 @@
  * iterations run (0 when the channel decision already is a codeword;
  * max_iter when the syndrome never clears or early stop is off).
  *
+ * With LDPC_LAYERED the plain path runs the layered schedule instead (Section
+ * II, Algorithm 2): r = 0 and L = L_ch initially; one iteration visits the
+ * check rows one at a time in ascending index order, and visiting row m sets
+ *   q_mn = L_n - r_mn ;  r_mn = the Loop 2 rule over q_m. ;  L_n = q_mn + r_mn
+ * for every n in N(m), so each row sees the updates of the rows before it.
+ * The hard decision, syndrome test and iteration count are as above, per pass
+ * over the rows.  Rows in a maximal run of consecutive rows that share no
+ * variable (a layer; a block-row of a QC code) run in parallel, which does
+ * not change the result.  To decode in another row order, permute the rows
+ * of H.
+ *
  * Conventions for every call:
  *   - Frame buffers are row-major [frames][n]: frame f, bit j at f*n + j.
  *   - "device" pointers are HIP device memory of the device the code handle
@@ -61,6 +72,7 @@ typedef enum {
 typedef enum { LDPC_F32 = 0, LDPC_F64 = 1 } ldpc_dtype;
 
 #define LDPC_EARLY_STOP 1u  /* flag: stop a frame at its first zero syndrome */
+#define LDPC_LAYERED 2u     /* flag: layered schedule (ldpc_decode, and batch jobs routed to it) */
 
 /* Clamp on check-to-variable messages (the paper gives none; 20 keeps the
  * FP64 tanh/atanh evaluation accurate). */
@@ -104,6 +116,13 @@ ldpc_status ldpc_code_from_qc(int32_t mb, int32_t nb, int32_t Z, const int32_t *
 /* Sizes of a code: m, n and the number of edges (ones of H).  Any output may be NULL. */
 ldpc_status ldpc_code_info(ldpc_code code, int32_t *m, int32_t *n, int64_t *edges);
 
+/* Layers of the layered schedule (Section II, Algorithm 2): the rows in
+ * ascending order, split into maximal runs in which no two rows share a
+ * variable; each layer is one parallel step.  Outputs the number of layers and
+ * the fewest and most rows in a layer (0, 0, 0 for a code without rows).  Any
+ * output may be NULL. */
+ldpc_status ldpc_code_layers(ldpc_code code, int32_t *nlayers, int32_t *min_rows, int32_t *max_rows);
+
 /* Release a code.  The caller must ensure no enqueued work still uses it.  NULL is ignored. */
 void ldpc_code_destroy(ldpc_code code);
 
@@ -117,11 +136,13 @@ ldpc_status ldpc_workspace_bytes(ldpc_code code, ldpc_dtype dtype, int32_t frame
 
 /*
  * Decode `frames` frames with per-iteration kernel launches (the plain
- * flooding path: one check-node and one variable-node kernel per iteration,
- * messages streamed through device memory).
+ * path, messages streamed through device memory): flooding runs one
+ * check-node and one variable-node kernel per iteration; layered
+ * (LDPC_LAYERED) one kernel per layer, plus a syndrome kernel per iteration
+ * with early stop.
  *   dtype      LDPC_F32 (llr/posterior are float) or LDPC_F64 (double)
  *   max_iter   >= 0; 0 returns the hard decision of llr, iters 0, posterior = llr
- *   flags      0 or LDPC_EARLY_STOP
+ *   flags      0, LDPC_EARLY_STOP, LDPC_LAYERED or both
  *   llr        device, [frames][n] of dtype, read only
  *   bits       device, [frames][n] uint8 0/1 (written)
  *   iters      device, [frames] int32 (written)
@@ -156,7 +177,8 @@ ldpc_status ldpc_batch_workspace_bytes(const ldpc_job *jobs, int32_t njobs, ldpc
  * frame held in LDS) run together in ONE persistent launch whose workgroups
  * pull (job, frame) items from a device-side queue; each workgroup runs every
  * iteration of its frame, with per-frame early stop.  Jobs whose code does
- * not fit run through the plain per-iteration kernels on the same stream.
+ * not fit, and jobs with LDPC_LAYERED, run through the plain per-iteration
+ * kernels on the same stream.
  * Each frame's result is identical to decoding that frame alone.
  * Errors as ldpc_decode; jobs with frames == 0 are skipped.
  */
@@ -223,7 +245,8 @@ ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_server *out);
 
 /*
  * Queue a request: `frames` frames of codes[code_id], LLRs llr[frames][n]
- * (host memory, float), decoded with max_iter / flags as in ldpc_decode.
+ * (host memory, float), decoded with max_iter / flags as in ldpc_decode
+ * (flags 0 or LDPC_EARLY_STOP: the server runs the flooding schedule only).
  * Outputs go to host memory bits[frames][n], iters[frames] and, if non-NULL,
  * posterior[frames][n]; every buffer must stay valid and untouched until the
  * request is done.  arrival_ns: the request's arrival time on the
@@ -294,7 +317,7 @@ ldpc_status ldpc_batch_fits_fused(ldpc_code code, ldpc_dtype dtype, size_t *lds_
  */
 typedef enum {
     LDPC_KERNEL_INGEST = 0,    /* caller layout -> frame-interleaved layout */
-    LDPC_KERNEL_CHECK = 1,     /* check-node update, one iteration */
+    LDPC_KERNEL_CHECK = 1,     /* check-node update: one iteration (flooding) or one layer (layered) */
     LDPC_KERNEL_VARIABLE = 2,  /* variable-node update + hard decision, one iteration */
     LDPC_KERNEL_OUTPUT = 3,    /* frame-interleaved -> caller layout */
     LDPC_KERNEL_FUSED = 4,     /* persistent frame-resident decoder (all iterations) */

@@ -24,6 +24,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ldpc.h")
 LDPC_OK, LDPC_EINVAL, LDPC_ENOMEM, LDPC_EDEVICE, LDPC_EBUSY, LDPC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 LDPC_F32, LDPC_F64 = 0, 1
 LDPC_EARLY_STOP = 1
+LDPC_LAYERED = 2
 LDPC_R_MAX = 20.0
 
 if not os.path.exists(LIB_PATH):
@@ -51,6 +52,7 @@ _sig("ldpc_status_str", ctypes.c_char_p, [ctypes.c_int])
 _sig("ldpc_code_from_csr", ctypes.c_int, [_I32, _I32, _P, _P, ctypes.POINTER(_P)])
 _sig("ldpc_code_from_qc", ctypes.c_int, [_I32, _I32, _I32, _P, ctypes.POINTER(_P)])
 _sig("ldpc_code_info", ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_int64)])
+_sig("ldpc_code_layers", ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)])
 _sig("ldpc_code_destroy", None, [_P])
 _sig("ldpc_workspace_bytes", ctypes.c_int, [_P, ctypes.c_int, _I32, _I32, ctypes.POINTER(ctypes.c_size_t)])
 _sig("ldpc_decode", ctypes.c_int, [_P, ctypes.c_int, _I32, _I32, ctypes.c_uint32, _P, _P, _P, _P, _P,
@@ -171,6 +173,14 @@ def ldpc_code_info(handle):
     m, n, e = _I32(), _I32(), ctypes.c_int64()
     _check(_lib.ldpc_code_info(_handle(handle), ctypes.byref(m), ctypes.byref(n), ctypes.byref(e)), "ldpc_code_info")
     return m.value, n.value, e.value
+
+
+def ldpc_code_layers(handle):
+    """(number of layers, fewest rows in a layer, most rows in a layer)."""
+    nl, lo, hi = _I32(), _I32(), _I32()
+    _check(_lib.ldpc_code_layers(_handle(handle), ctypes.byref(nl), ctypes.byref(lo), ctypes.byref(hi)),
+           "ldpc_code_layers")
+    return nl.value, lo.value, hi.value
 
 
 def ldpc_code_destroy(handle):
@@ -319,10 +329,15 @@ def _workspace(nbytes, device):
     return ws
 
 
+def _flags(early_stop: bool, layered: bool) -> int:
+    return (LDPC_EARLY_STOP if early_stop else 0) | (LDPC_LAYERED if layered else 0)
+
+
 def decode(code: Code, llr: torch.Tensor, max_iter: int, early_stop: bool = False, want_posterior: bool = True,
-           stream=None, workspace: torch.Tensor = None):
-    """Decode llr [frames, n] (float32 or float64, on the GPU).  Returns
-    (bits uint8 [frames, n], iters int32 [frames], posterior or None)."""
+           stream=None, workspace: torch.Tensor = None, layered: bool = False):
+    """Decode llr [frames, n] (float32 or float64, on the GPU), flooding or
+    (layered=True) layered schedule.  Returns (bits uint8 [frames, n], iters
+    int32 [frames], posterior or None)."""
     assert llr.is_cuda and llr.dim() == 2 and llr.shape[1] == code.n and llr.is_contiguous()
     frames = llr.shape[0]
     dev = llr.device
@@ -332,7 +347,7 @@ def decode(code: Code, llr: torch.Tensor, max_iter: int, early_stop: bool = Fals
     need = ldpc_workspace_bytes(code.handle, llr.dtype, frames, max_iter)
     if workspace is None or workspace.numel() < need:
         workspace = _workspace(need, dev)
-    flags = LDPC_EARLY_STOP if early_stop else 0
+    flags = _flags(early_stop, layered)
     _check(ldpc_decode(code.handle, llr.dtype, frames, max_iter, flags, llr, bits, iters, post, workspace,
                        workspace.numel(), stream), "ldpc_decode")
     return bits, iters, post
@@ -342,18 +357,18 @@ class Job:
     """One job of a batch, holding its output tensors."""
 
     def __init__(self, code: Code, llr: torch.Tensor, max_iter: int, early_stop: bool = False,
-                 want_posterior: bool = True):
+                 want_posterior: bool = True, layered: bool = False):
         assert llr.is_cuda and llr.dim() == 2 and llr.shape[1] == code.n and llr.is_contiguous()
         self.code, self.llr, self.max_iter, self.early_stop = code, llr, max_iter, early_stop
+        self.layered = layered
         dev = llr.device
         self.bits = torch.empty((llr.shape[0], code.n), dtype=torch.uint8, device=dev)
         self.iters = torch.empty(llr.shape[0], dtype=torch.int32, device=dev)
         self.posterior = torch.empty_like(llr) if want_posterior else None
 
     def c_struct(self) -> ldpc_job:
-        return ldpc_job(self.code.handle, self.llr.shape[0], self.max_iter,
-                        LDPC_EARLY_STOP if self.early_stop else 0, _ptr(self.llr), _ptr(self.bits),
-                        _ptr(self.iters), _ptr(self.posterior))
+        return ldpc_job(self.code.handle, self.llr.shape[0], self.max_iter, _flags(self.early_stop, self.layered),
+                        _ptr(self.llr), _ptr(self.bits), _ptr(self.iters), _ptr(self.posterior))
 
 
 class Plan:

@@ -109,7 +109,7 @@ void plan(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, std::vector<Group>
         if (jobs[i].frames == 0)
             continue;
         const FusedFit fit = fused_fit(jobs[i].code, dt, limit);
-        if (!fit.ok) {
+        if (!fit.ok || (jobs[i].flags & LDPC_LAYERED) != 0) {  // the fused kernel runs flooding only
             plain.push_back(i);
             continue;
         }
@@ -157,7 +157,7 @@ ldpc_status validate_jobs(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype)
     for (int32_t i = 0; i < njobs; ++i) {
         const ldpc_job &j = jobs[i];
         if (!j.code || j.frames < 0 || j.frames > LDPC_MAX_FRAMES || j.max_iter < 0 ||
-            (j.flags & ~LDPC_EARLY_STOP) != 0)
+            (j.flags & ~(LDPC_EARLY_STOP | LDPC_LAYERED)) != 0)
             return LDPC_EINVAL;
         if (j.frames > 0 && (!j.llr || !j.bits || !j.iters))
             return LDPC_EINVAL;

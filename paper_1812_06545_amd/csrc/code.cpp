@@ -97,9 +97,41 @@ void slot_tables(const HostLayout &h, const std::vector<int32_t> &row_blk_start,
         col_gmax[j / 64] = std::max(col_gmax[j / 64], h.col_ptr[j + 1] - h.col_ptr[j]);
 }
 
+// Greedy layers over the rows in ascending order: a row opens a new layer
+// when it shares a variable with a row of the current one.  Visiting the
+// layers in order, each as a parallel step, equals visiting the rows one at a
+// time in order.
+void layer_tables(const HostLayout &h, std::vector<int32_t> &layer_ptr, std::vector<int32_t> &layer_dmax)
+{
+    std::vector<int32_t> mark(h.n, -1);
+    int32_t cur = 0;
+    layer_ptr.assign(1, 0);
+    layer_dmax.assign(1, 0);
+    for (int32_t i = 0; i < h.m; ++i) {
+        const int32_t b = h.row_ptr[i], e = h.row_ptr[i + 1];
+        bool clash = false;
+        for (int32_t k = b; k < e && !clash; ++k)
+            clash = mark[h.col_idx[k]] == cur;
+        if (clash) {
+            ++cur;
+            layer_ptr.push_back(i);
+            layer_dmax.push_back(0);
+        }
+        for (int32_t k = b; k < e; ++k)
+            mark[h.col_idx[k]] = cur;
+        layer_dmax.back() = std::max(layer_dmax.back(), e - b);
+    }
+    layer_ptr.push_back(h.m);
+    if (h.m == 0) {
+        layer_ptr.assign(1, 0);
+        layer_dmax.clear();
+    }
+}
+
 ldpc_status upload(const HostLayout &h, const std::vector<int32_t> *qc_tab, const std::vector<int32_t> &row_blk_start,
                    int32_t Z, ldpc_code_s *c)
 {
+    layer_tables(h, c->layer_ptr, c->layer_dmax);
     std::vector<int32_t> brow_order, row_gmax, col_gmax;
     slot_tables(h, row_blk_start, Z, brow_order, row_gmax, col_gmax);
     const size_t words = h.row_ptr.size() + h.col_idx.size() + h.col_ptr.size() + h.col_edge.size() +
@@ -273,6 +305,26 @@ extern "C" ldpc_status ldpc_code_info(ldpc_code code, int32_t *m, int32_t *n, in
         *n = code->n;
     if (edges)
         *edges = code->E;
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_code_layers(ldpc_code code, int32_t *nlayers, int32_t *min_rows, int32_t *max_rows)
+{
+    if (!code)
+        return LDPC_EINVAL;
+    const int32_t L = static_cast<int32_t>(code->layer_dmax.size());
+    int32_t lo = L ? INT32_MAX : 0, hi = 0;
+    for (int32_t l = 0; l < L; ++l) {
+        const int32_t r = code->layer_ptr[l + 1] - code->layer_ptr[l];
+        lo = std::min(lo, r);
+        hi = std::max(hi, r);
+    }
+    if (nlayers)
+        *nlayers = L;
+    if (min_rows)
+        *min_rows = lo;
+    if (max_rows)
+        *max_rows = hi;
     return LDPC_OK;
 }
 

@@ -29,9 +29,16 @@
 // gathers anyway, and marks unsatisfied frames.  The variable kernel of
 // iteration t then retires a frame whose syndrome was zero (iters = t-1) and
 // leaves its posterior untouched.  No host synchronisation is needed.
+//
+// The layered schedule (LDPC_LAYERED) runs on the same arrays: r per edge,
+// starting at 0, and L, starting at Lch.  An iteration is one launch per layer
+// (layered_kernels.h); with early stop a syndrome kernel and a retire kernel
+// test x^(t-1) = [L < 0] before pass t, since inside a pass the rows see
+// different posteriors and cannot test one decision together.
 #include <algorithm>
 
 #include "flood_kernels.h"
+#include "layered_kernels.h"
 
 namespace ldpc {
 namespace {
@@ -117,6 +124,46 @@ __global__ __launch_bounds__(256) void k_output(const typename A::T *__restrict_
     }
 }
 
+// Syndrome of the hard decision [L < 0]: one wavefront = one row x 64
+// frames; an unsatisfied row marks its frames in `unsat`.
+template <class A>
+__global__ __launch_bounds__(256) void k_syndrome(const int32_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ col_idx, int32_t m, int32_t n,
+                                                  int32_t groups, int32_t nchunk, const typename A::T *__restrict__ L,
+                                                  const int32_t *__restrict__ done, int32_t *__restrict__ unsat)
+{
+    using T = typename A::T;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    int group, chunk;
+    map_block(static_cast<int>(blockIdx.x), groups, nchunk, group, chunk);
+    const int row = group * kWaves + wave;
+    if (row >= m)
+        return;
+    const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
+    if (done[f] >= 0)
+        return;
+    const uint32_t off = static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(T));
+    const int32_t e0 = row_ptr[row];
+    const int32_t d = __builtin_amdgcn_readfirstlane(row_ptr[row + 1] - e0);
+    const T *Lc = L + static_cast<int64_t>(chunk) * n * kChunk;
+    uint32_t parity = 0;
+#pragma unroll 8
+    for (int32_t k = 0; k < d; ++k)
+        parity ^= static_cast<uint32_t>(ld_lane(Lc + col_idx[e0 + k] * kChunk, off) < T(0));
+    if (parity)
+        unsat[f] = 1;
+}
+
+// A frame still running whose decision x^t satisfies every row stops at t.
+__global__ __launch_bounds__(256) void k_retire(int64_t Fp, int32_t *__restrict__ done,
+                                                const int32_t *__restrict__ unsat, int32_t t)
+{
+    const int64_t f = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f < Fp && done[f] < 0 && unsat[f] == 0)
+        done[f] = t;
+}
+
 struct Carve {
     char *p;
     template <class U>
@@ -176,6 +223,38 @@ void launch_check<ArithF64>(const ldpc_code_s *c, bool first, bool es, dim3 grid
         launch_check_bucket<ArithF64, 64, false>(a, first, es, grid, s);
 }
 
+// Smallest layer-kernel bucket that holds every row of layer l.
+template <class A>
+void launch_layer(int32_t dmax, bool first, bool es, dim3 grid, hipStream_t s, const LayerArgs<A> &a);
+
+template <>
+void launch_layer<ArithF32>(int32_t d, bool first, bool es, dim3 grid, hipStream_t s, const LayerArgs<ArithF32> &a)
+{
+    if (d <= 8)
+        launch_layer_bucket<ArithF32, 8, true>(a, first, es, grid, s);
+    else if (d <= 16)
+        launch_layer_bucket<ArithF32, 16, true>(a, first, es, grid, s);
+    else if (d <= 24)
+        launch_layer_bucket<ArithF32, 24, true>(a, first, es, grid, s);
+    else if (d <= 32)
+        launch_layer_bucket<ArithF32, 32, true>(a, first, es, grid, s);
+    else
+        launch_layer_bucket<ArithF32, 64, false>(a, first, es, grid, s);
+}
+
+template <>
+void launch_layer<ArithF64>(int32_t d, bool first, bool es, dim3 grid, hipStream_t s, const LayerArgs<ArithF64> &a)
+{
+    if (d <= 8)
+        launch_layer_bucket<ArithF64, 8, false>(a, first, es, grid, s);
+    else if (d <= 16)
+        launch_layer_bucket<ArithF64, 16, false>(a, first, es, grid, s);
+    else if (d <= 32)
+        launch_layer_bucket<ArithF64, 32, false>(a, first, es, grid, s);
+    else
+        launch_layer_bucket<ArithF64, 64, false>(a, first, es, grid, s);
+}
+
 template <class A>
 ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, uint32_t flags, const void *llr_v,
                         uint8_t *bits, int32_t *iters, void *post_v, void *ws, hipStream_t s)
@@ -209,7 +288,29 @@ ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, 
     const int32_t rgroups = (c->m + kWaves - 1) / kWaves;
     const int32_t cgroups = (c->n + kWaves - 1) / kWaves;
     const dim3 rgrid(static_cast<unsigned>(rgroups) * nchunk), cgrid(static_cast<unsigned>(cgroups) * nchunk);
-    for (int32_t t = 1; t <= max_iter; ++t) {
+    const bool layered = (flags & LDPC_LAYERED) != 0;
+    for (int32_t t = 1; t <= max_iter && layered; ++t) {
+        const bool first = (t == 1);
+        if (es && c->m > 0) {
+            int32_t *unsat_t = unsat + static_cast<int64_t>(t - 1) * Fp;
+            {
+                ProfScope ps(LDPC_KERNEL_OTHER, s);
+                hipLaunchKernelGGL((k_syndrome<A>), rgrid, dim3(256), 0, s, c->row_ptr, c->col_idx, c->m, c->n,
+                                   rgroups, nchunk, L, done, unsat_t);
+            }
+            ProfScope ps(LDPC_KERNEL_OTHER, s);
+            hipLaunchKernelGGL(k_retire, dim3(static_cast<unsigned>((Fp + 255) / 256)), dim3(256), 0, s, Fp, done,
+                               unsat_t, t - 1);
+        }
+        for (size_t l = 0; l + 1 < c->layer_ptr.size(); ++l) {
+            const int32_t row0 = c->layer_ptr[l], rows = c->layer_ptr[l + 1] - row0;
+            const int32_t groups = (rows + kWaves - 1) / kWaves;
+            const LayerArgs<A> la{c->row_ptr, c->col_idx, row0, rows, c->n, c->E, groups, nchunk, R, L, done};
+            ProfScope ps(LDPC_KERNEL_CHECK, s);
+            launch_layer<A>(c->layer_dmax[l], first, es, dim3(static_cast<unsigned>(groups) * nchunk), s, la);
+        }
+    }
+    for (int32_t t = 1; t <= max_iter && !layered; ++t) {
         const bool first = (t == 1);
         int32_t *unsat_t = unsat + static_cast<int64_t>(t - 1) * Fp;
         {
@@ -266,8 +367,8 @@ extern "C" ldpc_status ldpc_decode(ldpc_code code, ldpc_dtype dtype, int32_t fra
                                    uint32_t flags, const void *llr, uint8_t *bits, int32_t *iters, void *posterior,
                                    void *workspace, size_t workspace_bytes, void *stream)
 {
-    if (!code || frames < 0 || frames > LDPC_MAX_FRAMES || max_iter < 0 || (flags & ~LDPC_EARLY_STOP) != 0 ||
-        (dtype != LDPC_F32 && dtype != LDPC_F64))
+    if (!code || frames < 0 || frames > LDPC_MAX_FRAMES || max_iter < 0 ||
+        (flags & ~(LDPC_EARLY_STOP | LDPC_LAYERED)) != 0 || (dtype != LDPC_F32 && dtype != LDPC_F64))
         return LDPC_EINVAL;
     if (frames == 0)
         return LDPC_OK;

@@ -1,0 +1,6 @@
+// Layer kernels, FP32, rows of degree <= 8 (exact-degree bodies).
+#include "layered_kernels.h"
+
+namespace ldpc {
+LDPC_DEFINE_LAYER_BUCKET(ArithF32, 8, true)
+}  // namespace ldpc

@@ -1,0 +1,191 @@
+// Device code of the layered schedule on the streaming layout (the same
+// chunked frame-interleaved arrays as the flooding path: r per edge and the
+// posterior L per variable, [chunk][edge or variable][64 frames]).
+//
+// Layered decoding (arxiv 1812.06545, Section II, Algorithm 2): check rows are
+// visited one at a time in ascending order and each row's new messages update
+// the posteriors of its variables at once:
+//     q_mn = L_n - r_mn ;  r_mn = check rule over q_m. ;  L_n = q_mn + r_mn.
+// Consecutive rows that share no variable commute, so a maximal run of them
+// (a layer: a block-row of a QC code) is one launch, one wavefront per row and
+// 64 frames; within a layer every L_n is read and written by one row only.
+// The check rule is the flooding path's (same two-half exclusive sums, same
+// phi evaluation), so a row gives the same messages for the same q.
+#pragma once
+
+#include "flood_kernels.h"
+
+namespace ldpc {
+namespace layered {
+
+using flood::kWaves;
+using flood::ld_lane;
+using flood::map_block;
+using flood::st_lane;
+
+// One check row of compile-time degree D: all loads first, then the forward
+// and backward sweeps; each new message and its posterior are stored as soon
+// as they are formed.  FIRST (the first pass) reads no old messages: they
+// are all 0.
+template <class A, int D, bool FIRST>
+__device__ __forceinline__ void layer_row(const int32_t *__restrict__ cols, typename A::T *__restrict__ L,
+                                          typename A::T *__restrict__ Rrow, uint32_t off)
+{
+    using T = typename A::T;
+    constexpr int H = (D + 1) / 2;
+    T q[D], rv[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        q[k] = ld_lane(L + cols[k] * kChunk, off);
+        rv[k] = FIRST ? T(0) : ld_lane(Rrow + k * kChunk, off);
+    }
+    T a[D], p[D];
+    T acc0 = T(0), acc1 = T(0);
+    uint32_t sign = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (!FIRST)
+            q[k] = q[k] - rv[k];
+        check_forward<A>(q[k], a[k], p[k], k < H ? acc0 : acc1, sign);
+    }
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int k = D - 1; k >= 0; --k) {
+        const T r = k < H ? check_backward<A>(a[k], p[k], s0, acc1, sign) : check_backward<A>(a[k], p[k], s1, acc0, sign);
+        st_lane(Rrow + k * kChunk, off, r);
+        st_lane(L + cols[k] * kChunk, off, q[k] + r);
+    }
+}
+
+// The same row for a run-time degree d <= DMAX (guarded loops; FP64 and
+// degrees above the largest exact bucket).
+template <class A, int DMAX, bool FIRST>
+__device__ __forceinline__ void layer_row_guarded(const int32_t *__restrict__ cols, int d,
+                                                  typename A::T *__restrict__ L, typename A::T *__restrict__ Rrow,
+                                                  uint32_t off)
+{
+    using T = typename A::T;
+    const int h = (d + 1) / 2;
+    T q[DMAX], rv[DMAX];
+#pragma unroll
+    for (int k = 0; k < DMAX; ++k) {
+        if (k < d) {
+            q[k] = ld_lane(L + cols[k] * kChunk, off);
+            rv[k] = FIRST ? T(0) : ld_lane(Rrow + k * kChunk, off);
+        }
+    }
+    T a[DMAX], p[DMAX];
+    T acc0 = T(0), acc1 = T(0);
+    uint32_t sign = 0;
+#pragma unroll
+    for (int k = 0; k < DMAX; ++k) {
+        if (k < d) {
+            if (!FIRST)
+                q[k] = q[k] - rv[k];
+            if (k < h)
+                check_forward<A>(q[k], a[k], p[k], acc0, sign);
+            else
+                check_forward<A>(q[k], a[k], p[k], acc1, sign);
+        }
+    }
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int k = DMAX - 1; k >= 0; --k) {
+        if (k < d) {
+            const T r = k < h ? check_backward<A>(a[k], p[k], s0, acc1, sign)
+                              : check_backward<A>(a[k], p[k], s1, acc0, sign);
+            st_lane(Rrow + k * kChunk, off, r);
+            st_lane(L + cols[k] * kChunk, off, q[k] + r);
+        }
+    }
+}
+
+// Exact-degree dispatch for d in [D, DB] (straight-line body per degree).
+template <class A, int D, int DB, bool FIRST>
+__device__ __forceinline__ void layer_row_exact(int d, const int32_t *__restrict__ cols, typename A::T *__restrict__ L,
+                                                typename A::T *__restrict__ Rrow, uint32_t off)
+{
+    if constexpr (D < DB) {
+        if (d == D)
+            layer_row<A, D, FIRST>(cols, L, Rrow, off);
+        else
+            layer_row_exact<A, D + 1, DB, FIRST>(d, cols, L, Rrow, off);
+    } else {
+        layer_row<A, DB, FIRST>(cols, L, Rrow, off);
+    }
+}
+
+// One layer: rows [row0, row0 + rows), one wavefront = one row x 64 frames.
+// Frames already stopped (done >= 0) are left untouched.
+template <class A, int DB, bool EXACT, bool FIRST, bool ES>
+__global__ __launch_bounds__(256) void k_layer(const int32_t *__restrict__ row_ptr,
+                                               const int32_t *__restrict__ col_idx, int32_t row0, int32_t rows,
+                                               int32_t n, int64_t E, int32_t groups, int32_t nchunk,
+                                               typename A::T *__restrict__ R, typename A::T *__restrict__ L,
+                                               const int32_t *__restrict__ done)
+{
+    using T = typename A::T;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    int group, chunk;
+    map_block(static_cast<int>(blockIdx.x), groups, nchunk, group, chunk);
+    const int slot = group * kWaves + wave;
+    if (slot >= rows)
+        return;
+    const int row = row0 + slot;
+    const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
+    if (ES && done[f] >= 0)
+        return;
+    const uint32_t off = static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(T));
+    const int32_t e0 = row_ptr[row];
+    const int32_t d = __builtin_amdgcn_readfirstlane(row_ptr[row + 1] - e0);
+    T *Rrow = R + (static_cast<int64_t>(chunk) * E + e0) * kChunk;
+    T *Lc = L + static_cast<int64_t>(chunk) * n * kChunk;
+    if (d > 0) {
+        if constexpr (EXACT)
+            layer_row_exact<A, 1, DB, FIRST>(d, col_idx + e0, Lc, Rrow, off);
+        else
+            layer_row_guarded<A, DB, FIRST>(col_idx + e0, d, Lc, Rrow, off);
+    }
+}
+
+}  // namespace layered
+
+// Arguments of one layer launch.
+template <class A>
+struct LayerArgs {
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    int32_t row0, rows, n;
+    int64_t E;
+    int32_t groups, nchunk;
+    typename A::T *R;
+    typename A::T *L;
+    const int32_t *done;
+};
+
+// Launcher of the layer kernel for rows of degree <= DB; each (dtype, bucket)
+// is defined in its own translation unit.
+template <class A, int DB, bool EXACT>
+void launch_layer_bucket(const LayerArgs<A> &a, bool first, bool es, dim3 grid, hipStream_t s);
+
+#define LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, F_, E_)                                                              \
+    hipLaunchKernelGGL((layered::k_layer<A_, DB_, EX_, F_, E_>), grid, dim3(256), 0, s, a.row_ptr, a.col_idx,  \
+                       a.row0, a.rows, a.n, a.E, a.groups, a.nchunk, a.R, a.L, a.done)
+
+#define LDPC_DEFINE_LAYER_BUCKET(A_, DB_, EX_)                                                                  \
+    template <>                                                                                                 \
+    void launch_layer_bucket<A_, DB_, EX_>(const LayerArgs<A_> &a, bool first, bool es, dim3 grid,              \
+                                           hipStream_t s)                                                       \
+    {                                                                                                           \
+        if (first && es)                                                                                        \
+            LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, true, true);                                                    \
+        else if (first)                                                                                         \
+            LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, true, false);                                                   \
+        else if (es)                                                                                            \
+            LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, false, true);                                                   \
+        else                                                                                                    \
+            LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, false, false);                                                  \
+    }
+
+}  // namespace ldpc

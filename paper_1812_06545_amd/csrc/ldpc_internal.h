@@ -56,6 +56,10 @@ struct ldpc_code_s {
     const int32_t *brow_order = nullptr;
     const int32_t *row_gmax = nullptr;
     const int32_t *col_gmax = nullptr;
+    // Layers of the layered schedule (host): maximal runs of consecutive rows,
+    // in ascending order, in which no two rows share a variable.  Layer l is
+    // rows [layer_ptr[l], layer_ptr[l+1]); layer_dmax[l] its largest degree.
+    std::vector<int32_t> layer_ptr, layer_dmax;
 };
 
 namespace ldpc {

@@ -22,10 +22,19 @@ import numpy as np
 
 GATE = 1e-3
 TOL = {np.float32: 1e-4, np.float64: 1e-6}
+# Layered schedule: every row sees the rows before it within a pass, which
+# amplifies rounding differences faster than flooding does.  Injecting
+# relative noise of 6e-8 (FP32 rounding) into every q, r and L update of the
+# FP64 layered oracle moves posteriors of the 3.5 dB qc1944 parity input by
+# about 2e-4 after 10 passes (test_oracle_layered pins this spread between
+# 1e-4 and half the bar), so the FP32 bar is 1e-3 there; at five passes or
+# fewer the flooding bar of 1e-4 still holds and is tested.
+TOL_LAYERED = {np.float32: 1e-3, np.float64: 1e-6}
 
 
-def compare(ref, bits, iters, post, dtype, where=""):
-    tol = TOL[np.dtype(dtype).type]
+def compare(ref, bits, iters, post, dtype, where="", tol=None):
+    if tol is None:
+        tol = TOL[np.dtype(dtype).type]
     bits = np.asarray(bits)
     iters = np.asarray(iters)
     Lr = ref["posterior"]
