@@ -155,6 +155,7 @@ def main():
     if args.path == "plain" and not args.no_extra:
         other_path = batch_path_run(h, llrs, bits, iters, post, F, n, T, args.steps)
     extra = None if args.no_extra else extra_workloads()
+    layered = None if args.no_extra else layered_workloads(args.steps)
 
     copy = copy_probe(args.copy_probe_mb) if args.copy_probe_mb > 0 else None
     if copy and achieved:
@@ -187,6 +188,7 @@ def main():
         "kernels": kernels,
         "batch_path": other_path,
         "other_workloads": extra,
+        "layered": layered,
         "copy_probe": copy,
         "serving": serving,
         "cpu_baseline": cpu,
@@ -277,6 +279,86 @@ def extra_workloads():
     out["stair64800"] = {"plain_ms": ms, "plain_mbps": 256 * st.code.n / (ms * 1e-3) / 1e6,
                          "mean_iters": float(res["out"][1].float().mean().item())}
     return out
+
+
+def layered_workloads(steps):
+    """The layered schedule (LDPC_LAYERED), timed with HIP events:
+    - qc1944 at 2.0 dB, 4096 frames, 10 passes fixed, on the plain path (one
+      launch per layer; the layer kernel's achieved bandwidth: per edge and
+      frame a layer reads r and L and writes both, 16 bytes, 12 on the first
+      pass, which reads no r) and on the fused frame-resident kernel;
+    - time to decode with early stop (max 20) against flooding on the same
+      inputs, both paths: qc1944 code at 3.5 dB and gallager504 (FP64) at 2.0 dB.
+    Fused-kernel timings here follow ldpc_autotune_batch for their shape."""
+    import torch
+
+    import paper_1812_06545_amd as L
+    from workloads import configs
+    out = {}
+    b = configs.qc1944(2.0)
+    F, n, E = b.llr.shape[0], b.code.n, b.code.edges
+    h = L.Code.from_workload(b.code)
+    llr = torch.from_numpy(b.llr).cuda()
+    ws = torch.empty(L.ldpc_workspace_bytes(h, torch.float32, F, 10), dtype=torch.uint8, device="cuda")
+    L.decode(h, llr, 10, layered=True, workspace=ws)
+    torch.cuda.synchronize()
+    L.ldpc_profile_collect()
+    L.ldpc_profile_enable(True)
+    ms = _time_ms(lambda: L.decode(h, llr, 10, layered=True, workspace=ws), steps)
+    L.ldpc_profile_enable(False)
+    prof = L.ldpc_profile_collect()
+    kms, kcount = prof["check"]
+    fp = (F + 63) // 64 * 64
+    layers = L.ldpc_code_layers(h)[0]
+    per_decode = fp * (12 * E + 9 * 16 * E)
+    achieved = per_decode * (kcount / (10 * layers)) / (kms * 1e-3) / 1e9 if kcount else None
+    fused_ms = _batch_ms(L, [(h, llr, 10, False, True)], torch.float32, steps, tune=True)
+    out["qc1944_2dB_10passes"] = {
+        "plain_ms": ms, "plain_mbps": F * n / (ms * 1e-3) / 1e6, "layers": layers,
+        "layer_kernel": {"launches": kcount, "avg_us": kms * 1e3 / max(kcount, 1),
+                         "bytes_per_decode": per_decode, "achieved_gbs": achieved,
+                         "frac_of_peak": achieved / HBM_PEAK_GBS if achieved else None},
+        "batch_ms": fused_ms, "batch_mbps": F * n / (fused_ms * 1e-3) / 1e6}
+
+    def converge(batch, dtype, T, reps):
+        hh = L.Code.from_workload(batch.code)
+        x = torch.from_numpy(batch.llr).cuda()
+        wsz = torch.empty(L.ldpc_workspace_bytes(hh, dtype, x.shape[0], T), dtype=torch.uint8, device="cuda")
+        bits = x.shape[0] * batch.code.n
+        res = {}
+        for name, lay in (("flooding", False), ("layered", True)):
+            got = {}
+
+            def run():
+                got["o"] = L.decode(hh, x, T, early_stop=True, layered=lay, workspace=wsz)
+            t = _time_ms(run, reps)
+            tb = _batch_ms(L, [(hh, x, T, True, lay)], dtype, reps, tune=True)
+            it = got["o"][1].float()
+            res[name] = {"plain_ms": t, "plain_mbps": bits / (t * 1e-3) / 1e6, "batch_ms": tb,
+                         "batch_mbps": bits / (tb * 1e-3) / 1e6, "mean_iters": float(it.mean().item()),
+                         "unconverged": float((it == T).float().mean().item())}
+        return res
+    out["qc1944_3.5dB_early_stop20"] = converge(configs.qc1944(3.5), torch.float32, 20, 5)
+    out["gallager504_f64_early_stop20"] = converge(configs.gallager504(), torch.float64, 20, 5)
+    return out
+
+
+def _batch_ms(L, items, dtype, reps, tune=False):
+    """HIP-event time of one ldpc_decode_batch over items (handle, llr tensor,
+    max_iter, early_stop, layered); with tune, after ldpc_autotune_batch has
+    picked the workgroup size for this batch shape."""
+    import torch
+    jobs = [L.Job(hh, x, T, early_stop=es, layered=lay) for hh, x, T, es, lay in items]
+    if tune:
+        L.autotune_batch(jobs)
+    cj = [j.c_struct() for j in jobs]
+    nb = L.ldpc_batch_workspace_bytes(cj, dtype)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+
+    def run():
+        if L.ldpc_decode_batch(cj, dtype, ws, nb) != 0:
+            raise RuntimeError("ldpc_decode_batch failed")
+    return _time_ms(run, reps)
 
 
 def copy_probe(mb):

@@ -19,7 +19,7 @@
  * iterations run (0 when the channel decision already is a codeword;
  * max_iter when the syndrome never clears or early stop is off).
  *
- * With LDPC_LAYERED the plain path runs the layered schedule instead (Section
+ * With LDPC_LAYERED the decoder runs the layered schedule instead (Section
  * II, Algorithm 2): r = 0 and L = L_ch initially; one iteration visits the
  * check rows one at a time in ascending index order, and visiting row m sets
  *   q_mn = L_n - r_mn ;  r_mn = the Loop 2 rule over q_m. ;  L_n = q_mn + r_mn
@@ -72,7 +72,7 @@ typedef enum {
 typedef enum { LDPC_F32 = 0, LDPC_F64 = 1 } ldpc_dtype;
 
 #define LDPC_EARLY_STOP 1u  /* flag: stop a frame at its first zero syndrome */
-#define LDPC_LAYERED 2u     /* flag: layered schedule (ldpc_decode, and batch jobs routed to it) */
+#define LDPC_LAYERED 2u     /* flag: layered schedule (ldpc_decode and ldpc_decode_batch jobs) */
 
 /* Clamp on check-to-variable messages (the paper gives none; 20 keeps the
  * FP64 tanh/atanh evaluation accurate). */
@@ -176,9 +176,11 @@ ldpc_status ldpc_batch_workspace_bytes(const ldpc_job *jobs, int32_t njobs, ldpc
  * Jobs whose code fits the fused frame-resident kernel (messages of one
  * frame held in LDS) run together in ONE persistent launch whose workgroups
  * pull (job, frame) items from a device-side queue; each workgroup runs every
- * iteration of its frame, with per-frame early stop.  Jobs whose code does
- * not fit, and jobs with LDPC_LAYERED, run through the plain per-iteration
- * kernels on the same stream.
+ * iteration of its frame, with per-frame early stop, on the schedule its job's
+ * flags select (flooding or LDPC_LAYERED: block-rows, or the code's layers,
+ * one at a time with a workgroup barrier between them).  Jobs whose code
+ * does not fit run through the plain per-iteration kernels on the same
+ * stream.
  * Each frame's result is identical to decoding that frame alone.
  * Errors as ldpc_decode; jobs with frames == 0 are skipped.
  */
@@ -286,8 +288,9 @@ ldpc_status ldpc_batch_set_threads(int32_t threads);
 /*
  * Autotuner of the batch path.  Decodes the given batch (its output buffers
  * are overwritten, inputs untouched) once per candidate workgroup size of
- * the fused kernel (128, 256, 384, 512), checks that every candidate gives
- * bit-identical outputs, times each (HIP events, 3 runs after a warm-up) and
+ * the fused kernel (64, 128, 192, 256, 384, 512), checks that every
+ * candidate gives bit-identical outputs, times each (HIP events, 3 runs
+ * after a warm-up) and
  * records the fastest for this batch shape (codes, frame counts rounded up
  * to a power of two, iteration caps, flags, dtype); later ldpc_decode_batch
  * calls of the same shape use it.  Blocks until done.  *best_threads and

@@ -109,7 +109,7 @@ void plan(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, std::vector<Group>
         if (jobs[i].frames == 0)
             continue;
         const FusedFit fit = fused_fit(jobs[i].code, dt, limit);
-        if (!fit.ok || (jobs[i].flags & LDPC_LAYERED) != 0) {  // the fused kernel runs flooding only
+        if (!fit.ok) {
             plain.push_back(i);
             continue;
         }
@@ -195,6 +195,8 @@ fused::Code code_entry(const ldpc_code_s *c)
     e.brow_order = c->brow_order;
     e.row_gmax = c->row_gmax;
     e.col_gmax = c->col_gmax;
+    e.layer_ptr = c->d_layer_ptr;
+    e.nlayers = static_cast<int32_t>(c->layer_dmax.size());
     return e;
 }
 
@@ -358,7 +360,7 @@ extern "C" ldpc_status ldpc_autotune_batch(const ldpc_job *jobs, int32_t njobs, 
     if (st != LDPC_OK)
         return st;
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    static const int kCandidates[] = {128, 256, 384, 512};
+    static const int kCandidates[] = {64, 128, 192, 256, 384, 512};
     const std::string key = shape_key(jobs, njobs, dtype);
     std::vector<char> ref, cur;
     int best = 0;

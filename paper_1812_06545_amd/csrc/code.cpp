@@ -135,7 +135,8 @@ ldpc_status upload(const HostLayout &h, const std::vector<int32_t> *qc_tab, cons
     std::vector<int32_t> brow_order, row_gmax, col_gmax;
     slot_tables(h, row_blk_start, Z, brow_order, row_gmax, col_gmax);
     const size_t words = h.row_ptr.size() + h.col_idx.size() + h.col_ptr.size() + h.col_edge.size() +
-                         (qc_tab ? qc_tab->size() : 0) + brow_order.size() + row_gmax.size() + col_gmax.size();
+                         (qc_tab ? qc_tab->size() : 0) + brow_order.size() + row_gmax.size() + col_gmax.size() +
+                         c->layer_ptr.size();
     std::vector<int32_t> blob;
     blob.reserve(words);
     auto put = [&](const std::vector<int32_t> &v) {
@@ -145,7 +146,7 @@ ldpc_status upload(const HostLayout &h, const std::vector<int32_t> *qc_tab, cons
     };
     const size_t o_rp = put(h.row_ptr), o_ci = put(h.col_idx), o_cp = put(h.col_ptr), o_ce = put(h.col_edge);
     const size_t o_qc = qc_tab ? put(*qc_tab) : 0;
-    const size_t o_bo = put(brow_order), o_rg = put(row_gmax), o_cg = put(col_gmax);
+    const size_t o_bo = put(brow_order), o_rg = put(row_gmax), o_cg = put(col_gmax), o_lp = put(c->layer_ptr);
     void *d = nullptr;
     if (hipMalloc(&d, std::max<size_t>(blob.size(), 1) * sizeof(int32_t)) != hipSuccess)
         return LDPC_ENOMEM;
@@ -163,6 +164,7 @@ ldpc_status upload(const HostLayout &h, const std::vector<int32_t> *qc_tab, cons
     c->brow_order = brow_order.empty() ? nullptr : base + o_bo;
     c->row_gmax = base + o_rg;
     c->col_gmax = base + o_cg;
+    c->d_layer_ptr = base + o_lp;
     c->m = h.m;
     c->n = h.n;
     c->E = static_cast<int64_t>(h.col_idx.size());

@@ -1,5 +1,6 @@
 // Fused frame-resident decoder: one workgroup decodes one frame through all
-// of its iterations with the frame's messages held in LDS.
+// of its iterations with the frame's messages held in LDS, on the flooding
+// schedule or (jobs with LDPC_LAYERED) the layered one.
 //
 // Schedule (arxiv 1812.06545, Section II; Algorithm 1): the same flooding
 // two-phase iteration as the plain path, but the global barrier between the
@@ -40,6 +41,8 @@ struct Code {
     int32_t m, n, Z, nblocks;
     int32_t mb, nb, qc, words;  // words: QC table words (0 for CSR codes)
     const int32_t *tab, *row_ptr, *col_idx, *col_ptr, *col_edge, *brow_order, *row_gmax, *col_gmax;
+    const int32_t *layer_ptr;  // layered schedule, CSR codes: layer l = rows [layer_ptr[l], layer_ptr[l+1])
+    int32_t nlayers;
 };
 
 struct Job {
@@ -166,6 +169,72 @@ __device__ __forceinline__ void fused_row_dispatch(int hwave, const Row &row, in
             fused_row_dispatch<A, D + 1, DB>(hwave, row, k0, dh, sR, sL, first, parity);
     } else {
         fused_half_row<A, DB>(row, k0, dh, sR, sL, first, parity);
+    }
+}
+
+// One half of a check row under the layered schedule (Section II, Algorithm
+// 2): as fused_half_row, and the row's new messages update its variables'
+// posteriors at once, L_n = q_mn + r_mn.  No other row of the layer touches
+// these edges or variables, so the forward pass parks q_k in the variable's
+// own L slot and a_k in the edge's r slot; the backward pass reads both back
+// and writes r_new and q_k + r_new.
+template <class A, int D, class Row>
+__device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh, typename A::T *__restrict__ sR,
+                                                 typename A::T *__restrict__ sL, bool first)
+{
+    using T = typename A::T;
+    T p[D];
+    T acc = T(0);
+    uint32_t sign = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const bool real = j < dh;
+        const int32_t ri = real ? row.ridx(k0 + j) : 0;
+        const int32_t ci = real ? row.col(k0 + j) : 0;
+        const T l = sL[ci];
+        const T rr = first ? T(0) : sR[ri];
+        const T lv = real ? l : T(__builtin_huge_val());
+        const T q = first ? lv : lv - (real ? rr : T(0));
+        T a_k;
+        check_forward<A>(q, a_k, p[j], acc, sign);
+        if (real) {
+            sR[ri] = a_k;
+            sL[ci] = q;
+        }
+    }
+    const T s_other = pair_swap(acc);
+    const uint32_t sign_total = sign ^ pair_swap(sign);
+    T s = T(0);
+#pragma unroll
+    for (int j = D - 1; j >= 0; --j) {
+        const bool real = j < dh;
+        const int32_t ri = real ? row.ridx(k0 + j) : 0;
+        const T a_k = real ? sR[ri] : T(0);
+        const T r = check_backward<A>(a_k, p[j], s, s_other, sign_total);
+        if (real) {
+            const int32_t ci = row.col(k0 + j);
+            const T q = sL[ci];
+            sR[ri] = r;
+            sL[ci] = q + r;
+        }
+    }
+}
+
+template <class A, int D, int DB, class Row>
+__device__ __forceinline__ void layered_row_dispatch(int hwave, const Row &row, int k0, int dh,
+                                                     typename A::T *__restrict__ sR, typename A::T *__restrict__ sL,
+                                                     bool first)
+{
+    constexpr bool exact = std::is_same<A, ArithF32>::value && std::is_same<Row, RowQC>::value;
+    if constexpr (!exact) {
+        layered_half_row<A, DB>(row, k0, dh, sR, sL, first);
+    } else if constexpr (D < DB) {
+        if (hwave == D)
+            layered_half_row<A, D>(row, k0, dh, sR, sL, first);
+        else
+            layered_row_dispatch<A, D + 1, DB>(hwave, row, k0, dh, sR, sL, first);
+    } else {
+        layered_half_row<A, DB>(row, k0, dh, sR, sL, first);
     }
 }
 
@@ -297,6 +366,110 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
         job.iters[f] = it;
 }
 
+// One frame under the layered schedule: check rows are visited in ascending
+// order, one layer at a time (QC codes: one block-row, Z rows; other codes:
+// the code's layer table), the rows of a layer in parallel with two lanes
+// each and a workgroup barrier between layers.  With early stop the syndrome
+// of [L < 0] is tested before the first pass and after every pass but the
+// last.  Each row's arithmetic is the plain layered path's, bit for bit.
+template <class A, int DB>
+__device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &job, int64_t f,
+                                                     typename A::T *__restrict__ sR, typename A::T *__restrict__ sL,
+                                                     const int32_t *__restrict__ sTab)
+{
+    using T = typename A::T;
+    const int tid = static_cast<int>(threadIdx.x), NT = static_cast<int>(blockDim.x);
+    const int lane = tid & 63, half = lane >> 5, wave = tid >> 6, nwaves = NT >> 6;
+    const int32_t m = c.m, n = c.n, Z = c.Z;
+    const T *llr = static_cast<const T *>(job.llr) + f * n;
+    const int32_t *rbs = sTab;
+    const int32_t *pack = sTab + c.words;
+
+    for (int j = tid; j < n; j += NT)
+        sL[j] = llr[j] * T(A::kIn);
+    __syncthreads();
+
+    // 1 if some row is unsatisfied by [sL < 0]: each lane takes one half of a
+    // row, partner lanes combine their parities.
+    auto unsatisfied = [&]() -> int {
+        uint32_t bad = 0;
+        for (int rb = wave * 32; rb < m; rb += nwaves * 32) {
+            const int s = rb + (lane & 31);
+            uint32_t par = 0;
+            if (s < m) {
+                if (c.qc) {
+                    const int32_t si = s / Z;
+                    const int32_t b0 = rbs[si], d = rbs[si + 1] - b0, h = (d + 1) >> 1;
+                    const RowQC row{b0, s - si * Z, Z, pack};
+                    const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
+                    for (int32_t k = 0; k < dh; ++k)
+                        par ^= static_cast<uint32_t>(sL[row.col(k0 + k)] < T(0));
+                } else {
+                    const int32_t e0 = c.row_ptr[s], d = c.row_ptr[s + 1] - e0, h = (d + 1) >> 1;
+                    const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
+                    for (int32_t k = 0; k < dh; ++k)
+                        par ^= static_cast<uint32_t>(sL[c.col_idx[e0 + k0 + k]] < T(0));
+                }
+            }
+            bad |= par ^ pair_swap(par);
+        }
+        return __syncthreads_or(static_cast<int>(bad));
+    };
+
+    const bool es = (job.flags & LDPC_EARLY_STOP) != 0;
+    int32_t it = job.max_iter;
+    if (es && !unsatisfied()) {
+        it = 0;
+    } else {
+        for (int32_t t = 1; t <= job.max_iter; ++t) {
+            const bool first = (t == 1);
+            if (c.qc) {
+                for (int32_t i = 0; i < c.mb; ++i) {
+                    const int32_t b0 = rbs[i], d = rbs[i + 1] - b0, h = (d + 1) >> 1;
+                    for (int rb = wave * 32; rb < Z; rb += nwaves * 32) {
+                        const int r = rb + (lane & 31);
+                        if (d == 0 || r >= Z)
+                            continue;
+                        const RowQC row{b0, r, Z, pack};
+                        layered_row_dispatch<A, 1, DB / 2>(h, row, half ? h : 0, half ? d - h : h, sR, sL, first);
+                    }
+                    __syncthreads();
+                }
+            } else {
+                for (int32_t l = 0; l < c.nlayers; ++l) {
+                    const int32_t row0 = c.layer_ptr[l], rows = c.layer_ptr[l + 1] - row0;
+                    for (int rb = wave * 32; rb < rows; rb += nwaves * 32) {
+                        const int slot = rb + (lane & 31);
+                        if (slot >= rows)
+                            continue;
+                        const int32_t e0 = c.row_ptr[row0 + slot], d = c.row_ptr[row0 + slot + 1] - e0;
+                        if (d == 0)
+                            continue;
+                        const int32_t h = (d + 1) >> 1;
+                        const RowCSR row{e0, c.col_idx};
+                        layered_row_dispatch<A, 1, DB / 2>(h, row, half ? h : 0, half ? d - h : h, sR, sL, first);
+                    }
+                    __syncthreads();
+                }
+            }
+            if (es && t < job.max_iter && !unsatisfied()) {
+                it = t;
+                break;
+            }
+        }
+    }
+    uint8_t *bits = job.bits + f * n;
+    T *post = job.post ? static_cast<T *>(job.post) + f * n : nullptr;
+    for (int j = tid; j < n; j += NT) {
+        const T v = sL[j];
+        bits[j] = static_cast<uint8_t>(v < T(0));
+        if (post)
+            post[j] = it == 0 ? llr[j] : v * T(A::kOut);
+    }
+    if (tid == 0)
+        job.iters[f] = it;
+}
+
 // Persistent batch kernel: workgroups take (job, frame) items from *counter.
 // 512-thread workgroups, two per CU for n = 1944 (LDS bound): FP32 bodies are
 // held to 128 VGPRs so both fit (4 waves per SIMD); FP64 bodies get 256.
@@ -341,7 +514,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWaves
             }
             __syncthreads();
         }
-        decode_frame<A, DB>(c, job, item - job.item_begin, sR, sL, sTab);
+        if (job.flags & LDPC_LAYERED)
+            decode_frame_layered<A, DB>(c, job, item - job.item_begin, sR, sL, sTab);
+        else
+            decode_frame<A, DB>(c, job, item - job.item_begin, sR, sL, sTab);
         __syncthreads();
     }
 }

@@ -60,6 +60,7 @@ struct ldpc_code_s {
     // in ascending order, in which no two rows share a variable.  Layer l is
     // rows [layer_ptr[l], layer_ptr[l+1]); layer_dmax[l] its largest degree.
     std::vector<int32_t> layer_ptr, layer_dmax;
+    const int32_t *d_layer_ptr = nullptr;  // device copy of layer_ptr
 };
 
 namespace ldpc {

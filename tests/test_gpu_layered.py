@@ -144,24 +144,68 @@ def test_prefix_bitwise(L):
         assert np.array_equal(x[sel], y[sel])
 
 
-def test_batch_routes_layered_jobs(L):
-    """Layered jobs in a batch run on the plain path: identical to decoding alone."""
+def _batch_vs_plain(L, items, dtype_name):
+    """items: (handle, llr ndarray, T, es, layered).  One ldpc_decode_batch
+    call (fused frame-resident kernel) must equal ldpc_decode of each job
+    alone, bit for bit."""
     import torch
-    mix = configs.qc_mix(total=600)
-    sel = [1, 6, 10]
-    handles = [L.Code.from_workload(mix[i].code) for i in sel]
-    jobs = []
-    for h, i, lay in zip(handles, sel, (True, False, True)):
-        jobs.append(L.Job(h, torch.from_numpy(mix[i].llr).cuda(), 10, early_stop=True, layered=lay))
+    jobs = [L.Job(h, torch.from_numpy(x).cuda(), T, early_stop=es, layered=lay) for h, x, T, es, lay in items]
     L.decode_batch(jobs)
     torch.cuda.synchronize()
-    for h, i, j in zip(handles, sel, jobs):
-        bits, iters, post = L.decode(h, torch.from_numpy(mix[i].llr).cuda(), 10, early_stop=True,
-                                     layered=j.layered)
+    for (h, x, T, es, lay), j in zip(items, jobs):
+        bits, iters, post = L.decode(h, torch.from_numpy(x).cuda(), T, early_stop=es, layered=lay)
         torch.cuda.synchronize()
-        assert np.array_equal(j.bits.cpu().numpy(), bits.cpu().numpy())
-        assert np.array_equal(j.iters.cpu().numpy(), iters.cpu().numpy())
-        assert np.array_equal(j.posterior.cpu().numpy(), post.cpu().numpy())
+        where = f"{dtype_name} layered={lay} n={x.shape[1]} frames={x.shape[0]}"
+        assert np.array_equal(j.bits.cpu().numpy(), bits.cpu().numpy()), where
+        assert np.array_equal(j.iters.cpu().numpy(), iters.cpu().numpy()), where
+        assert np.array_equal(j.posterior.cpu().numpy(), post.cpu().numpy()), where
+    return jobs
+
+
+def test_batch_layered_matches_plain(L):
+    """Layered and flooding jobs of several codes in one fused launch equal the
+    plain path's results for each job alone."""
+    mix = configs.qc_mix(total=900)
+    sel = [1, 6, 10, 11]
+    items = [(L.Code.from_workload(mix[i].code), mix[i].llr, 10, True, lay)
+             for i, lay in zip(sel, (True, False, True, True))]
+    b = configs.qc1944(2.5, frames=70)
+    items.append((L.Code.from_workload(b.code), b.llr, 10, False, True))
+    jobs = _batch_vs_plain(L, items, "FP32")
+    # the fused layered results against the oracle too
+    for (h, x, T, es, lay), j, idx in zip(items, jobs, sel + [None]):
+        if not lay:
+            continue
+        code = mix[idx].code if idx is not None else b.code
+        ref = oracle.decode(code, x, T, es, nthreads=8, schedule="layered")
+        compare(ref, j.bits.cpu().numpy(), j.iters.cpu().numpy(), j.posterior.cpu().numpy(), np.float32,
+                f"fused layered {code.name}", tol=TOL_LAYERED[np.float32])
+
+
+def test_batch_layered_f64_csr(L):
+    """FP64 layered in the fused kernel on a code without circulant structure
+    (the code's layer table drives the layers)."""
+    g = configs.gallager504(frames=300)
+    h = L.Code.from_workload(g.code)
+    jobs = _batch_vs_plain(L, [(h, g.llr, 20, True, True)], "FP64")
+    ref = oracle.decode(g.code, g.llr, 20, True, nthreads=8, schedule="layered")
+    compare(ref, jobs[0].bits.cpu().numpy(), jobs[0].iters.cpu().numpy(), jobs[0].posterior.cpu().numpy(),
+            np.float64, "fused layered gallager504 FP64", tol=TOL_LAYERED[np.float64])
+
+
+def test_batch_layered_small_codes(L):
+    """Degenerate shapes through the fused layered kernel: one check, a chain
+    (one row per layer), cycles, a tree, a variable in no check and a check on
+    one variable; 0 and 1 iterations; all equal to the plain path."""
+    rng = np.random.default_rng(5)
+    items = []
+    for code in (codes.single_parity_check(8), codes.repetition_chain(9), codes.hamming74(),
+                 codes.random_tree_code(12, 5), codes.Code.from_row_lists(3, 6, [[0, 1, 2], [3], [2, 4]])):
+        h = L.Code.from_workload(code)
+        llr = rng.normal(0.4, 1.5, size=(67, code.n)).astype(np.float32)
+        for T, es in ((0, False), (1, False), (7, True)):
+            items.append((h, llr, T, es, True))
+    _batch_vs_plain(L, items, "FP32 small codes")
 
 
 def test_server_refuses_layered(L):
