@@ -138,7 +138,7 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
     }
     const T s_other = pair_swap(acc);
     const uint32_t sign_total = sign ^ pair_swap(sign);
-    parity ^= par ^ pair_swap(par);
+    parity |= par ^ pair_swap(par);  // a lane may hold several rows: any unsatisfied row counts
     T s = T(0);
 #pragma unroll
     for (int j = D - 1; j >= 0; --j) {
