@@ -26,8 +26,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--path", choices=("plain", "batch"), default="plain",
-                    help="plain: per-iteration kernels (ldpc_decode); batch: ldpc_decode_batch")
+    ap.add_argument("--path", choices=("plain", "batch", "layered"), default="plain",
+                    help="plain: per-iteration kernels (ldpc_decode); batch: ldpc_decode_batch; "
+                         "layered: ldpc_decode with the layered schedule (10 passes instead of iterations)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
@@ -90,12 +91,13 @@ def main():
     iters = torch.empty(F, dtype=torch.int32, device=dev)
     post = torch.empty((F, n), dtype=torch.float32, device=dev)
 
-    if args.path == "plain":
+    if args.path in ("plain", "layered"):
         ws_bytes = L.ldpc_workspace_bytes(h.handle, torch.float32, F, T)
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        flags = L.LDPC_LAYERED if args.path == "layered" else 0
 
         def step(i):
-            st = L.ldpc_decode(h.handle, torch.float32, F, T, 0, llrs[i % 4], bits, iters, post, ws, ws_bytes)
+            st = L.ldpc_decode(h.handle, torch.float32, F, T, flags, llrs[i % 4], bits, iters, post, ws, ws_bytes)
             if st != 0:
                 raise L.LdpcError(st, "ldpc_decode")
     else:
@@ -135,6 +137,13 @@ def main():
         per_frame_first = 4 * E + 4 * n
         per_frame_later = 8 * E + 4 * n
         bytes_per_launch = F * (per_frame_first + (T - 1) * per_frame_later) / T
+    elif args.path == "layered":
+        # one launch per layer; per edge and frame a layer reads r and L and
+        # writes both (16 bytes; 12 on the first pass, which reads no r);
+        # averaged over the launches of one decode
+        name, (kms, kcount) = "layer", prof["check"]
+        layers = L.ldpc_code_layers(h)[0]
+        bytes_per_launch = F * (12 * E + (T - 1) * 16 * E) / (T * layers)
     else:
         name, (kms, kcount) = "fused", prof["fused"]
         # frame-resident kernel: reads the channel LLRs and writes bits and the
@@ -181,7 +190,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "qc1944: seeded QC code, 12x24 base, Z=81, n=1944, rate 1/2, 4096 frames/step, "
-                               "10 iterations (no early stop), BPSK/AWGN at 1.0/1.5/2.0/2.5 dB",
+                               "10 iterations (no early stop), BPSK/AWGN at 1.0/1.5/2.0/2.5 dB"
+                               + (" (layered schedule: 10 passes)" if args.path == "layered" else ""),
                    "path": args.path, "frames": F, "n": n, "edges": E, "iterations": T},
         "info_mbps": k_info * F * args.steps / elapsed / 1e6,
         "roofline": roofline,
