@@ -48,8 +48,8 @@ HBM_PEAK_GBS = 8000.0
 # kernel), averaged over one first-iteration and nine later launches.  Valid
 # only for the kernel source they were taken on (hash below); otherwise null.
 CHECK_TRAFFIC = {
-    "bytes_per_launch": 555.2e6,
-    "source_sha256": "7457961639e8122b8b43542a3d4a4d065f337f229b38c491f74e1a2b08627287",
+    "bytes_per_launch": 543.4e6,
+    "source_sha256": "a34a2df9c42de5b471a76143a417b1c290ff56e3ed7df1f09356d6c182fbb648",
     "profile": "profiles/hbm_traffic_check_qc1944.md",
 }
 CHECK_SOURCES = ("flood_kernels.h", "spa_math.h", "check_f32_d24.hip")

@@ -41,6 +41,18 @@ __device__ __forceinline__ void st_lane(T *base, uint32_t lane_off, T v)
 {
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + lane_off) = v;
 }
+// Non-temporal forms for the streamed messages r (read once and written once
+// per launch, no reuse inside it); the gathered posteriors keep the cached forms.
+template <class T>
+__device__ __forceinline__ T ld_lane_nt(const T *base, uint32_t lane_off)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + lane_off));
+}
+template <class T>
+__device__ __forceinline__ void st_lane_nt(T *base, uint32_t lane_off, T v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + lane_off));
+}
 
 // One check row of compile-time degree D: all 2D loads are issued before any
 // arithmetic (the wave waits once per row, and straight-line code lets each
@@ -56,7 +68,7 @@ __device__ __forceinline__ void check_row(const int32_t *__restrict__ cols, cons
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         lv[k] = ld_lane(L + cols[k] * kChunk, off);
-        rv[k] = FIRST ? T(0) : ld_lane(Rrow + k * kChunk, off);
+        rv[k] = FIRST ? T(0) : ld_lane_nt(Rrow + k * kChunk, off);
     }
     T a[D], p[D];
     T acc0 = T(0), acc1 = T(0);
@@ -72,7 +84,7 @@ __device__ __forceinline__ void check_row(const int32_t *__restrict__ cols, cons
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) {
         const T r = k < H ? check_backward<A>(a[k], p[k], s0, acc1, sign) : check_backward<A>(a[k], p[k], s1, acc0, sign);
-        st_lane(Rrow + k * kChunk, off, r);
+        st_lane_nt(Rrow + k * kChunk, off, r);
     }
 }
 
@@ -90,7 +102,7 @@ __device__ __forceinline__ void check_row_guarded(const int32_t *__restrict__ co
     for (int k = 0; k < DMAX; ++k) {
         if (k < d) {
             lv[k] = ld_lane(L + cols[k] * kChunk, off);
-            rv[k] = FIRST ? T(0) : ld_lane(Rrow + k * kChunk, off);
+            rv[k] = FIRST ? T(0) : ld_lane_nt(Rrow + k * kChunk, off);
         }
     }
     T a[DMAX], p[DMAX];
@@ -114,7 +126,7 @@ __device__ __forceinline__ void check_row_guarded(const int32_t *__restrict__ co
         if (k < d) {
             const T r = k < h ? check_backward<A>(a[k], p[k], s0, acc1, sign)
                               : check_backward<A>(a[k], p[k], s1, acc0, sign);
-            st_lane(Rrow + k * kChunk, off, r);
+            st_lane_nt(Rrow + k * kChunk, off, r);
         }
     }
 }

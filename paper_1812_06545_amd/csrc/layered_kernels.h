@@ -20,13 +20,16 @@ namespace layered {
 
 using flood::kWaves;
 using flood::ld_lane;
+using flood::ld_lane_nt;
 using flood::map_block;
 using flood::st_lane;
+using flood::st_lane_nt;
 
 // One check row of compile-time degree D: all loads first, then the forward
 // and backward sweeps; each new message and its posterior are stored as soon
 // as they are formed.  FIRST (the first pass) reads no old messages: they
-// are all 0.
+// are all 0.  Messages stream with non-temporal accesses; posteriors, which
+// later layers gather, stay cached.
 template <class A, int D, bool FIRST>
 __device__ __forceinline__ void layer_row(const int32_t *__restrict__ cols, typename A::T *__restrict__ L,
                                           typename A::T *__restrict__ Rrow, uint32_t off)
@@ -37,7 +40,7 @@ __device__ __forceinline__ void layer_row(const int32_t *__restrict__ cols, type
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         q[k] = ld_lane(L + cols[k] * kChunk, off);
-        rv[k] = FIRST ? T(0) : ld_lane(Rrow + k * kChunk, off);
+        rv[k] = FIRST ? T(0) : ld_lane_nt(Rrow + k * kChunk, off);
     }
     T a[D], p[D];
     T acc0 = T(0), acc1 = T(0);
@@ -52,7 +55,7 @@ __device__ __forceinline__ void layer_row(const int32_t *__restrict__ cols, type
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) {
         const T r = k < H ? check_backward<A>(a[k], p[k], s0, acc1, sign) : check_backward<A>(a[k], p[k], s1, acc0, sign);
-        st_lane(Rrow + k * kChunk, off, r);
+        st_lane_nt(Rrow + k * kChunk, off, r);
         st_lane(L + cols[k] * kChunk, off, q[k] + r);
     }
 }
@@ -71,7 +74,7 @@ __device__ __forceinline__ void layer_row_guarded(const int32_t *__restrict__ co
     for (int k = 0; k < DMAX; ++k) {
         if (k < d) {
             q[k] = ld_lane(L + cols[k] * kChunk, off);
-            rv[k] = FIRST ? T(0) : ld_lane(Rrow + k * kChunk, off);
+            rv[k] = FIRST ? T(0) : ld_lane_nt(Rrow + k * kChunk, off);
         }
     }
     T a[DMAX], p[DMAX];
@@ -94,7 +97,7 @@ __device__ __forceinline__ void layer_row_guarded(const int32_t *__restrict__ co
         if (k < d) {
             const T r = k < h ? check_backward<A>(a[k], p[k], s0, acc1, sign)
                               : check_backward<A>(a[k], p[k], s1, acc0, sign);
-            st_lane(Rrow + k * kChunk, off, r);
+            st_lane_nt(Rrow + k * kChunk, off, r);
             st_lane(L + cols[k] * kChunk, off, q[k] + r);
         }
     }

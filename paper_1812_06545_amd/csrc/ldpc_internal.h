@@ -88,8 +88,8 @@ class ProfScope {
 
 // Copies bytes (a multiple of 16, both pointers 16-byte aligned) with the
 // streaming copy kernel on `stream`; either side may be pinned host memory
-// mapped for the device.  `cus` is the device's compute-unit count.
-ldpc_status launch_copy16(void *dst, const void *src, size_t bytes, int cus, hipStream_t stream);
+// mapped for the device.
+ldpc_status launch_copy16(void *dst, const void *src, size_t bytes, hipStream_t stream);
 
 // Streaming (per-iteration) path.
 size_t stream_workspace_bytes(const ldpc_code_s *c, ldpc_dtype dt, int32_t frames, int32_t max_iter);

@@ -121,7 +121,6 @@ struct ldpc_server_s {
     // device arena and its pinned host mirror (same offsets)
     // device arena of LLRs; pinned host memory for staged LLRs and results,
     // by its host (h_) and device (dh_) addresses; all share element offsets
-    int cus = 0;
     float *d_llr = nullptr;
     float *h_llr = nullptr, *h_post = nullptr, *dh_llr = nullptr, *dh_post = nullptr;
     uint8_t *h_bits = nullptr, *dh_bits = nullptr;
@@ -256,8 +255,8 @@ bool ldpc_server_s::admit(std::unique_lock<std::mutex> &lk)
         // bits, iteration counts and posteriors straight into pinned host
         // memory (each once).  The runtime's copy calls are not used here:
         // they have been seen to block the calling thread for milliseconds.
-        ldpc_status rc = ldpc::launch_copy16(d_llr + eb, dh_llr + eb, sizeof(float) * static_cast<size_t>(align4(e)), cus,
-                                       s.stream);
+        ldpc_status rc =
+            ldpc::launch_copy16(d_llr + eb, dh_llr + eb, sizeof(float) * static_cast<size_t>(align4(e)), s.stream);
         if (rc == LDPC_OK)
             rc = ldpc_decode_batch(jobs.data(), static_cast<int32_t>(jobs.size()), LDPC_F32, s.ws, s.ws_bytes,
                                    s.stream);
@@ -371,10 +370,6 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_serve
         delete sv;
         return LDPC_EINVAL;
     }
-    if (hipDeviceGetAttribute(&sv->cus, hipDeviceAttributeMultiprocessorCount, sv->device) != hipSuccess) {
-        delete sv;
-        return LDPC_EDEVICE;
-    }
     if (hipMalloc(&d, llr_bytes) != hipSuccess) {
         delete sv;
         return LDPC_ENOMEM;
@@ -425,7 +420,7 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_serve
     std::memset(sv->h_llr, 0, big);  // the copies below leave zero LLRs for the warm-up decodes
     for (Slot &s : sv->slots) {
         for (const size_t len : {std::min<size_t>(big, 4096), big})
-            if (launch_copy16(sv->d_llr, sv->dh_llr, len, sv->cus, s.stream) != LDPC_OK) {
+            if (launch_copy16(sv->d_llr, sv->dh_llr, len, s.stream) != LDPC_OK) {
                 sv->free_all();
                 delete sv;
                 return LDPC_EDEVICE;
