@@ -238,9 +238,8 @@ ldpc_status launch_group(const ldpc_job *jobs, const Group &g, char *ws, int thr
     auto *counter = reinterpret_cast<unsigned long long *>(ws + kGroupBytes - 256);
     {
         ProfScope ps(LDPC_KERNEL_OTHER, s);
-        hipLaunchKernelGGL(k_store_batch, dim3(1), dim3(256), 0, s, b, d_batch, counter);
+        LDPC_LAUNCH(ps, k_store_batch, dim3(1), dim3(256), 0, s, b, d_batch, counter);
     }
-    ProfScope ps(LDPC_KERNEL_FUSED, s);
     switch (g.bucket) {
     case 8: return launch_fused_bucket<A, 8>(b, d_batch, counter, lds, threads, s);
     case 16: return launch_fused_bucket<A, 16>(b, d_batch, counter, lds, threads, s);

@@ -277,12 +277,12 @@ ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, 
     const int init_blocks = static_cast<int>(std::min<int64_t>((Fp + unsat_words + 255) / 256, 4096));
     {
         ProfScope ps(LDPC_KERNEL_OTHER, s);
-        hipLaunchKernelGGL(k_frames_init, dim3(init_blocks), dim3(256), 0, s, Fp, done, unsat, unsat_words);
+        LDPC_LAUNCH(ps, k_frames_init, dim3(init_blocks), dim3(256), 0, s, Fp, done, unsat, unsat_words);
     }
     const dim3 tiles((c->n + 63) / 64, nchunk);
     {
         ProfScope ps(LDPC_KERNEL_INGEST, s);
-        hipLaunchKernelGGL((k_ingest<A>), tiles, dim3(256), 0, s, llr, frames, c->n, Lch, L);
+        LDPC_LAUNCH(ps, (k_ingest<A>), tiles, dim3(256), 0, s, llr, frames, c->n, Lch, L);
     }
 
     const int32_t rgroups = (c->m + kWaves - 1) / kWaves;
@@ -295,18 +295,17 @@ ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, 
             int32_t *unsat_t = unsat + static_cast<int64_t>(t - 1) * Fp;
             {
                 ProfScope ps(LDPC_KERNEL_OTHER, s);
-                hipLaunchKernelGGL((k_syndrome<A>), rgrid, dim3(256), 0, s, c->row_ptr, c->col_idx, c->m, c->n,
+                LDPC_LAUNCH(ps, (k_syndrome<A>), rgrid, dim3(256), 0, s, c->row_ptr, c->col_idx, c->m, c->n,
                                    rgroups, nchunk, L, done, unsat_t);
             }
             ProfScope ps(LDPC_KERNEL_OTHER, s);
-            hipLaunchKernelGGL(k_retire, dim3(static_cast<unsigned>((Fp + 255) / 256)), dim3(256), 0, s, Fp, done,
+            LDPC_LAUNCH(ps, k_retire, dim3(static_cast<unsigned>((Fp + 255) / 256)), dim3(256), 0, s, Fp, done,
                                unsat_t, t - 1);
         }
         for (size_t l = 0; l + 1 < c->layer_ptr.size(); ++l) {
             const int32_t row0 = c->layer_ptr[l], rows = c->layer_ptr[l + 1] - row0;
             const int32_t groups = (rows + kWaves - 1) / kWaves;
             const LayerArgs<A> la{c->row_ptr, c->col_idx, row0, rows, c->n, c->E, groups, nchunk, R, L, done};
-            ProfScope ps(LDPC_KERNEL_CHECK, s);
             launch_layer<A>(c->layer_dmax[l], first, es, dim3(static_cast<unsigned>(groups) * nchunk), s, la);
         }
     }
@@ -314,21 +313,20 @@ ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, 
         const bool first = (t == 1);
         int32_t *unsat_t = unsat + static_cast<int64_t>(t - 1) * Fp;
         {
-            ProfScope ps(LDPC_KERNEL_CHECK, s);
             const CheckArgs<A> ca{c->row_ptr, c->col_idx, c->m, c->n, c->E, rgroups, nchunk, R, L, done, unsat_t};
             launch_check<A>(c, first, es, rgrid, s, ca);
         }
         ProfScope ps(LDPC_KERNEL_VARIABLE, s);
         if (es)
-            hipLaunchKernelGGL((k_variable<A, true>), cgrid, dim3(256), 0, s, c->col_ptr, c->col_edge, c->n, c->E,
+            LDPC_LAUNCH(ps, (k_variable<A, true>), cgrid, dim3(256), 0, s, c->col_ptr, c->col_edge, c->n, c->E,
                                cgroups, nchunk, R, Lch, L, done, unsat_t, t - 1);
         else
-            hipLaunchKernelGGL((k_variable<A, false>), cgrid, dim3(256), 0, s, c->col_ptr, c->col_edge, c->n, c->E,
+            LDPC_LAUNCH(ps, (k_variable<A, false>), cgrid, dim3(256), 0, s, c->col_ptr, c->col_edge, c->n, c->E,
                                cgroups, nchunk, R, Lch, L, done, unsat_t, t - 1);
     }
     {
         ProfScope ps(LDPC_KERNEL_OUTPUT, s);
-        hipLaunchKernelGGL((k_output<A>), tiles, dim3(256), 0, s, L, llr, done, frames, c->n, max_iter,
+        LDPC_LAUNCH(ps, (k_output<A>), tiles, dim3(256), 0, s, L, llr, done, frames, c->n, max_iter,
                            static_cast<int32_t>(es), bits, iters, post);
     }
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EDEVICE;

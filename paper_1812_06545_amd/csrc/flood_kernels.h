@@ -276,8 +276,11 @@ template <class A, int DB, bool EXACT>
 void launch_check_bucket(const CheckArgs<A> &a, bool first, bool es, dim3 grid, hipStream_t s);
 
 #define LDPC_CHECK_LAUNCH_ONE(A_, DB_, EX_, F_, E_)                                                              \
-    hipLaunchKernelGGL((flood::k_check<A_, DB_, EX_, F_, E_>), grid, dim3(256), 0, s, a.row_ptr, a.col_idx, a.m, \
-                       a.n, a.E, a.groups, a.nchunk, a.R, a.L, a.done, a.unsat)
+    do {                                                                                                         \
+        ProfScope ps(LDPC_KERNEL_CHECK, s);                                                                      \
+        LDPC_LAUNCH(ps, (flood::k_check<A_, DB_, EX_, F_, E_>), grid, dim3(256), 0, s, a.row_ptr, a.col_idx, a.m, \
+                    a.n, a.E, a.groups, a.nchunk, a.R, a.L, a.done, a.unsat);                                   \
+    } while (0)
 
 #define LDPC_DEFINE_CHECK_BUCKET(A_, DB_, EX_)                                                                  \
     template <>                                                                                                 \

@@ -550,8 +550,9 @@ ldpc_status launch_fused_bucket(const fused::Batch &batch, fused::Batch *d_batch
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)              \
             return LDPC_EDEVICE;                                                                                 \
         const int64_t grid = std::min<int64_t>(batch.nitems, static_cast<int64_t>(per_cu) * cus);               \
-        hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(threads), lds_bytes, s, d_batch,        \
-                           counter);                                                                             \
+        ProfScope ps(LDPC_KERNEL_FUSED, s);                                                                      \
+        LDPC_LAUNCH(ps, kern, dim3(static_cast<unsigned>(grid)), dim3(threads), static_cast<uint32_t>(lds_bytes), \
+                    s, d_batch, counter);                                                                        \
         return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EDEVICE;                                         \
     }
 

@@ -173,8 +173,11 @@ template <class A, int DB, bool EXACT>
 void launch_layer_bucket(const LayerArgs<A> &a, bool first, bool es, dim3 grid, hipStream_t s);
 
 #define LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, F_, E_)                                                              \
-    hipLaunchKernelGGL((layered::k_layer<A_, DB_, EX_, F_, E_>), grid, dim3(256), 0, s, a.row_ptr, a.col_idx,  \
-                       a.row0, a.rows, a.n, a.E, a.groups, a.nchunk, a.R, a.L, a.done)
+    do {                                                                                                         \
+        ProfScope ps(LDPC_KERNEL_CHECK, s);                                                                      \
+        LDPC_LAUNCH(ps, (layered::k_layer<A_, DB_, EX_, F_, E_>), grid, dim3(256), 0, s, a.row_ptr, a.col_idx,  \
+                    a.row0, a.rows, a.n, a.E, a.groups, a.nchunk, a.R, a.L, a.done);                            \
+    } while (0)
 
 #define LDPC_DEFINE_LAYER_BUCKET(A_, DB_, EX_)                                                                  \
     template <>                                                                                                 \

@@ -1,6 +1,7 @@
 // Internal declarations shared by the libldpc translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -72,19 +73,33 @@ inline int64_t frames_padded(int64_t frames) { return (frames + kChunk - 1) / kC
 
 bool code_on_current_device(const ldpc_code_s *c);
 
-// Brackets one kernel launch with profiling events when profiling is on.
+// Timing of one kernel launch when profiling is on (and the stream is not
+// being captured): the scope hands out a start and a stop event that the
+// launch carries itself (LDPC_LAUNCH, i.e. hipExtLaunchKernelGGL), so the
+// runtime stamps the kernel's own start and end and no separate event
+// packet sits between dependent launches; the scope files the pair on exit.
+// Otherwise both events are null and LDPC_LAUNCH is a plain launch.
 class ProfScope {
   public:
     ProfScope(ldpc_kernel_kind kind, hipStream_t stream);
     ~ProfScope();
     ProfScope(const ProfScope &) = delete;
     ProfScope &operator=(const ProfScope &) = delete;
+    hipEvent_t start() const { return start_; }
+    hipEvent_t stop() const { return stop_; }
 
   private:
     int kind_ = -1;
-    hipStream_t stream_ = nullptr;
-    hipEvent_t start_ = nullptr;
+    hipEvent_t start_ = nullptr, stop_ = nullptr;
 };
+
+#define LDPC_LAUNCH(ps, kernel, grid, block, shmem, stream, ...)                                                  \
+    do {                                                                                                         \
+        if ((ps).start())                                                                                        \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, (ps).start(), (ps).stop(), 0u, __VA_ARGS__); \
+        else                                                                                                     \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                                \
+    } while (0)
 
 // Copies bytes (a multiple of 16, both pointers 16-byte aligned) with the
 // streaming copy kernel on `stream`; either side may be pinned host memory

@@ -33,8 +33,8 @@ ldpc_status launch_copy16(void *dst, const void *src, size_t bytes, hipStream_t 
     if (blocks > 0x7fffffff)
         return LDPC_EINVAL;
     ProfScope ps(LDPC_KERNEL_OTHER, stream);
-    hipLaunchKernelGGL(k_copy, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
-                       static_cast<const v4f *>(src), static_cast<v4f *>(dst), n);
+    LDPC_LAUNCH(ps, k_copy, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, static_cast<const v4f *>(src),
+                static_cast<v4f *>(dst), n);
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EDEVICE;
 }
 

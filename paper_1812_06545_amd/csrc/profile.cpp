@@ -1,4 +1,5 @@
-// Per-kernel device timing with HIP events (measurement aid, off by default).
+// Per-kernel device timing with HIP events carried by the launches themselves
+// (measurement aid, off by default).
 #include <atomic>
 #include <mutex>
 #include <vector>
@@ -46,32 +47,24 @@ ldpc::ProfScope::ProfScope(ldpc_kernel_kind kind, hipStream_t stream)
     if (!g_enabled.load(std::memory_order_relaxed) || capturing(stream))
         return;
     start_ = take_event();
-    if (!start_)
-        return;
-    if (hipEventRecord(start_, stream) != hipSuccess) {
-        std::lock_guard<std::mutex> lk(g_mu);
-        g_pool.push_back(start_);
+    stop_ = start_ ? take_event() : nullptr;
+    if (!stop_) {
+        if (start_) {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_pool.push_back(start_);
+        }
         start_ = nullptr;
         return;
     }
     kind_ = kind;
-    stream_ = stream;
 }
 
 ldpc::ProfScope::~ProfScope()
 {
     if (!start_)
         return;
-    hipEvent_t stop = take_event();
-    if (!stop || hipEventRecord(stop, stream_) != hipSuccess) {
-        std::lock_guard<std::mutex> lk(g_mu);
-        g_pool.push_back(start_);
-        if (stop)
-            g_pool.push_back(stop);
-        return;
-    }
     std::lock_guard<std::mutex> lk(g_mu);
-    g_records.push_back({kind_, start_, stop});
+    g_records.push_back({kind_, start_, stop_});
 }
 
 extern "C" ldpc_status ldpc_profile_enable(int enable)
