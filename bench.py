@@ -50,7 +50,7 @@ PROFILE_EVERY = 4  # timed steps per step whose launches are bracketed by HIP ev
 # only for the kernel source they were taken on (hash below); otherwise null.
 CHECK_TRAFFIC = {
     "bytes_per_launch": 543.4e6,
-    "source_sha256": "a34a2df9c42de5b471a76143a417b1c290ff56e3ed7df1f09356d6c182fbb648",
+    "source_sha256": "69d801661a59aa8c747bb11b6d9973a376a3bac918cee4aa498b178b0e058293",
     "profile": "profiles/hbm_traffic_check_qc1944.md",
 }
 CHECK_SOURCES = ("flood_kernels.h", "spa_math.h", "check_f32_d24.hip")
