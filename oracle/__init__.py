@@ -10,6 +10,9 @@ message passing, Algorithm 1's loop order) with the sum-product check rule of
 Section I; see spa_oracle.c for the exact definition and readings.  With
 ``schedule="layered"`` it runs the serial check-node schedule of the paper's
 layered algorithm (Algorithm 2, Section II) instead; see layered_oracle.c.
+With ``rule="minsum"`` the check rule is min-sum (the rule Algorithm 1 is
+named after), with optional scale and offset of the magnitude; see
+minsum_oracle.c.
 """
 from __future__ import annotations
 
@@ -39,6 +42,11 @@ def _load(path: str = LIB):
             f.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int,
                           ctypes.c_double, P, P, P, P, P, ctypes.c_int]
             f.restype = ctypes.c_int
+        if hasattr(lib, "oracle_minsum_decode"):
+            f = lib.oracle_minsum_decode
+            f.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P, P, P, P, ctypes.c_int]
+            f.restype = ctypes.c_int
         if path != LIB:
             return lib
         _lib = lib
@@ -50,12 +58,15 @@ def _ptr(a):
 
 
 def decode(code, llr, max_iter: int, early_stop: bool, r_max: float = R_MAX, nthreads: int = 1,
-           want_trace: bool = True, lib=None, schedule: str = "flooding"):
+           want_trace: bool = True, lib=None, schedule: str = "flooding", rule: str = "spa",
+           ms_scale: float = 1.0, ms_offset: float = 0.0):
     """Decode frames ``llr`` (F, n) -> dict(bits, iters, posterior, cond, min_abs).
 
     ``schedule`` is "flooding" (all checks, then all variables, per iteration)
     or "layered" (check rows one at a time in ascending order, each updating
-    its variables at once; one iteration = one pass over the rows).
+    its variables at once; one iteration = one pass over the rows).  ``rule``
+    is "spa" (sum-product) or "minsum" (|r| = max(ms_scale * min - ms_offset,
+    0), then the clamp).
 
     float32 input is upcast to float64 unchanged, so both sides see the same
     values.  ``lib`` lets the tests point at a deliberately broken build.
@@ -73,9 +84,16 @@ def decode(code, llr, max_iter: int, early_stop: bool, r_max: float = R_MAX, nth
     L = lib if lib is not None else _load()
     if schedule not in ("flooding", "layered"):
         raise ValueError(f"unknown schedule {schedule!r}")
-    fn = L.oracle_spa_decode if schedule == "flooding" else L.oracle_spa_layered_decode
-    st = fn(code.m, n, _ptr(rp), _ptr(ci), F, _ptr(llr), int(max_iter), int(bool(early_stop)), float(r_max),
-            _ptr(bits), _ptr(iters), _ptr(post), _ptr(cond), _ptr(mabs), int(nthreads))
+    if rule == "minsum":
+        st = L.oracle_minsum_decode(code.m, n, _ptr(rp), _ptr(ci), F, _ptr(llr), int(max_iter), int(bool(early_stop)),
+                                    int(schedule == "layered"), float(ms_scale), float(ms_offset), float(r_max),
+                                    _ptr(bits), _ptr(iters), _ptr(post), _ptr(cond), _ptr(mabs), int(nthreads))
+    elif rule == "spa":
+        fn = L.oracle_spa_decode if schedule == "flooding" else L.oracle_spa_layered_decode
+        st = fn(code.m, n, _ptr(rp), _ptr(ci), F, _ptr(llr), int(max_iter), int(bool(early_stop)), float(r_max),
+                _ptr(bits), _ptr(iters), _ptr(post), _ptr(cond), _ptr(mabs), int(nthreads))
+    else:
+        raise ValueError(f"unknown rule {rule!r}")
     if st != 0:
-        raise ValueError(f"oracle ({schedule}) failed with status {st}")
+        raise ValueError(f"oracle ({schedule}, {rule}) failed with status {st}")
     return {"bits": bits, "iters": iters, "posterior": post, "cond": cond, "min_abs": mabs}

@@ -1,5 +1,6 @@
-"""Build step for the oracle: compiles spa_oracle.c (flooding) and
-layered_oracle.c (layered schedule) into liboracle_spa.so.
+"""Build step for the oracle: compiles spa_oracle.c (flooding), layered_oracle.c
+(layered schedule) and minsum_oracle.c (min-sum rule, both schedules) into
+liboracle_spa.so.
 
 Test infrastructure only (see spa_oracle.c).  Plain gcc, no fast-math, so the
 libm tanh/atanh used are the IEEE-accurate ones.
@@ -12,10 +13,11 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "spa_oracle.c")
 SRC_LAYERED = os.path.join(HERE, "layered_oracle.c")
+SRC_MINSUM = os.path.join(HERE, "minsum_oracle.c")
 LIB = os.path.join(HERE, "liboracle_spa.so")
 
 
-def compile_oracle(src=(SRC, SRC_LAYERED), out: str = LIB, extra=()) -> str:
+def compile_oracle(src=(SRC, SRC_LAYERED, SRC_MINSUM), out: str = LIB, extra=()) -> str:
     """Compile one source file (a path) or several (a sequence) into `out`."""
     srcs = [src] if isinstance(src, str) else list(src)
     cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Werror",
