@@ -30,6 +30,13 @@
  * not change the result.  To decode in another row order, permute the rows
  * of H.
  *
+ * With LDPC_MIN_SUM the Loop 2 rule is min-sum (Section II: Algorithm 1 is
+ * named the min-sum algorithm), on either schedule:
+ *   r_mn = prod_{n' != n} sgn(q_mn') * min(max(scale * min_{n' != n} |q_mn'| - offset, 0), LDPC_R_MAX)
+ * with sgn(0) = +1; scale = 1 and offset = 0 is plain min-sum, scale < 1
+ * normalised and offset > 0 offset min-sum (ldpc_decode_minsum; ldpc_decode
+ * uses 1 and 0).  A check of degree 1 sends +LDPC_R_MAX.
+ *
  * Conventions for every call:
  *   - Frame buffers are row-major [frames][n]: frame f, bit j at f*n + j.
  *   - "device" pointers are HIP device memory of the device the code handle
@@ -73,6 +80,7 @@ typedef enum { LDPC_F32 = 0, LDPC_F64 = 1 } ldpc_dtype;
 
 #define LDPC_EARLY_STOP 1u  /* flag: stop a frame at its first zero syndrome */
 #define LDPC_LAYERED 2u     /* flag: layered schedule (ldpc_decode and ldpc_decode_batch jobs) */
+#define LDPC_MIN_SUM 4u     /* flag: min-sum check rule instead of sum-product */
 
 /* Clamp on check-to-variable messages (the paper gives none; 20 keeps the
  * FP64 tanh/atanh evaluation accurate). */
@@ -142,7 +150,7 @@ ldpc_status ldpc_workspace_bytes(ldpc_code code, ldpc_dtype dtype, int32_t frame
  * with early stop.
  *   dtype      LDPC_F32 (llr/posterior are float) or LDPC_F64 (double)
  *   max_iter   >= 0; 0 returns the hard decision of llr, iters 0, posterior = llr
- *   flags      0, LDPC_EARLY_STOP, LDPC_LAYERED or both
+ *   flags      any of LDPC_EARLY_STOP, LDPC_LAYERED, LDPC_MIN_SUM (or 0)
  *   llr        device, [frames][n] of dtype, read only
  *   bits       device, [frames][n] uint8 0/1 (written)
  *   iters      device, [frames] int32 (written)
@@ -154,6 +162,16 @@ ldpc_status ldpc_decode(ldpc_code code, ldpc_dtype dtype, int32_t frames, int32_
                         const void *llr, uint8_t *bits, int32_t *iters, void *posterior, void *workspace,
                         size_t workspace_bytes, void *stream);
 
+/*
+ * ldpc_decode with the min-sum magnitude correction given: with LDPC_MIN_SUM
+ * in flags, |r| = max(ms_scale * min - ms_offset, 0) before the clamp
+ * (ms_offset in natural LLR units).  EINVAL unless ms_scale is finite and
+ * > 0 and ms_offset finite and >= 0 (checked whatever the flags).
+ */
+ldpc_status ldpc_decode_minsum(ldpc_code code, ldpc_dtype dtype, int32_t frames, int32_t max_iter, uint32_t flags,
+                               float ms_scale, float ms_offset, const void *llr, uint8_t *bits, int32_t *iters,
+                               void *posterior, void *workspace, size_t workspace_bytes, void *stream);
+
 /* One decoding job of a batch: same meaning as the ldpc_decode arguments. */
 typedef struct {
     ldpc_code code;
@@ -164,6 +182,8 @@ typedef struct {
     uint8_t *bits;
     int32_t *iters;
     void *posterior; /* may be NULL */
+    float ms_scale;  /* min-sum correction (used with LDPC_MIN_SUM), as in ldpc_decode_minsum: */
+    float ms_offset; /* scale > 0 (1 = plain min-sum), offset >= 0 */
 } ldpc_job;
 
 /*

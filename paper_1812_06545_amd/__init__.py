@@ -25,6 +25,7 @@ LDPC_OK, LDPC_EINVAL, LDPC_ENOMEM, LDPC_EDEVICE, LDPC_EBUSY, LDPC_EUNSUPPORTED =
 LDPC_F32, LDPC_F64 = 0, 1
 LDPC_EARLY_STOP = 1
 LDPC_LAYERED = 2
+LDPC_MIN_SUM = 4
 LDPC_R_MAX = 20.0
 
 if not os.path.exists(LIB_PATH):
@@ -38,7 +39,8 @@ _I32 = ctypes.c_int32
 
 class ldpc_job(ctypes.Structure):
     _fields_ = [("code", _P), ("frames", _I32), ("max_iter", _I32), ("flags", ctypes.c_uint32),
-                ("llr", _P), ("bits", _P), ("iters", _P), ("posterior", _P)]
+                ("llr", _P), ("bits", _P), ("iters", _P), ("posterior", _P),
+                ("ms_scale", ctypes.c_float), ("ms_offset", ctypes.c_float)]
 
 
 def _sig(name, res, args):
@@ -57,6 +59,8 @@ _sig("ldpc_code_destroy", None, [_P])
 _sig("ldpc_workspace_bytes", ctypes.c_int, [_P, ctypes.c_int, _I32, _I32, ctypes.POINTER(ctypes.c_size_t)])
 _sig("ldpc_decode", ctypes.c_int, [_P, ctypes.c_int, _I32, _I32, ctypes.c_uint32, _P, _P, _P, _P, _P,
                                    ctypes.c_size_t, _P])
+_sig("ldpc_decode_minsum", ctypes.c_int, [_P, ctypes.c_int, _I32, _I32, ctypes.c_uint32, ctypes.c_float,
+                                          ctypes.c_float, _P, _P, _P, _P, _P, ctypes.c_size_t, _P])
 _sig("ldpc_batch_workspace_bytes", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int,
                                                   ctypes.POINTER(ctypes.c_size_t)])
 _sig("ldpc_decode_batch", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, _P, ctypes.c_size_t, _P])
@@ -201,6 +205,13 @@ def ldpc_decode(handle, dtype, frames, max_iter, flags, llr, bits, iters, poster
                             _stream_handle(stream))
 
 
+def ldpc_decode_minsum(handle, dtype, frames, max_iter, flags, ms_scale, ms_offset, llr, bits, iters, posterior,
+                       workspace, workspace_bytes, stream=None) -> int:
+    return _lib.ldpc_decode_minsum(_handle(handle), _dtype_code(dtype), int(frames), int(max_iter), int(flags),
+                                   float(ms_scale), float(ms_offset), _ptr(llr), _ptr(bits), _ptr(iters),
+                                   _ptr(posterior), _ptr(workspace), int(workspace_bytes), _stream_handle(stream))
+
+
 def _jobs_array(jobs):
     arr = (ldpc_job * max(len(jobs), 1))()
     for i, j in enumerate(jobs):
@@ -329,15 +340,20 @@ def _workspace(nbytes, device):
     return ws
 
 
-def _flags(early_stop: bool, layered: bool) -> int:
-    return (LDPC_EARLY_STOP if early_stop else 0) | (LDPC_LAYERED if layered else 0)
+def _flags(early_stop: bool, layered: bool, rule: str = "spa") -> int:
+    if rule not in ("spa", "minsum"):
+        raise ValueError(f"unknown check rule {rule!r}")
+    return ((LDPC_EARLY_STOP if early_stop else 0) | (LDPC_LAYERED if layered else 0)
+            | (LDPC_MIN_SUM if rule == "minsum" else 0))
 
 
 def decode(code: Code, llr: torch.Tensor, max_iter: int, early_stop: bool = False, want_posterior: bool = True,
-           stream=None, workspace: torch.Tensor = None, layered: bool = False):
+           stream=None, workspace: torch.Tensor = None, layered: bool = False, rule: str = "spa",
+           ms_scale: float = 1.0, ms_offset: float = 0.0):
     """Decode llr [frames, n] (float32 or float64, on the GPU), flooding or
-    (layered=True) layered schedule.  Returns (bits uint8 [frames, n], iters
-    int32 [frames], posterior or None)."""
+    (layered=True) layered schedule, sum-product or (rule="minsum") min-sum
+    check rule with magnitude max(ms_scale * min - ms_offset, 0).  Returns
+    (bits uint8 [frames, n], iters int32 [frames], posterior or None)."""
     assert llr.is_cuda and llr.dim() == 2 and llr.shape[1] == code.n and llr.is_contiguous()
     frames = llr.shape[0]
     dev = llr.device
@@ -347,9 +363,9 @@ def decode(code: Code, llr: torch.Tensor, max_iter: int, early_stop: bool = Fals
     need = ldpc_workspace_bytes(code.handle, llr.dtype, frames, max_iter)
     if workspace is None or workspace.numel() < need:
         workspace = _workspace(need, dev)
-    flags = _flags(early_stop, layered)
-    _check(ldpc_decode(code.handle, llr.dtype, frames, max_iter, flags, llr, bits, iters, post, workspace,
-                       workspace.numel(), stream), "ldpc_decode")
+    flags = _flags(early_stop, layered, rule)
+    _check(ldpc_decode_minsum(code.handle, llr.dtype, frames, max_iter, flags, ms_scale, ms_offset, llr, bits, iters,
+                              post, workspace, workspace.numel(), stream), "ldpc_decode_minsum")
     return bits, iters, post
 
 
@@ -357,18 +373,20 @@ class Job:
     """One job of a batch, holding its output tensors."""
 
     def __init__(self, code: Code, llr: torch.Tensor, max_iter: int, early_stop: bool = False,
-                 want_posterior: bool = True, layered: bool = False):
+                 want_posterior: bool = True, layered: bool = False, rule: str = "spa", ms_scale: float = 1.0,
+                 ms_offset: float = 0.0):
         assert llr.is_cuda and llr.dim() == 2 and llr.shape[1] == code.n and llr.is_contiguous()
         self.code, self.llr, self.max_iter, self.early_stop = code, llr, max_iter, early_stop
-        self.layered = layered
+        self.layered, self.rule, self.ms_scale, self.ms_offset = layered, rule, ms_scale, ms_offset
         dev = llr.device
         self.bits = torch.empty((llr.shape[0], code.n), dtype=torch.uint8, device=dev)
         self.iters = torch.empty(llr.shape[0], dtype=torch.int32, device=dev)
         self.posterior = torch.empty_like(llr) if want_posterior else None
 
     def c_struct(self) -> ldpc_job:
-        return ldpc_job(self.code.handle, self.llr.shape[0], self.max_iter, _flags(self.early_stop, self.layered),
-                        _ptr(self.llr), _ptr(self.bits), _ptr(self.iters), _ptr(self.posterior))
+        return ldpc_job(self.code.handle, self.llr.shape[0], self.max_iter,
+                        _flags(self.early_stop, self.layered, self.rule), _ptr(self.llr), _ptr(self.bits),
+                        _ptr(self.iters), _ptr(self.posterior), float(self.ms_scale), float(self.ms_offset))
 
 
 class Plan:

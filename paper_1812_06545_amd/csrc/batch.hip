@@ -157,7 +157,9 @@ ldpc_status validate_jobs(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype)
     for (int32_t i = 0; i < njobs; ++i) {
         const ldpc_job &j = jobs[i];
         if (!j.code || j.frames < 0 || j.frames > LDPC_MAX_FRAMES || j.max_iter < 0 ||
-            (j.flags & ~(LDPC_EARLY_STOP | LDPC_LAYERED)) != 0)
+            (j.flags & ~(LDPC_EARLY_STOP | LDPC_LAYERED | LDPC_MIN_SUM)) != 0)
+            return LDPC_EINVAL;
+        if ((j.flags & LDPC_MIN_SUM) && !ldpc::minsum_params_ok(j.ms_scale, j.ms_offset))
             return LDPC_EINVAL;
         if (j.frames > 0 && (!j.llr || !j.bits || !j.iters))
             return LDPC_EINVAL;
@@ -224,6 +226,8 @@ ldpc_status launch_group(const ldpc_job *jobs, const Group &g, char *ws, int thr
         e.frames = j.frames;
         e.max_iter = j.max_iter;
         e.flags = j.flags;
+        e.ms_scale = j.ms_scale;
+        e.ms_offset = j.ms_offset;
         e.item_begin = items;
         e.llr = j.llr;
         e.bits = j.bits;
@@ -298,7 +302,7 @@ extern "C" ldpc_status ldpc_decode_batch(const ldpc_job *jobs, int32_t njobs, ld
     for (int32_t i : plain) {
         const ldpc_job &j = jobs[i];
         const ldpc_status r = stream_decode(j.code, dtype, j.frames, j.max_iter, j.flags, j.llr, j.bits, j.iters,
-                                            j.posterior, ws, s);
+                                            j.posterior, ws, s, j.ms_scale, j.ms_offset);
         if (r != LDPC_OK)
             return r;
     }

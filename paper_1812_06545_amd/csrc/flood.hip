@@ -35,10 +35,16 @@
 // (layered_kernels.h); with early stop a syndrome kernel and a retire kernel
 // test x^(t-1) = [L < 0] before pass t, since inside a pass the rows see
 // different posteriors and cannot test one decision together.
+//
+// With LDPC_MIN_SUM the check rule is min-sum (minsum_kernels.h) on either
+// schedule; the variable kernel, the syndrome and the retire kernels are
+// shared.
 #include <algorithm>
+#include <cmath>
 
 #include "flood_kernels.h"
 #include "layered_kernels.h"
+#include "minsum_kernels.h"
 
 namespace ldpc {
 namespace {
@@ -255,9 +261,27 @@ void launch_layer<ArithF64>(int32_t d, bool first, bool es, dim3 grid, hipStream
         launch_layer_bucket<ArithF64, 64, false>(a, first, es, grid, s);
 }
 
+// Min-sum bucket of a row degree: 8, 16, 32 or 64.
+template <class A>
+void launch_ms(int32_t d, bool layered, bool first, bool es, dim3 grid, hipStream_t s, const MinSumArgs<A> &a)
+{
+    if (d <= 8)
+        layered ? launch_layer_ms_bucket<A, 8>(a, first, es, grid, s) : launch_check_ms_bucket<A, 8>(a, first, es, grid, s);
+    else if (d <= 16)
+        layered ? launch_layer_ms_bucket<A, 16>(a, first, es, grid, s)
+                : launch_check_ms_bucket<A, 16>(a, first, es, grid, s);
+    else if (d <= 32)
+        layered ? launch_layer_ms_bucket<A, 32>(a, first, es, grid, s)
+                : launch_check_ms_bucket<A, 32>(a, first, es, grid, s);
+    else
+        layered ? launch_layer_ms_bucket<A, 64>(a, first, es, grid, s)
+                : launch_check_ms_bucket<A, 64>(a, first, es, grid, s);
+}
+
 template <class A>
 ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, uint32_t flags, const void *llr_v,
-                        uint8_t *bits, int32_t *iters, void *post_v, void *ws, hipStream_t s)
+                        uint8_t *bits, int32_t *iters, void *post_v, void *ws, hipStream_t s, double ms_scale,
+                        double ms_offset)
 {
     using T = typename A::T;
     const int64_t Fp = frames_padded(frames);
@@ -289,6 +313,8 @@ ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, 
     const int32_t cgroups = (c->n + kWaves - 1) / kWaves;
     const dim3 rgrid(static_cast<unsigned>(rgroups) * nchunk), cgrid(static_cast<unsigned>(cgroups) * nchunk);
     const bool layered = (flags & LDPC_LAYERED) != 0;
+    const bool ms = (flags & LDPC_MIN_SUM) != 0;
+    const T scale = static_cast<T>(ms_scale), offset = static_cast<T>(ms_offset * A::kIn);
     for (int32_t t = 1; t <= max_iter && layered; ++t) {
         const bool first = (t == 1);
         if (es && c->m > 0) {
@@ -305,14 +331,25 @@ ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, 
         for (size_t l = 0; l + 1 < c->layer_ptr.size(); ++l) {
             const int32_t row0 = c->layer_ptr[l], rows = c->layer_ptr[l + 1] - row0;
             const int32_t groups = (rows + kWaves - 1) / kWaves;
-            const LayerArgs<A> la{c->row_ptr, c->col_idx, row0, rows, c->n, c->E, groups, nchunk, R, L, done};
-            launch_layer<A>(c->layer_dmax[l], first, es, dim3(static_cast<unsigned>(groups) * nchunk), s, la);
+            const dim3 grid(static_cast<unsigned>(groups) * nchunk);
+            if (ms) {
+                const MinSumArgs<A> ma{c->row_ptr, c->col_idx, row0, rows, c->m, c->n, c->E, groups, nchunk,
+                                       R, L, done, nullptr, scale, offset};
+                launch_ms<A>(c->layer_dmax[l], true, first, es, grid, s, ma);
+            } else {
+                const LayerArgs<A> la{c->row_ptr, c->col_idx, row0, rows, c->n, c->E, groups, nchunk, R, L, done};
+                launch_layer<A>(c->layer_dmax[l], first, es, grid, s, la);
+            }
         }
     }
     for (int32_t t = 1; t <= max_iter && !layered; ++t) {
         const bool first = (t == 1);
         int32_t *unsat_t = unsat + static_cast<int64_t>(t - 1) * Fp;
-        {
+        if (ms) {
+            const MinSumArgs<A> ma{c->row_ptr, c->col_idx, 0, c->m, c->m, c->n, c->E, rgroups, nchunk,
+                                   R, L, done, unsat_t, scale, offset};
+            launch_ms<A>(c->max_row_deg, false, first, es, rgrid, s, ma);
+        } else {
             const CheckArgs<A> ca{c->row_ptr, c->col_idx, c->m, c->n, c->E, rgroups, nchunk, R, L, done, unsat_t};
             launch_check<A>(c, first, es, rgrid, s, ca);
         }
@@ -342,11 +379,18 @@ size_t stream_workspace_bytes(const ldpc_code_s *c, ldpc_dtype dt, int32_t frame
 
 ldpc_status stream_decode(const ldpc_code_s *c, ldpc_dtype dt, int32_t frames, int32_t max_iter, uint32_t flags,
                           const void *llr, uint8_t *bits, int32_t *iters, void *posterior, void *ws,
-                          hipStream_t stream)
+                          hipStream_t stream, double ms_scale, double ms_offset)
 {
     if (dt == LDPC_F64)
-        return decode_impl<ArithF64>(c, frames, max_iter, flags, llr, bits, iters, posterior, ws, stream);
-    return decode_impl<ArithF32>(c, frames, max_iter, flags, llr, bits, iters, posterior, ws, stream);
+        return decode_impl<ArithF64>(c, frames, max_iter, flags, llr, bits, iters, posterior, ws, stream, ms_scale,
+                                     ms_offset);
+    return decode_impl<ArithF32>(c, frames, max_iter, flags, llr, bits, iters, posterior, ws, stream, ms_scale,
+                                 ms_offset);
+}
+
+bool minsum_params_ok(double scale, double offset)
+{
+    return std::isfinite(scale) && scale > 0.0 && std::isfinite(offset) && offset >= 0.0;
 }
 
 }  // namespace ldpc
@@ -365,8 +409,18 @@ extern "C" ldpc_status ldpc_decode(ldpc_code code, ldpc_dtype dtype, int32_t fra
                                    uint32_t flags, const void *llr, uint8_t *bits, int32_t *iters, void *posterior,
                                    void *workspace, size_t workspace_bytes, void *stream)
 {
+    return ldpc_decode_minsum(code, dtype, frames, max_iter, flags, 1.0f, 0.0f, llr, bits, iters, posterior,
+                              workspace, workspace_bytes, stream);
+}
+
+extern "C" ldpc_status ldpc_decode_minsum(ldpc_code code, ldpc_dtype dtype, int32_t frames, int32_t max_iter,
+                                          uint32_t flags, float ms_scale, float ms_offset, const void *llr,
+                                          uint8_t *bits, int32_t *iters, void *posterior, void *workspace,
+                                          size_t workspace_bytes, void *stream)
+{
     if (!code || frames < 0 || frames > LDPC_MAX_FRAMES || max_iter < 0 ||
-        (flags & ~(LDPC_EARLY_STOP | LDPC_LAYERED)) != 0 || (dtype != LDPC_F32 && dtype != LDPC_F64))
+        (flags & ~(LDPC_EARLY_STOP | LDPC_LAYERED | LDPC_MIN_SUM)) != 0 || (dtype != LDPC_F32 && dtype != LDPC_F64) ||
+        !ldpc::minsum_params_ok(ms_scale, ms_offset))
         return LDPC_EINVAL;
     if (frames == 0)
         return LDPC_OK;
@@ -379,5 +433,5 @@ extern "C" ldpc_status ldpc_decode(ldpc_code code, ldpc_dtype dtype, int32_t fra
     if (!ldpc::code_on_current_device(code))
         return LDPC_EINVAL;
     return ldpc::stream_decode(code, dtype, frames, max_iter, flags, llr, bits, iters, posterior, workspace,
-                               static_cast<hipStream_t>(stream));
+                               static_cast<hipStream_t>(stream), ms_scale, ms_offset);
 }

@@ -28,6 +28,7 @@
 #include <type_traits>
 
 #include "ldpc_internal.h"
+#include "minsum_kernels.h"
 #include "spa_math.h"
 
 namespace ldpc {
@@ -48,6 +49,7 @@ struct Code {
 struct Job {
     int32_t code, frames, max_iter;
     uint32_t flags;
+    float ms_scale, ms_offset;  // min-sum correction (LDPC_MIN_SUM), natural LLR units
     int64_t item_begin;
     const void *llr;
     uint8_t *bits;
@@ -238,6 +240,49 @@ __device__ __forceinline__ void layered_row_dispatch(int hwave, const Row &row, 
     }
 }
 
+// One half of a check row under the min-sum rule, flooding or (LAYERED)
+// layered, padded body of length D: each lane keeps the running minimum
+// state of its half, the partner lanes merge theirs, and every real edge gets
+// one select.  Flooding folds the parity of the previous decision into
+// `parity` (as fused_half_row); layered writes L = q + r at once.
+template <class A, int D, bool LAYERED, class Row>
+__device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, typename A::T *__restrict__ sR,
+                                            typename A::T *__restrict__ sL, bool first, uint32_t &parity,
+                                            typename A::T scale, typename A::T offset)
+{
+    using T = typename A::T;
+    T q[D];
+    MinState<T> st;
+    min_init(st);
+    uint32_t par = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const bool real = j < dh;
+        const int32_t ri = real ? row.ridx(k0 + j) : 0;
+        const T l = sL[real ? row.col(k0 + j) : 0];
+        const T rr = first ? T(0) : sR[ri];
+        par ^= static_cast<uint32_t>(real && l < T(0));
+        q[j] = first ? l : l - rr;
+        if (real)
+            min_add(st, q[j], k0 + j);
+    }
+    const T o_m1 = pair_swap(st.m1), o_m2 = pair_swap(st.m2);
+    const int32_t o_idx = static_cast<int32_t>(pair_swap(static_cast<uint32_t>(st.idx)));
+    const uint32_t o_neg = pair_swap(st.neg);
+    min_merge(st, o_m1, o_m2, o_idx, o_neg);
+    if (!LAYERED)
+        parity |= par ^ pair_swap(par);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        if (j < dh) {
+            const T r = min_message<A>(st, q[j], k0 + j, scale, offset);
+            sR[row.ridx(k0 + j)] = r;
+            if (LAYERED)
+                sL[row.col(k0 + j)] = q[j] + r;
+        }
+    }
+}
+
 // Column sum L = Lch + sum of r in ascending row order, run-time degree dv <= D
 // (dummy edges read slot 0 and are not added).
 template <class A, int D, class Edge>
@@ -295,6 +340,8 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
     __syncthreads();
 
     const bool es = (job.flags & LDPC_EARLY_STOP) != 0;
+    const bool ms = (job.flags & LDPC_MIN_SUM) != 0;
+    const T ms_scale = static_cast<T>(job.ms_scale), ms_offset = static_cast<T>(job.ms_offset * A::kIn);
     int32_t it = job.max_iter;
     for (int32_t t = 1; t <= job.max_iter; ++t) {
         const bool first = (t == 1);
@@ -316,13 +363,23 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
                 d = rbs[i + 1] - rbs[i];
                 const int32_t h = (d + 1) >> 1;
                 const RowQC row{rbs[i], r, Z, pack};
-                fused_row_dispatch<A, 1, DB / 2>(hwave, row, half ? h : 0, half ? d - h : h, sR, sL, first, parity);
+                if (ms)
+                    ms_half_row<A, DB / 2, false>(row, half ? h : 0, half ? d - h : h, sR, sL, first, parity, ms_scale,
+                                                  ms_offset);
+                else
+                    fused_row_dispatch<A, 1, DB / 2>(hwave, row, half ? h : 0, half ? d - h : h, sR, sL, first,
+                                                     parity);
             } else {
                 const int32_t e0 = c.row_ptr[s];
                 d = c.row_ptr[s + 1] - e0;
                 const int32_t h = (d + 1) >> 1;
                 const RowCSR row{e0, c.col_idx};
-                fused_row_dispatch<A, 1, DB / 2>(hwave, row, half ? h : 0, half ? d - h : h, sR, sL, first, parity);
+                if (ms)
+                    ms_half_row<A, DB / 2, false>(row, half ? h : 0, half ? d - h : h, sR, sL, first, parity, ms_scale,
+                                                  ms_offset);
+                else
+                    fused_row_dispatch<A, 1, DB / 2>(hwave, row, half ? h : 0, half ? d - h : h, sR, sL, first,
+                                                     parity);
             }
         }
         const int unsat = __syncthreads_or(static_cast<int>(parity));
@@ -417,6 +474,9 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
     };
 
     const bool es = (job.flags & LDPC_EARLY_STOP) != 0;
+    const bool ms = (job.flags & LDPC_MIN_SUM) != 0;
+    const T ms_scale = static_cast<T>(job.ms_scale), ms_offset = static_cast<T>(job.ms_offset * A::kIn);
+    uint32_t no_parity = 0;
     int32_t it = job.max_iter;
     if (es && !unsatisfied()) {
         it = 0;
@@ -431,7 +491,12 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
                         if (d == 0 || r >= Z)
                             continue;
                         const RowQC row{b0, r, Z, pack};
-                        layered_row_dispatch<A, 1, DB / 2>(h, row, half ? h : 0, half ? d - h : h, sR, sL, first);
+                        if (ms)
+                            ms_half_row<A, DB / 2, true>(row, half ? h : 0, half ? d - h : h, sR, sL, first,
+                                                         no_parity, ms_scale, ms_offset);
+                        else
+                            layered_row_dispatch<A, 1, DB / 2>(h, row, half ? h : 0, half ? d - h : h, sR, sL,
+                                                               first);
                     }
                     __syncthreads();
                 }
@@ -447,7 +512,12 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
                             continue;
                         const int32_t h = (d + 1) >> 1;
                         const RowCSR row{e0, c.col_idx};
-                        layered_row_dispatch<A, 1, DB / 2>(h, row, half ? h : 0, half ? d - h : h, sR, sL, first);
+                        if (ms)
+                            ms_half_row<A, DB / 2, true>(row, half ? h : 0, half ? d - h : h, sR, sL, first,
+                                                         no_parity, ms_scale, ms_offset);
+                        else
+                            layered_row_dispatch<A, 1, DB / 2>(h, row, half ? h : 0, half ? d - h : h, sR, sL,
+                                                               first);
                     }
                     __syncthreads();
                 }

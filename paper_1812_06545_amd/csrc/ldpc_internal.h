@@ -108,8 +108,12 @@ ldpc_status launch_copy16(void *dst, const void *src, size_t bytes, hipStream_t 
 
 // Streaming (per-iteration) path.
 size_t stream_workspace_bytes(const ldpc_code_s *c, ldpc_dtype dt, int32_t frames, int32_t max_iter);
+// ms_scale / ms_offset: the min-sum magnitude correction (used with
+// LDPC_MIN_SUM; natural-LLR units).
 ldpc_status stream_decode(const ldpc_code_s *c, ldpc_dtype dt, int32_t frames, int32_t max_iter, uint32_t flags,
                           const void *llr, uint8_t *bits, int32_t *iters, void *posterior, void *ws,
-                          hipStream_t stream);
+                          hipStream_t stream, double ms_scale, double ms_offset);
+// scale finite and > 0, offset finite and >= 0.
+bool minsum_params_ok(double scale, double offset);
 
 }  // namespace ldpc

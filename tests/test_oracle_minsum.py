@@ -4,11 +4,15 @@ plausible slip, compiled to a temporary library and run through every pin;
 at least one pin must fail.  (Taking sgn(0) = -1 is no mutant: an exactly
 zero incoming message makes every other message of its row zero in
 magnitude, so its sign can only turn +0 into -0, which no output shows.)"""
+import ctypes
+
+import numpy as np
 import pytest
 
 import oracle
 import pins_minsum
 from oracle.build import SRC_MINSUM, compile_oracle
+from workloads import configs
 
 
 def _dec(lib=None):
@@ -55,3 +59,61 @@ def test_minsum_mutant_is_caught(name, tmp_path):
         except (AssertionError, ValueError, FloatingPointError):
             failed.append(check.__name__)
     assert failed, f"mutant {name} passed every pin"
+
+
+def _noisy_minsum_lib(tmp_path):
+    """The min-sum oracle with relative noise of 6e-8 (one FP32 rounding)
+    injected into every q, r and L it forms."""
+    src = open(SRC_MINSUM).read()
+    src = src.replace("#define ORACLE_ENOMEM (-2)", """#define ORACLE_ENOMEM (-2)
+static unsigned long long g_state = 1;
+void noise_seed(unsigned long long s) { g_state = s; }
+static double noise(double v)
+{
+    g_state = g_state * 6364136223846793005ULL + 1442695040888963407ULL;
+    const double u = (double)(g_state >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    return v * (1.0 + u * 6e-8);
+}""")
+    edits = [("    return negative ? -mag : mag;", "    return noise(negative ? -mag : mag);"),
+             ("                    L[j] = s;", "                    L[j] = noise(s);"),
+             ("                        q[g->col_edge[k]] = s - r[g->col_edge[k]];",
+              "                        q[g->col_edge[k]] = noise(s - r[g->col_edge[k]]);"),
+             ("                        q[e] = L[g->col_idx[e]] - r[e];", "                        q[e] = noise(L[g->col_idx[e]] - r[e]);"),
+             ("                        L[g->col_idx[e]] = q[e] + r[e];", "                        L[g->col_idx[e]] = noise(q[e] + r[e]);")]
+    for old, new in edits:
+        assert src.count(old) == 1, old
+        src = src.replace(old, new)
+    path = tmp_path / "noisy_minsum.c"
+    path.write_text(src)
+    lib = oracle._load(compile_oracle(str(path), str(tmp_path / "libnoisy_minsum.so"), extra=("-Wno-error",)))
+    lib.noise_seed.argtypes = [ctypes.c_ulonglong]
+    return lib
+
+
+def _spread(lib, code, llr, T, schedule, scale, offset, seeds=(1, 2, 3)):
+    base = oracle.decode(code, llr, T, False, rule="minsum", ms_scale=scale, ms_offset=offset, schedule=schedule,
+                         nthreads=4)
+    scale_n = np.maximum(np.abs(base["posterior"]), base["cond"])
+    worst = 0.0
+    for seed in seeds:
+        lib.noise_seed(seed)
+        o = oracle.decode(code, llr, T, False, rule="minsum", ms_scale=scale, ms_offset=offset, schedule=schedule,
+                          nthreads=1, lib=lib)
+        worst = max(worst, float((np.abs(o["posterior"] - base["posterior"]) / scale_n).max()))
+    return worst
+
+
+def test_fp32_rounding_horizon(tmp_path):
+    """Justifies the horizons of the FP32 min-sum parity tests, on their input
+    (qc1944, 2.0 dB, 100 frames): FP32-sized rounding noise in the FP64
+    min-sum oracle stays below half the 1e-4 bar at 4 flooding iterations
+    and 1 layered pass for all three corrections tested, and exceeds the bar
+    by 10 iterations (plain min-sum) or 3 passes: past those horizons no
+    FP32 implementation can be held to it."""
+    lib = _noisy_minsum_lib(tmp_path)
+    b = configs.qc1944(2.0, frames=100)
+    for scale, offset in ((1.0, 0.0), (0.75, 0.0), (1.0, 0.5)):
+        assert _spread(lib, b.code, b.llr, 4, "flooding", scale, offset) < 0.5e-4
+        assert _spread(lib, b.code, b.llr, 1, "layered", scale, offset) < 0.5e-4
+    assert _spread(lib, b.code, b.llr, 10, "flooding", 1.0, 0.0) > 1e-4
+    assert _spread(lib, b.code, b.llr, 3, "layered", 1.0, 0.0) > 1e-4
