@@ -171,6 +171,7 @@ def main():
         other_path = batch_path_run(h, llrs, bits, iters, post, F, n, T, args.steps)
     extra = None if args.no_extra else extra_workloads()
     layered = None if args.no_extra else layered_workloads(args.steps)
+    minsum = None if args.no_extra else minsum_workloads(args.steps)
 
     copy = copy_probe(args.copy_probe_mb) if args.copy_probe_mb > 0 else None
     if copy and achieved:
@@ -205,6 +206,7 @@ def main():
         "batch_path": other_path,
         "other_workloads": extra,
         "layered": layered,
+        "min_sum": minsum,
         "copy_probe": copy,
         "serving": serving,
         "cpu_baseline": cpu,
@@ -361,12 +363,65 @@ def layered_workloads(steps):
     return out
 
 
+def minsum_workloads(steps):
+    """The min-sum check rule (LDPC_MIN_SUM), HIP-event timed:
+    - qc1944 2.0 dB, 4096 frames, 10 iterations, normalised min-sum (scale
+      0.75), plain flooding path: Mbit/s and the min-sum check kernel's
+      achieved bandwidth on the sum-product check kernel's algorithmic bytes
+      (no transcendentals: the kernel is a pure HBM stream); the fused path
+      and the layered schedule on the same input;
+    - early stop (max 20) at 3.5 dB against sum-product, plain flooding."""
+    import torch
+
+    import paper_1812_06545_amd as L
+    from workloads import configs
+    out = {}
+    b = configs.qc1944(2.0)
+    F, n, E = b.llr.shape[0], b.code.n, b.code.edges
+    h = L.Code.from_workload(b.code)
+    x = torch.from_numpy(b.llr).cuda()
+    ws = torch.empty(L.ldpc_workspace_bytes(h, torch.float32, F, 20), dtype=torch.uint8, device="cuda")
+
+    def plain(layered=False, T=10, es=False, llr=x, rule="minsum"):
+        return lambda: L.decode(h, llr, T, early_stop=es, layered=layered, rule=rule, ms_scale=0.75, workspace=ws)
+    ms = _time_ms(plain(), steps)
+    L.ldpc_profile_collect()
+    L.ldpc_profile_enable(True)
+    _time_ms(plain(), steps)
+    L.ldpc_profile_enable(False)
+    kms, kcount = L.ldpc_profile_collect()["check"]
+    bytes_per_launch = F * ((4 * E + 4 * n) + 9 * (8 * E + 4 * n)) / 10
+    achieved = bytes_per_launch / (kms / kcount * 1e-3) / 1e9 if kcount else None
+    fused = _batch_ms(L, [(h, x, 10, False, False, "minsum", 0.75)], torch.float32, steps, tune=True)
+    lay = _time_ms(plain(layered=True), steps)
+    out["qc1944_2dB_10it_nms0.75"] = {
+        "plain_ms": ms, "plain_mbps": F * n / (ms * 1e-3) / 1e6,
+        "check_kernel": {"avg_us": kms * 1e3 / max(kcount, 1), "bytes_per_launch": bytes_per_launch,
+                         "achieved_gbs": achieved, "frac_of_peak": achieved / HBM_PEAK_GBS if achieved else None},
+        "batch_ms": fused, "batch_mbps": F * n / (fused * 1e-3) / 1e6,
+        "layered_plain_ms": lay, "layered_plain_mbps": F * n / (lay * 1e-3) / 1e6}
+    hi = torch.from_numpy(configs.qc1944(3.5).llr).cuda()
+    res = {}
+    for name, rule in (("sum_product", "spa"), ("min_sum_0.75", "minsum")):
+        got = {}
+
+        def run():
+            got["o"] = plain(T=20, es=True, llr=hi, rule=rule)()
+        t = _time_ms(run, 5)
+        it = got["o"][1].float()
+        res[name] = {"plain_ms": t, "mean_iters": float(it.mean().item()),
+                     "unconverged": float((it == 20).float().mean().item())}
+    out["qc1944_3.5dB_early_stop20"] = res
+    return out
+
+
 def _batch_ms(L, items, dtype, reps, tune=False):
     """HIP-event time of one ldpc_decode_batch over items (handle, llr tensor,
-    max_iter, early_stop, layered); with tune, after ldpc_autotune_batch has
-    picked the workgroup size for this batch shape."""
+    max_iter, early_stop, layered[, rule, min-sum scale]); with tune, after
+    ldpc_autotune_batch has picked the workgroup size for this batch shape."""
     import torch
-    jobs = [L.Job(hh, x, T, early_stop=es, layered=lay) for hh, x, T, es, lay in items]
+    jobs = [L.Job(hh, x, T, early_stop=es, layered=lay, rule=rest[0] if rest else "spa",
+                  ms_scale=rest[1] if rest else 1.0) for hh, x, T, es, lay, *rest in items]
     if tune:
         L.autotune_batch(jobs)
     cj = [j.c_struct() for j in jobs]
