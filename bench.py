@@ -172,6 +172,7 @@ def main():
     extra = None if args.no_extra else extra_workloads()
     layered = None if args.no_extra else layered_workloads(args.steps)
     minsum = None if args.no_extra else minsum_workloads(args.steps)
+    mstream = None if args.no_extra else mstream_run()
 
     copy = copy_probe(args.copy_probe_mb) if args.copy_probe_mb > 0 else None
     if copy and achieved:
@@ -207,6 +208,7 @@ def main():
         "other_workloads": extra,
         "layered": layered,
         "min_sum": minsum,
+        "multi_stream_baseline": mstream,
         "copy_probe": copy,
         "serving": serving,
         "cpu_baseline": cpu,
@@ -413,6 +415,58 @@ def minsum_workloads(steps):
                      "unconverged": float((it == 20).float().mean().item())}
     out["qc1944_3.5dB_early_stop20"] = res
     return out
+
+
+def mstream_run():
+    """The paper's multi-stream structure (ldpc_mstream_run: W host workers,
+    each with its own stream and F frames per batch; host LLRs in, host bits
+    out, copies included) on qc1944 frames at 2.0 dB, 10 iterations, against
+    the same frames through one ldpc_decode_batch launch per 32768-frame
+    batch with the same host copies around it; throughput and the host CPU
+    time the structure costs (workers wait on blocking events)."""
+    import numpy as np
+    import torch
+
+    import paper_1812_06545_amd as L
+    from workloads import configs
+    b = configs.qc1944(2.0)
+    h = L.Code.from_workload(b.code)
+    total = 32768
+    llr = np.ascontiguousarray(np.tile(b.llr, (total // b.llr.shape[0], 1)))
+    bits = np.zeros((total, b.code.n), np.uint8)
+    iters = np.zeros(total, np.int32)
+    rows = []
+    for W, F in ((1, 4096), (2, 4096), (4, 2048), (8, 1024), (4, 4096), (8, 4096)):
+        L.ldpc_mstream_run(h, W, F, min(2 * W, total // F), 10, 0, 1, llr, bits, iters)  # warm-up
+        rc, st = L.ldpc_mstream_run(h, W, F, total // F, 10, 0, 1, llr, bits, iters)
+        if rc != 0:
+            raise RuntimeError(f"ldpc_mstream_run failed: {rc}")
+        rows.append({"workers": W, "frames_per_batch": F, "mbps": st["mbps"], "wall_ms": st["wall_ms"],
+                     "host_cores_busy": st["cpu_cores_busy"], "host_cpu_load": st["cpu_load"]})
+    # one device-side launch over all frames, with the same host copies around it
+    x = torch.empty((total, b.code.n), dtype=torch.float32, pin_memory=True)
+    job = L.Job(h, torch.empty((total, b.code.n), dtype=torch.float32, device="cuda"), 10, want_posterior=False)
+    cj = [job.c_struct()]
+    nb = L.ldpc_batch_workspace_bytes(cj, torch.float32)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+    out_bits = torch.empty((total, b.code.n), dtype=torch.uint8, pin_memory=True)
+
+    def one():
+        x.numpy()[:] = llr
+        job.llr.copy_(x, non_blocking=True)
+        if L.ldpc_decode_batch(cj, torch.float32, ws, nb) != 0:
+            raise RuntimeError("ldpc_decode_batch failed")
+        out_bits.copy_(job.bits, non_blocking=True)
+        torch.cuda.synchronize()
+        bits[:] = out_bits.numpy()
+    one()
+    t0 = time.perf_counter()
+    one()
+    wall = time.perf_counter() - t0
+    return {"workload": "qc1944 2.0 dB frames (4096 tiled to 32768), 10 iterations, FP32, host LLRs in and host "
+                        "bits out",
+            "multi_stream": rows,
+            "one_launch_with_copies": {"mbps": total * b.code.n / wall / 1e6, "wall_ms": wall * 1e3}}
 
 
 def _batch_ms(L, items, dtype, reps, tune=False):

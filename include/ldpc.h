@@ -352,6 +352,35 @@ ldpc_status ldpc_profile_enable(int enable);
 ldpc_status ldpc_profile_collect(double *ms, int64_t *counts);
 
 /*
+ * The paper's multi-stream structure (Section III-C), as a measured baseline:
+ * `workers` host threads, each with its own stream, pinned staging and
+ * device buffers for `frames_per_batch` frames, take batches of frames in
+ * turn; a worker copies its batch's LLRs (host memory, float, [batches *
+ * frames_per_batch][n], read only) into pinned staging and to the device,
+ * decodes them with ldpc_decode (flags as there; FP32), copies bits and
+ * iteration counts back, waits for its stream (spinning, or blocking on the
+ * event when blocking_sync != 0) and copies the results into bits
+ * ([batches * frames_per_batch][n]) and iters.  Blocks until every batch is
+ * done.  *stats (may be NULL) receives wall time, throughput and the
+ * process's CPU time over the run (getrusage: user + system, all threads).
+ * EINVAL for bad sizes or flags, ENOMEM if buffers cannot be allocated,
+ * EDEVICE (or a decode error) if a worker's call fails.
+ */
+typedef struct {
+    double wall_ms;        /* first batch taken to last result copied */
+    double frames_per_s;
+    double mbps;           /* coded bits: frames * n per second, 1e6 */
+    double cpu_ms;         /* process CPU time (user + system) during the run */
+    double cpu_cores_busy; /* cpu_ms / wall_ms: host cores kept busy on average */
+    double cpu_load;       /* cpu_cores_busy / online_cores */
+    int32_t online_cores;
+} ldpc_mstream_stats;
+
+ldpc_status ldpc_mstream_run(ldpc_code code, int32_t workers, int32_t frames_per_batch, int32_t batches,
+                             int32_t max_iter, uint32_t flags, int32_t blocking_sync, const float *llr, uint8_t *bits,
+                             int32_t *iters, ldpc_mstream_stats *stats);
+
+/*
  * Streaming copy of `bytes` (a multiple of 16; both pointers 16-byte aligned,
  * device memory) on `stream`: a yardstick for achievable HBM bandwidth and
  * for scaling hardware byte counters.  Not part of decoding.

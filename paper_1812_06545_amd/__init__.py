@@ -212,6 +212,35 @@ def ldpc_decode_minsum(handle, dtype, frames, max_iter, flags, ms_scale, ms_offs
                                    _ptr(posterior), _ptr(workspace), int(workspace_bytes), _stream_handle(stream))
 
 
+class ldpc_mstream_stats(ctypes.Structure):
+    _fields_ = [("wall_ms", ctypes.c_double), ("frames_per_s", ctypes.c_double), ("mbps", ctypes.c_double),
+                ("cpu_ms", ctypes.c_double), ("cpu_cores_busy", ctypes.c_double), ("cpu_load", ctypes.c_double),
+                ("online_cores", _I32)]
+
+
+_sig("ldpc_mstream_run", ctypes.c_int, [_P, _I32, _I32, _I32, _I32, ctypes.c_uint32, _I32, _P, _P, _P,
+                                        ctypes.POINTER(ldpc_mstream_stats)])
+
+
+def ldpc_mstream_run(handle, workers, frames_per_batch, batches, max_iter, flags, blocking_sync, llr, bits, iters):
+    """The multi-stream baseline over host numpy arrays (llr float32
+    [batches * frames_per_batch, n]); returns (status, stats dict)."""
+    def hp(a):
+        if a is None or isinstance(a, int):
+            return a
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    need = int(batches) * int(frames_per_batch)
+    if need > 0 and not isinstance(llr, int):
+        n = ldpc_code_info(handle)[1]
+        if llr.size < need * n or bits.size < need * n or iters.size < need:
+            raise ValueError("host arrays smaller than batches * frames_per_batch frames")
+    st = ldpc_mstream_stats()
+    rc = _lib.ldpc_mstream_run(_handle(handle), int(workers), int(frames_per_batch), int(batches), int(max_iter),
+                               int(flags), int(bool(blocking_sync)), hp(llr), hp(bits), hp(iters), ctypes.byref(st))
+    return rc, {name: getattr(st, name) for name, _ in st._fields_}
+
+
 def _jobs_array(jobs):
     arr = (ldpc_job * max(len(jobs), 1))()
     for i, j in enumerate(jobs):
