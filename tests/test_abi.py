@@ -78,3 +78,13 @@ def test_batch_rejects_and_empty():
     assert lib.ldpc_decode_batch(None, 0, 7, None, 0, None) == L.LDPC_EINVAL  # bad dtype
     job = L.ldpc_job(None, 4, 10, 0, None, None, None, None)
     assert L.library().ldpc_decode_batch(ctypes.byref(job), 1, 0, None, 0, None) == L.LDPC_EINVAL
+
+
+def test_minsum_and_mstream_argument_errors_without_device():
+    """Argument errors of the min-sum entry point and the multi-stream
+    baseline are reported before any device call."""
+    lib = L.library()
+    assert lib.ldpc_decode_minsum(None, 0, 1, 10, L.LDPC_MIN_SUM, 1.0, 0.0, None, None, None, None, None, 0,
+                                  None) == L.LDPC_EINVAL
+    assert lib.ldpc_mstream_run(None, 1, 64, 1, 10, 0, 1, None, None, None, None) == L.LDPC_EINVAL
+

@@ -170,7 +170,7 @@ def test_frames_zero_and_errors(L):
     ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
     assert L.ldpc_decode(h.handle, torch.float32, 0, 10, 0, llr, bits, iters, None, ws, need) == L.LDPC_OK
     assert L.ldpc_decode(h.handle, torch.float32, 64, 10, 0, llr, bits, iters, None, ws, need - 1) == L.LDPC_EINVAL
-    assert L.ldpc_decode(h.handle, torch.float32, 64, 10, 4, llr, bits, iters, None, ws, need) == L.LDPC_EINVAL
+    assert L.ldpc_decode(h.handle, torch.float32, 64, 10, 8, llr, bits, iters, None, ws, need) == L.LDPC_EINVAL
     assert L.ldpc_decode(h.handle, torch.float32, 64, -1, 0, llr, bits, iters, None, ws, need) == L.LDPC_EINVAL
     assert L.ldpc_decode(h.handle, torch.float32, 64, 10, 0, None, bits, iters, None, ws, need) == L.LDPC_EINVAL
     misaligned = ws.data_ptr() + 16
