@@ -11,6 +11,12 @@ are resident in HBM and the steps cycle through them.
 Prints one JSON line: throughput (coded bits per second of device time), the
 dominant kernel's roofline position measured with HIP events inside the
 timed region, and the CPU oracle timed on the host on a bounded sample.
+Beside the headline (skipped with --no-extra unless noted) it reports: the
+same workload through the fused batch kernel; the other seeded workloads
+(gallager504 FP64, the 12-code mix, stair64800); the layered schedule and
+the min-sum rule on qc1944; the paper's multi-stream structure over host
+buffers; the copy probe (--copy-probe-mb); an open-loop serving run
+(--serve-seconds); the CPU oracle (--no-cpu-baseline skips it).
 """
 from __future__ import annotations
 

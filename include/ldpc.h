@@ -1,6 +1,6 @@
 /*
- * ldpc.h - C ABI of libldpc: flooding sum-product LDPC decoding on AMD
- * Instinct MI355X (gfx950).
+ * ldpc.h - C ABI of libldpc: LDPC belief-propagation decoding (sum-product
+ * or min-sum; flooding or layered schedule) on AMD Instinct MI355X (gfx950).
  *
  * The operation (arxiv 1812.06545, Section II): a binary LDPC code is given by
  * its sparse m x n parity-check matrix H (H[i][j] = 1 joins check node i to
