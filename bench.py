@@ -517,7 +517,7 @@ def copy_probe(mb):
     return {"bytes": 2 * nbytes, "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
-def serve_run(seconds, rate):
+def serve_run(seconds, rate, max_group_frames=1024, max_inflight=3):
     """Open-loop serving run: Poisson arrivals of decode requests (1-64 frames
     of one of the 12 QC codes, Eb/N0 uniform in [1, 3] dB per frame, 10
     iterations with early stop) submitted at their scheduled times; latency is
@@ -546,7 +546,7 @@ def serve_run(seconds, rate):
                      llr[rq.code_id].ctypes.data + start * n * llr[rq.code_id].itemsize,
                      outs[rq.code_id][0].ctypes.data, outs[rq.code_id][1].ctypes.data))
     lag = np.zeros(len(plan), np.int64)
-    srv = L.ldpc_server_create(handles, 512 << 20, max_inflight=3, max_group_frames=1024)
+    srv = L.ldpc_server_create(handles, 512 << 20, max_inflight=max_inflight, max_group_frames=max_group_frames)
     try:
         # warm-up: one request per code
         for cid in range(12):

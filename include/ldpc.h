@@ -228,13 +228,16 @@ void ldpc_plan_destroy(ldpc_plan plan);
  * requests, first come first served, whenever arena memory (fixed at
  * creation, sized by mem_budget_bytes) and one of max_inflight launch slots
  * are free; each admitted group's LLRs are packed contiguously in pinned host
- * memory, moved to the device by one copy kernel and decoded by one
- * ldpc_decode_batch call on the slot's own stream (so a group admitted while
- * others run overlaps with them on the device); the decode kernel writes the
- * results into pinned host memory, from which the scheduler fills the
- * requester's buffers and marks the request done.  The requester's LLRs are
- * read when the group is admitted, so they must stay valid until the request
- * completes.  Every frame's result equals decoding it alone.
+ * memory, ordered by code (then iteration limit, flags and whether
+ * posteriors are wanted; FIFO within each) so that neighbouring requests
+ * decoded alike form one job, moved to the device by one copy kernel and
+ * decoded by one ldpc_decode_batch call on the slot's own stream (so a group
+ * admitted while others run overlaps with them on the device); the decode
+ * kernel writes the results into pinned host memory, from which the
+ * scheduler fills the requester's buffers and marks the request done.  The
+ * requester's LLRs are read when the group is admitted, so they must stay
+ * valid until the request completes.  Every frame's result equals decoding it
+ * alone.
  * Codes must fit the fused kernel (ldpc_batch_fits_fused), all FP32.
  */
 typedef struct ldpc_server_s *ldpc_server;

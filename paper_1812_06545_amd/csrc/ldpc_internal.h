@@ -105,6 +105,9 @@ class ProfScope {
 // streaming copy kernel on `stream`; either side may be pinned host memory
 // mapped for the device.
 ldpc_status launch_copy16(void *dst, const void *src, size_t bytes, hipStream_t stream);
+// The same copy on a grid of at most max_blocks workgroups of 256 threads,
+// for copies that cross the host link while other kernels run.
+ldpc_status launch_link_copy16(void *dst, const void *src, size_t bytes, int32_t max_blocks, hipStream_t stream);
 
 // Streaming (per-iteration) path.
 size_t stream_workspace_bytes(const ldpc_code_s *c, ldpc_dtype dt, int32_t frames, int32_t max_iter);

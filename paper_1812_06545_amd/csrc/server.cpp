@@ -21,8 +21,10 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdint>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -85,6 +87,112 @@ class RangeAlloc {
 // 16-byte aligned, as the copy kernel needs.
 inline int64_t align4(int64_t e) { return (e + 3) & ~int64_t(3); }
 
+// Workgroups of the staging copy (pinned host -> device arena): enough to
+// keep the host link busy, few enough that the decode kernels of the other
+// slots keep their compute units while it runs.
+constexpr int32_t kLinkCopyBlocks = 64;
+
+// Host copies of one group (LLRs into staging, results out of it), split over
+// helper threads when the group is large: one thread copies about 10 GB/s,
+// and near capacity the next group's admission waits on these copies (the
+// tail latency grows several-fold without the helpers).  The calling (scheduler)
+// thread takes one share and each helper another; destinations are
+// disjoint, so the shares are independent.  Only the scheduler calls run().
+class CopyPool {
+  public:
+    struct Item {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    };
+    static constexpr size_t kParallelBytes = 256 << 10;  // smaller groups are copied by the caller alone
+
+    explicit CopyPool(int helpers)
+    {
+        parts_.resize(static_cast<size_t>(helpers) + 1);
+        for (int i = 0; i < helpers; ++i)
+            threads_.emplace_back([this, i] { loop(i + 1); });
+    }
+    ~CopyPool()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        go_.notify_all();
+        for (std::thread &t : threads_)
+            t.join();
+    }
+
+    void run(const std::vector<Item> &items)
+    {
+        size_t total = 0;
+        for (const Item &it : items)
+            total += it.bytes;
+        if (threads_.empty() || total < kParallelBytes) {
+            for (const Item &it : items)
+                if (it.bytes)
+                    std::memcpy(it.dst, it.src, it.bytes);
+            return;
+        }
+        // cut the items into parts of about total / parts bytes each
+        const size_t nparts = parts_.size(), share = (total + nparts - 1) / nparts;
+        for (auto &p : parts_)
+            p.clear();
+        size_t part = 0, room = nparts == 1 ? SIZE_MAX : share;
+        for (const Item &it : items) {
+            size_t off = 0;
+            while (off < it.bytes) {
+                const size_t take = std::min(room, it.bytes - off);
+                parts_[part].push_back({static_cast<char *>(it.dst) + off, static_cast<const char *>(it.src) + off, take});
+                off += take;
+                room -= take;
+                if (room == 0 && part + 1 < nparts) {
+                    ++part;
+                    room = part + 1 == nparts ? SIZE_MAX : share;  // the last part takes whatever is left
+                }
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            remaining_ = static_cast<int>(threads_.size());
+            ++gen_;
+        }
+        go_.notify_all();
+        for (const Item &it : parts_[0])
+            std::memcpy(it.dst, it.src, it.bytes);
+        std::unique_lock<std::mutex> lk(mu_);
+        done_.wait(lk, [&] { return remaining_ == 0; });
+    }
+
+  private:
+    void loop(size_t me)
+    {
+        uint64_t seen = 0;
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            go_.wait(lk, [&] { return stop_ || gen_ != seen; });
+            if (stop_)
+                return;
+            seen = gen_;
+            lk.unlock();
+            for (const Item &it : parts_[me])
+                std::memcpy(it.dst, it.src, it.bytes);
+            lk.lock();
+            if (--remaining_ == 0)
+                done_.notify_one();
+        }
+    }
+
+    std::vector<std::thread> threads_;
+    std::vector<std::vector<Item>> parts_;
+    std::mutex mu_;
+    std::condition_variable go_, done_;
+    uint64_t gen_ = 0;
+    int remaining_ = 0;
+    bool stop_ = false;
+};
+
 enum ReqState { kQueued = 0, kInFlight = 1, kDone = 2, kCancelled = 3 };
 
 struct Request {
@@ -118,7 +226,6 @@ struct ldpc_server_s {
     std::vector<ldpc_code> codes;
     std::vector<int32_t> code_n;
     int32_t max_group_frames = 0, max_queue = 0;
-    // device arena and its pinned host mirror (same offsets)
     // device arena of LLRs; pinned host memory for staged LLRs and results,
     // by its host (h_) and device (dh_) addresses; all share element offsets
     float *d_llr = nullptr;
@@ -135,6 +242,9 @@ struct ldpc_server_s {
     uint64_t next_ticket = 1;
     bool stop = false;
     std::thread sched;
+    std::unique_ptr<CopyPool> copies;  // used by the scheduler thread only
+    std::vector<CopyPool::Item> copy_items;
+    std::vector<ldpc_job> jobs;
 
     // statistics (guarded by mu)
     ldpc_server_stats st{};
@@ -157,14 +267,16 @@ bool ldpc_server_s::reap(std::unique_lock<std::mutex> &lk)
         if (!s.busy || hipEventQuery(s.done) != hipSuccess)
             continue;
         lk.unlock();
+        copy_items.clear();
         for (Request *r : s.reqs) {
             const int64_t n = code_n[r->code_id];
             const int64_t e = s.elem_begin + r->elem_off;
-            std::memcpy(r->bits, h_bits + e, static_cast<size_t>(r->frames * n));
-            std::memcpy(r->iters, h_iters + s.frame_begin + r->frame_off, sizeof(int32_t) * r->frames);
+            copy_items.push_back({r->bits, h_bits + e, static_cast<size_t>(r->frames * n)});
+            copy_items.push_back({r->iters, h_iters + s.frame_begin + r->frame_off, sizeof(int32_t) * r->frames});
             if (r->post)
-                std::memcpy(r->post, h_post + e, sizeof(float) * static_cast<size_t>(r->frames * n));
+                copy_items.push_back({r->post, h_post + e, sizeof(float) * static_cast<size_t>(r->frames * n)});
         }
+        copies->run(copy_items);
         const int64_t t = now_ns();
         lk.lock();
         for (Request *r : s.reqs) {
@@ -228,35 +340,58 @@ bool ldpc_server_s::admit(std::unique_lock<std::mutex> &lk)
             r->state = kInFlight;  // from here on cancel() refuses these requests
         // staging copies and launches run without the lock
         lk.unlock();
-        std::vector<ldpc_job> jobs;
-        jobs.reserve(k);
+        // The group's requests are laid out in the arena by code (and by
+        // iteration limit, flags and whether posteriors are wanted), FIFO
+        // within each, so that neighbours decoded alike merge into one job:
+        // a group of many small requests becomes a few jobs and fits one
+        // fused launch.
+        std::stable_sort(s.reqs.begin(), s.reqs.end(), [](const Request *a, const Request *b) {
+            if (a->code_id != b->code_id)
+                return a->code_id < b->code_id;
+            if (a->max_iter != b->max_iter)
+                return a->max_iter < b->max_iter;
+            if (a->flags != b->flags)
+                return a->flags < b->flags;
+            return (a->post != nullptr) < (b->post != nullptr);
+        });
+        jobs.clear();
+        copy_items.clear();
         int64_t eo = 0, fo = 0;
+        const Request *prev = nullptr;
         for (Request *r : s.reqs) {
             const int64_t n = code_n[r->code_id];
             r->elem_off = eo;
             r->frame_off = fo;
-            std::memcpy(h_llr + eb + eo, r->llr, sizeof(float) * static_cast<size_t>(r->frames * n));
-            ldpc_job j{};
-            j.code = codes[r->code_id];
-            j.frames = r->frames;
-            j.max_iter = r->max_iter;
-            j.flags = r->flags;
-            j.llr = d_llr + eb + eo;
-            j.bits = dh_bits + eb + eo;
-            j.iters = dh_iters + fb + fo;
-            j.posterior = r->post ? dh_post + eb + eo : nullptr;
+            copy_items.push_back({h_llr + eb + eo, r->llr, sizeof(float) * static_cast<size_t>(r->frames * n)});
+            if (prev && prev->code_id == r->code_id && prev->max_iter == r->max_iter && prev->flags == r->flags &&
+                (prev->post != nullptr) == (r->post != nullptr)) {
+                jobs.back().frames += r->frames;  // contiguous with the previous request's frames
+            } else {
+                ldpc_job j{};
+                j.code = codes[r->code_id];
+                j.frames = r->frames;
+                j.max_iter = r->max_iter;
+                j.flags = r->flags;
+                j.llr = d_llr + eb + eo;
+                j.bits = dh_bits + eb + eo;
+                j.iters = dh_iters + fb + fo;
+                j.posterior = r->post ? dh_post + eb + eo : nullptr;
+                jobs.push_back(j);
+            }
             s.want_post |= r->post != nullptr;
-            jobs.push_back(j);
+            prev = r;
             eo += r->frames * n;
             fo += r->frames;
         }
+        copies->run(copy_items);
         // The copy kernel moves the staged LLRs into the device arena (the
         // decode kernel reads them every iteration); the decode kernel writes
         // bits, iteration counts and posteriors straight into pinned host
         // memory (each once).  The runtime's copy calls are not used here:
         // they have been seen to block the calling thread for milliseconds.
         ldpc_status rc =
-            ldpc::launch_copy16(d_llr + eb, dh_llr + eb, sizeof(float) * static_cast<size_t>(align4(e)), s.stream);
+            ldpc::launch_link_copy16(d_llr + eb, dh_llr + eb, sizeof(float) * static_cast<size_t>(align4(e)),
+                                     kLinkCopyBlocks, s.stream);
         if (rc == LDPC_OK)
             rc = ldpc_decode_batch(jobs.data(), static_cast<int32_t>(jobs.size()), LDPC_F32, s.ws, s.ws_bytes,
                                    s.stream);
@@ -420,7 +555,7 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_serve
     std::memset(sv->h_llr, 0, big);  // the copies below leave zero LLRs for the warm-up decodes
     for (Slot &s : sv->slots) {
         for (const size_t len : {std::min<size_t>(big, 4096), big})
-            if (launch_copy16(sv->d_llr, sv->dh_llr, len, s.stream) != LDPC_OK) {
+            if (launch_link_copy16(sv->d_llr, sv->dh_llr, len, kLinkCopyBlocks, s.stream) != LDPC_OK) {
                 sv->free_all();
                 delete sv;
                 return LDPC_EDEVICE;
@@ -448,6 +583,8 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_serve
             return LDPC_EDEVICE;
         }
     }
+    const unsigned hw = std::thread::hardware_concurrency();
+    sv->copies.reset(new CopyPool(static_cast<int>(std::min(3u, hw > 4 ? hw / 4 : 0u))));
     sv->sched = std::thread([sv] { sv->run(); });
     *out = sv;
     return LDPC_OK;

@@ -159,3 +159,57 @@ def test_server_queue_limit(L, pool):
             assert L.ldpc_server_wait(srv, t, 60000.0) == 0
     finally:
         L.ldpc_server_destroy(srv)
+
+
+def test_server_merges_alike_requests(L, pool):
+    """Many small requests of a few codes with mixed iteration limits, flags
+    and posterior wishes: the scheduler lays each group out by code and
+    merges neighbours decoded alike into one job, so every group (at most
+    3 codes x 2 limits x 2 flag sets x 2 posterior wishes = 24 distinct jobs)
+    is one fused launch, and every request's result still equals decoding it
+    alone with its own settings."""
+    import torch
+    handles = [L.Code.from_workload(c) for c in pool.codes]
+    rng = np.random.default_rng(11)
+    reqs = []
+    for i in range(160):
+        cid = int(rng.choice([0, 5, 11]))
+        fr = int(rng.integers(1, 9))
+        req = configs.ServeRequest(0.0, cid, fr, float(rng.uniform(1.0, 3.0)))
+        llr, _ = pool.request_llr(7000 + i, req)
+        n = pool.codes[cid].n
+        reqs.append({"code": cid, "frames": fr, "llr": np.ascontiguousarray(llr), "T": int(rng.choice([5, 10])),
+                     "flags": int(rng.integers(2)), "bits": np.full((fr, n), 9, np.uint8),
+                     "iters": np.full(fr, -9, np.int32),
+                     "post": np.zeros((fr, n), np.float32) if rng.integers(2) else None})
+    srv = L.ldpc_server_create(handles, 64 << 20, max_inflight=2, max_group_frames=1024)
+    try:
+        L.ldpc_profile_collect()  # drop the creation warm-up's records
+        assert L.ldpc_profile_enable(True) == 0
+        L.ldpc_server_stats_get(srv, reset=True)
+        tickets = []
+        for r in reqs:
+            st, t = L.ldpc_server_submit(srv, r["code"], r["frames"], r["T"], r["flags"], r["llr"], r["bits"],
+                                         r["iters"], r["post"])
+            assert st == 0, st
+            tickets.append(t)
+        for t in tickets:
+            assert L.ldpc_server_wait(srv, t, 60000.0) == 0
+        stats = L.ldpc_server_stats_get(srv)
+        prof = L.ldpc_profile_collect()
+    finally:
+        L.ldpc_profile_enable(False)
+        L.ldpc_server_destroy(srv)
+    _log(f"[gpu] merge: {stats['launches']} groups, mean {stats['mean_group_frames']:.1f} frames, "
+         f"fused launches {prof['fused'][1]}")
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    assert stats["mean_group_frames"] > 16  # groups of several requests were formed
+    assert prof["fused"][1] == stats["launches"], "a group took more than one fused launch"
+    for k, r in enumerate(reqs):
+        bits, iters, post = L.decode(handles[r["code"]], torch.from_numpy(r["llr"]).cuda(), r["T"],
+                                     early_stop=bool(r["flags"]))
+        torch.cuda.synchronize()
+        assert np.array_equal(r["bits"], bits.cpu().numpy()), f"request {k} bits differ from alone"
+        assert np.array_equal(r["iters"], iters.cpu().numpy()), f"request {k} iters differ from alone"
+        if r["post"] is not None:
+            assert np.array_equal(r["post"], post.cpu().numpy()), f"request {k} posterior differs from alone"
