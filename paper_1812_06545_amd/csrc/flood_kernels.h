@@ -70,8 +70,9 @@ __device__ __forceinline__ void check_row(const int32_t *__restrict__ cols, cons
         lv[k] = ld_lane(L + cols[k] * kChunk, off);
         rv[k] = FIRST ? T(0) : ld_lane_nt(Rrow + k * kChunk, off);
     }
-    T a[D], p[D];
-    T acc0 = T(0), acc1 = T(0);
+    typename A::Term a[D];
+    typename A::Acc p[D];
+    typename A::Acc acc0 = A::identity(), acc1 = A::identity();
     uint32_t sign = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -80,7 +81,7 @@ __device__ __forceinline__ void check_row(const int32_t *__restrict__ cols, cons
         const T q = FIRST ? lv[k] : lv[k] - rv[k];
         check_forward<A>(q, a[k], p[k], k < H ? acc0 : acc1, sign);
     }
-    T s0 = T(0), s1 = T(0);
+    typename A::Acc s0 = A::identity(), s1 = A::identity();
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) {
         const T r = k < H ? check_backward<A>(a[k], p[k], s0, acc1, sign) : check_backward<A>(a[k], p[k], s1, acc0, sign);
@@ -105,8 +106,9 @@ __device__ __forceinline__ void check_row_guarded(const int32_t *__restrict__ co
             rv[k] = FIRST ? T(0) : ld_lane_nt(Rrow + k * kChunk, off);
         }
     }
-    T a[DMAX], p[DMAX];
-    T acc0 = T(0), acc1 = T(0);
+    typename A::Term a[DMAX];
+    typename A::Acc p[DMAX];
+    typename A::Acc acc0 = A::identity(), acc1 = A::identity();
     uint32_t sign = 0;
 #pragma unroll
     for (int k = 0; k < DMAX; ++k) {
@@ -120,7 +122,7 @@ __device__ __forceinline__ void check_row_guarded(const int32_t *__restrict__ co
                 check_forward<A>(q, a[k], p[k], acc1, sign);
         }
     }
-    T s0 = T(0), s1 = T(0);
+    typename A::Acc s0 = A::identity(), s1 = A::identity();
 #pragma unroll
     for (int k = DMAX - 1; k >= 0; --k) {
         if (k < d) {

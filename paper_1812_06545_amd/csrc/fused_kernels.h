@@ -17,9 +17,10 @@
 // Thread mapping: check rows are visited in slot order (for QC codes
 // block-rows sorted by decreasing degree).  A wavefront's 64 rows may differ
 // in degree; the wave runs the straight-line body of its largest degree and
-// pads shorter rows with dummy edges carrying q = +inf, whose phi is exactly
-// 0 and whose sign is +, so every real message is computed with exactly the
-// operations and rounding of the plain path (bit-identical results).
+// pads shorter rows with dummy edges carrying q = +inf, whose term is exactly
+// the identity of the row's combination and whose sign is +, so every real
+// message is computed with exactly the operations and rounding of the plain
+// path (bit-identical results).
 //
 // LDS per workgroup: r for every edge, the posterior L for every variable,
 // and the code's circulant-block tables (QC codes).
@@ -106,23 +107,29 @@ __device__ __forceinline__ uint32_t pair_swap(uint32_t v)
 }
 __device__ __forceinline__ float pair_swap(float v) { return __shfl_xor(v, 32); }
 __device__ __forceinline__ double pair_swap(double v) { return __shfl_xor(v, 32); }
+__device__ __forceinline__ ArithF32::Acc pair_swap(const ArithF32::Acc &v)
+{
+    return ArithF32::Acc{pair_swap(v.P), pair_swap(v.Q)};
+}
 
 // One half of a check row, run-time length dh <= D, as the straight-line
 // body of length D: this lane owns edges k0 .. k0+dh-1 of the row (the first
 // half, or the second), its partner lane the other half.  Edges j >= dh are
 // dummies: they read slot 0 (valid for any code with an edge) and enter as
-// q = +inf, r = 0, adding exact zeros and a + sign; nothing is written for
-// them.  The forward pass parks a_k in the edge's own r slot (free once q_k
-// is formed, owned by this lane alone) instead of a register array; after
-// the partner's half total and sign are exchanged, the backward pass reads
-// a_k back and overwrites the slot with the new message.
+// q = +inf, r = 0, whose terms are the exact identity of the combination
+// (t = 1, u = 0 in FP32; phi = 0 in FP64) with a + sign; nothing is written
+// for them.  The forward pass parks (part of) a_k in the edge's own r slot
+// (free once q_k is formed, owned by this lane alone) instead of a register
+// array; after the partner's half combination and sign are exchanged, the
+// backward pass reads a_k back and overwrites the slot with the new message.
 template <class A, int D, class Row>
 __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, typename A::T *__restrict__ sR,
                                                const typename A::T *__restrict__ sL, bool first, uint32_t &parity)
 {
     using T = typename A::T;
-    T p[D];
-    T acc = T(0);
+    typename A::Acc p[D];
+    typename A::Keep kp[D];
+    typename A::Acc acc = A::identity();
     uint32_t sign = 0, par = 0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -133,20 +140,21 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
         const T lv = real ? l : T(__builtin_huge_val());
         par ^= static_cast<uint32_t>(real && lv < T(0));
         const T q = first ? lv : lv - (real ? rr : T(0));
-        T a_k;
+        typename A::Term a_k;
         check_forward<A>(q, a_k, p[j], acc, sign);
+        kp[j] = A::keep(a_k);
         if (real)
-            sR[ri] = a_k;
+            sR[ri] = A::park(a_k);
     }
-    const T s_other = pair_swap(acc);
+    const typename A::Acc s_other = pair_swap(acc);
     const uint32_t sign_total = sign ^ pair_swap(sign);
     parity |= par ^ pair_swap(par);  // a lane may hold several rows: any unsatisfied row counts
-    T s = T(0);
+    typename A::Acc s = A::identity();
 #pragma unroll
     for (int j = D - 1; j >= 0; --j) {
         const bool real = j < dh;
         const int32_t ri = real ? row.ridx(k0 + j) : 0;
-        const T a_k = real ? sR[ri] : T(0);
+        const typename A::Term a_k = A::unpark(real ? sR[ri] : T(A::kDummyParked), kp[j]);
         const T r = check_backward<A>(a_k, p[j], s, s_other, sign_total);
         if (real)
             sR[ri] = r;
@@ -185,8 +193,9 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh,
                                                  typename A::T *__restrict__ sL, bool first)
 {
     using T = typename A::T;
-    T p[D];
-    T acc = T(0);
+    typename A::Acc p[D];
+    typename A::Keep kp[D];
+    typename A::Acc acc = A::identity();
     uint32_t sign = 0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -197,21 +206,22 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh,
         const T rr = first ? T(0) : sR[ri];
         const T lv = real ? l : T(__builtin_huge_val());
         const T q = first ? lv : lv - (real ? rr : T(0));
-        T a_k;
+        typename A::Term a_k;
         check_forward<A>(q, a_k, p[j], acc, sign);
+        kp[j] = A::keep(a_k);
         if (real) {
-            sR[ri] = a_k;
+            sR[ri] = A::park(a_k);
             sL[ci] = q;
         }
     }
-    const T s_other = pair_swap(acc);
+    const typename A::Acc s_other = pair_swap(acc);
     const uint32_t sign_total = sign ^ pair_swap(sign);
-    T s = T(0);
+    typename A::Acc s = A::identity();
 #pragma unroll
     for (int j = D - 1; j >= 0; --j) {
         const bool real = j < dh;
         const int32_t ri = real ? row.ridx(k0 + j) : 0;
-        const T a_k = real ? sR[ri] : T(0);
+        const typename A::Term a_k = A::unpark(real ? sR[ri] : T(A::kDummyParked), kp[j]);
         const T r = check_backward<A>(a_k, p[j], s, s_other, sign_total);
         if (real) {
             const int32_t ci = row.col(k0 + j);

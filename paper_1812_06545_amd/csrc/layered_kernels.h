@@ -9,8 +9,9 @@
 // Consecutive rows that share no variable commute, so a maximal run of them
 // (a layer: a block-row of a QC code) is one launch, one wavefront per row and
 // 64 frames; within a layer every L_n is read and written by one row only.
-// The check rule is the flooding path's (same two-half exclusive sums, same
-// phi evaluation), so a row gives the same messages for the same q.
+// The check rule is the flooding path's (same two-half exclusive
+// combinations, same arithmetic), so a row gives the same messages for the
+// same q.
 #pragma once
 
 #include "flood_kernels.h"
@@ -42,8 +43,9 @@ __device__ __forceinline__ void layer_row(const int32_t *__restrict__ cols, type
         q[k] = ld_lane(L + cols[k] * kChunk, off);
         rv[k] = FIRST ? T(0) : ld_lane_nt(Rrow + k * kChunk, off);
     }
-    T a[D], p[D];
-    T acc0 = T(0), acc1 = T(0);
+    typename A::Term a[D];
+    typename A::Acc p[D];
+    typename A::Acc acc0 = A::identity(), acc1 = A::identity();
     uint32_t sign = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -51,7 +53,7 @@ __device__ __forceinline__ void layer_row(const int32_t *__restrict__ cols, type
             q[k] = q[k] - rv[k];
         check_forward<A>(q[k], a[k], p[k], k < H ? acc0 : acc1, sign);
     }
-    T s0 = T(0), s1 = T(0);
+    typename A::Acc s0 = A::identity(), s1 = A::identity();
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) {
         const T r = k < H ? check_backward<A>(a[k], p[k], s0, acc1, sign) : check_backward<A>(a[k], p[k], s1, acc0, sign);
@@ -77,8 +79,9 @@ __device__ __forceinline__ void layer_row_guarded(const int32_t *__restrict__ co
             rv[k] = FIRST ? T(0) : ld_lane_nt(Rrow + k * kChunk, off);
         }
     }
-    T a[DMAX], p[DMAX];
-    T acc0 = T(0), acc1 = T(0);
+    typename A::Term a[DMAX];
+    typename A::Acc p[DMAX];
+    typename A::Acc acc0 = A::identity(), acc1 = A::identity();
     uint32_t sign = 0;
 #pragma unroll
     for (int k = 0; k < DMAX; ++k) {
@@ -91,7 +94,7 @@ __device__ __forceinline__ void layer_row_guarded(const int32_t *__restrict__ co
                 check_forward<A>(q[k], a[k], p[k], acc1, sign);
         }
     }
-    T s0 = T(0), s1 = T(0);
+    typename A::Acc s0 = A::identity(), s1 = A::identity();
 #pragma unroll
     for (int k = DMAX - 1; k >= 0; --k) {
         if (k < d) {

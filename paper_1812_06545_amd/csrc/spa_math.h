@@ -3,21 +3,35 @@
 //
 // Check rule (arxiv 1812.06545, Section I: belief propagation / sum-product;
 // Algorithm 1, Loop 2): r_mn = 2 atanh(prod_{n' != n} tanh(q_mn'/2)).
-// It is evaluated in the equivalent "phi" form: with
-//     phi(x) = -ln tanh(x/2) = ln((1 + e^-x) / (1 - e^-x))   (x >= 0),
-// prod tanh(|q|/2) = exp(-sum phi(|q|)) and 2 atanh(exp(-S)) = phi(S), so
-//     |r_mn| = phi( sum_{n' != n} phi(|q_mn'|) ),  sign = prod_{n' != n} sign(q_mn').
-// The exclusive sum is prefix + suffix (never total minus self, which cancels
-// catastrophically when one term dominates).
+// Signs and magnitudes separate: sign = prod sign(q_mn'), and the magnitude
+// follows from the |q|.  Each kernel evaluates a row as two halves with
+// prefix and suffix combinations (never "total minus self" or a division,
+// which cancel or fail when one term dominates or is zero), through an
+// arithmetic type A that supplies:
+//     Term  term(q)        per-edge quantity, q's sign in its sign bit;
+//     Acc   identity()     the empty combination;
+//     Acc   add(Acc, Term) combination grown by one edge;
+//     Acc   merge(Acc, Acc) combination of two disjoint edge sets;
+//     T     message(Acc)   |r| from the combination of the other edges,
+//                          clamped to R_MAX.
 //
-// FP32 runs in base-2 LLR units (every LLR multiplied by log2(e) on entry and
-// by ln 2 on exit), where phi becomes phi2(x) = log2((1 + 2^-x) / (1 - 2^-x))
-// and maps straight onto the hardware exp2 / log2 / reciprocal.  phi2 is
-// written as log2(1 + z), z = 2e / (1 - e), e = 2^-x, with the rounding error
-// of w = fl(1 + z) added back (c = (1 - w) + z is exact), which keeps the
-// result accurate to a few ulp when z is small (x large); for small x the
-// denominator 1 - e comes from a short series instead of the subtraction.  FP64 uses the
-// natural-log form with libm-quality exp / expm1 / log1p.
+// FP32 (base-2 LLR units: every LLR is multiplied by log2(e) on entry and by
+// ln 2 on exit) uses the product form directly.  An edge carries
+//     t = tanh(|q| ln2 / 2) = (1 - e) / (1 + e)   and   u = 1 - t = 2e / (1 + e),
+// with e = 2^-|q|, both to relative accuracy (1 - e for small |q| comes from a
+// short series instead of the subtraction).  A combination carries the
+// product P = prod t and its complement Q = 1 - P, the latter grown by
+// a (+) b = a + b - ab = 1 - (1 - a)(1 - b), so that Q stays accurate when P is
+// close to 1 (confident rows) just as P does when it is small.  The message
+// is 2 atanh(P) = log2((1 + P) / Q) = log2(1 + 2P / Q), with the rounding
+// error of w = fl(1 + z) added back (c = (1 - w) + z is exact for z < 1),
+// which keeps weak messages accurate.  Per edge: exp2 and one reciprocal
+// forward, one reciprocal and log2 back.
+//
+// FP64 uses the equivalent phi form with libm-quality exp / expm1 / log1p:
+//     phi(x) = -ln tanh(x/2) = log1p(2 e^-x / (1 - e^-x)),
+// prod tanh(|q|/2) = exp(-sum phi(|q|)) and 2 atanh(exp(-S)) = phi(S), so a
+// combination is the sum S of phi(|q|) and the message is phi(S).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,25 +46,63 @@ struct ArithF32 {
     static constexpr float kOut = 0.693147180559945309f; // internal -> natural LLR (ln 2)
     static constexpr float kRmax = 28.8539008177792681f; // R_MAX = 20 in internal units
 
-    __device__ static __forceinline__ float phi(float x)
+    struct Term {
+        float t;  // tanh(|q| ln2 / 2), with q's sign bit
+        float u;  // 1 - |t|
+    };
+    struct Acc {
+        float P;  // product of the |t|
+        float Q;  // 1 - P, formed from the u
+    };
+    // a (+) b = 1 - (1 - a)(1 - b) for a, b in [0, 1]
+    __device__ static __forceinline__ float oplus(float a, float b) { return __builtin_fmaf(-a, b, a + b); }
+
+    __device__ static __forceinline__ Acc identity() { return Acc{1.0f, 0.0f}; }
+    __device__ static __forceinline__ Term term(float q)
     {
+        const float x = __builtin_fabsf(q);
         const float e = __builtin_amdgcn_exp2f(-x);
         // d = 1 - 2^-x.  For small x the subtraction loses relative accuracy,
-        // and phi(S) for a small exclusive sum S is a large, confident message
-        // that needs it; there d comes from the Taylor series of
-        // -expm1(-x ln 2) (5 terms: truncation below 1e-8 relative for x < 1/8).
+        // which t (a small factor of P, the size of a weak message) needs;
+        // there d comes from the Taylor series of -expm1(-x ln 2) (5 terms:
+        // truncation below 1e-8 relative for x < 1/8).
         float p = __builtin_fmaf(-x, 1.33335581e-3f, 9.61812911e-3f);   // ln2^5/120, ln2^4/24
         p = __builtin_fmaf(-x, p, 5.55041087e-2f);                       // ln2^3/6
         p = __builtin_fmaf(-x, p, 2.40226507e-1f);                       // ln2^2/2
         p = __builtin_fmaf(-x, p, 6.93147181e-1f);                       // ln2
         const float d = (x < 0.125f) ? x * p : 1.0f - e;
-        float z = (e + e) * __builtin_amdgcn_rcpf(d);
-        z = __builtin_fminf(z, 0x1p100f);  // x -> 0: keeps the result finite (about 100)
+        const float ri = __builtin_amdgcn_rcpf(1.0f + e);
+        Term k;
+        k.t = mag_with_sign_of(d * ri, q);
+        k.u = (e + e) * ri;
+        return k;
+    }
+    __device__ static __forceinline__ Acc add(Acc a, const Term &k)
+    {
+        return Acc{a.P * __builtin_fabsf(k.t), oplus(a.Q, k.u)};
+    }
+    __device__ static __forceinline__ Acc merge(Acc a, Acc b) { return Acc{a.P * b.P, oplus(a.Q, b.Q)}; }
+    __device__ static __forceinline__ float message(Acc x)
+    {
+        float z = (x.P + x.P) * __builtin_amdgcn_rcpf(x.Q);
+        z = __builtin_fminf(z, 0x1p100f);  // Q -> 0: keeps the result finite (about 100) before the clamp
         const float w = 1.0f + z;
         float c = (1.0f - w) + z;
         c = (z < 1.0f) ? c : 0.0f;
-        return __builtin_fmaf(c, 1.44269504088896341f, __builtin_amdgcn_logf(w));
+        const float r = __builtin_fmaf(c, 1.44269504088896341f, __builtin_amdgcn_logf(w));
+        return r < kRmax ? r : kRmax;
     }
+    __device__ static __forceinline__ uint32_t term_sign(const Term &k) { return sign_bit(k.t); }
+
+    // The fused kernel parks a term's t in the edge's message slot and keeps u
+    // in a register; kDummyParked is the parked part of a dummy edge's term
+    // (q = +inf: t = 1, u = 0).
+    using Keep = float;
+    static constexpr float kDummyParked = 1.0f;
+    __device__ static __forceinline__ float park(const Term &k) { return k.t; }
+    __device__ static __forceinline__ Keep keep(const Term &k) { return k.u; }
+    __device__ static __forceinline__ Term unpark(float parked, Keep kept) { return Term{parked, kept}; }
+
     __device__ static __forceinline__ uint32_t sign_bit(float v) { return __float_as_uint(v) >> 31; }
     __device__ static __forceinline__ float with_sign(float mag, uint32_t neg)
     {
@@ -74,6 +126,27 @@ struct ArithF64 {
         const double d = -expm1(-x);
         return log1p((e + e) / d);
     }
+
+    using Term = double;  // phi(|q|) with q's sign bit
+    using Acc = double;   // sum of phi(|q|)
+    __device__ static __forceinline__ Acc identity() { return 0.0; }
+    __device__ static __forceinline__ Term term(double q) { return mag_with_sign_of(phi(fabs(q)), q); }
+    __device__ static __forceinline__ Acc add(Acc a, Term k) { return a + fabs(k); }
+    __device__ static __forceinline__ Acc merge(Acc a, Acc b) { return a + b; }
+    __device__ static __forceinline__ double message(Acc x)
+    {
+        const double r = phi(x);
+        return r < kRmax ? r : kRmax;
+    }
+    __device__ static __forceinline__ uint32_t term_sign(Term k) { return sign_bit(k); }
+
+    // The fused kernel parks the whole term in the edge's message slot
+    // (a dummy edge, q = +inf, has phi = 0).
+    struct Keep {};
+    static constexpr double kDummyParked = 0.0;
+    __device__ static __forceinline__ double park(Term k) { return k; }
+    __device__ static __forceinline__ Keep keep(Term) { return Keep{}; }
+    __device__ static __forceinline__ Term unpark(double parked, Keep) { return parked; }
     __device__ static __forceinline__ uint32_t sign_bit(double v)
     {
         return static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(v)) >> 63);
@@ -90,43 +163,39 @@ struct ArithF64 {
     }
 };
 
-// Exclusive sums of one check row.  The row's d edges are split at
+// Exclusive combinations of one check row.  The row's d edges are split at
 // h = ceil(d/2) into halves H0 = [0, h) and H1 = [h, d); for edge k in half
-// H, with p_k the sum of the earlier edges of H (left to right), s_k the sum
-// of the later edges of H (right to left) and S_other the total of the other
-// half (left to right),
-//     excl_k = (p_k + s_k) + S_other.
-// Every term is non-negative, so the order costs no accuracy; fixing it lets
-// the fused kernel spread a row over two lanes (one half each, exchanging
-// S and the sign) while the streaming kernel evaluates the same expression in
-// one lane, bit for bit.
+// H, with p_k the combination of the earlier edges of H (left to right), s_k
+// that of the later edges of H (right to left) and C_other the combination
+// of the other half (left to right),
+//     excl_k = merge(merge(p_k, s_k), C_other).
+// Fixing the order lets the fused kernel spread a row over two lanes (one
+// half each, exchanging C and the sign) while the streaming kernels evaluate
+// the same expression in one lane, bit for bit.
 
-// Forward step for an edge with incoming message q: a_k = sign(q) phi(|q|)
-// (sign in the sign bit), p_k = the half's running sum, which then grows.
+// Forward step for an edge with incoming message q: its term a_k, p_k = the
+// half's running combination, which then grows by a_k.
 template <class A>
-__device__ __forceinline__ void check_forward(typename A::T q, typename A::T &a_k, typename A::T &p_k,
-                                              typename A::T &acc, uint32_t &sign)
+__device__ __forceinline__ void check_forward(typename A::T q, typename A::Term &a_k, typename A::Acc &p_k,
+                                              typename A::Acc &acc, uint32_t &sign)
 {
-    const typename A::T mag = A::phi(fabs(q));
-    a_k = A::mag_with_sign_of(mag, q);
+    a_k = A::term(q);
     p_k = acc;
-    acc += mag;
+    acc = A::add(acc, a_k);
     sign ^= A::sign_bit(q);
 }
 
-// Backward step: outgoing message of an edge from its a_k, p_k, the half's
-// running suffix s (which then grows), the other half's total and the row's
-// total sign.
+// Backward step: outgoing message of an edge from its term, p_k, the half's
+// running suffix s (which then grows), the other half's combination and the
+// row's total sign.
 template <class A>
-__device__ __forceinline__ typename A::T check_backward(typename A::T a_k, typename A::T p_k, typename A::T &s,
-                                                        typename A::T s_other, uint32_t sign_total)
+__device__ __forceinline__ typename A::T check_backward(const typename A::Term &a_k, const typename A::Acc &p_k,
+                                                        typename A::Acc &s, const typename A::Acc &c_other,
+                                                        uint32_t sign_total)
 {
-    using T = typename A::T;
-    const T ex = (p_k + s) + s_other;
-    s += fabs(a_k);
-    T mag = A::phi(ex);
-    mag = mag < A::kRmax ? mag : A::kRmax;
-    return A::with_sign(mag, sign_total ^ A::sign_bit(a_k));
+    const typename A::Acc ex = A::merge(A::merge(p_k, s), c_other);
+    s = A::add(s, a_k);
+    return A::with_sign(A::message(ex), sign_total ^ A::term_sign(a_k));
 }
 
 }  // namespace ldpc
