@@ -9,8 +9,10 @@ iterations (early stop off).  Four batches at Eb/N0 = 1.0, 1.5, 2.0, 2.5 dB
 are resident in HBM and the steps cycle through them.
 
 Prints one JSON line: throughput (coded bits per second of device time), the
-dominant kernel's roofline position measured with HIP events inside the
-timed region, and the CPU oracle timed on the host on a bounded sample.
+median and spread of single steps (event pairs around each step, timed
+after the headline region), the dominant kernel's roofline position
+measured with HIP events inside the timed region, and the CPU oracle timed
+on the host on a bounded sample (all host threads, and one thread).
 Beside the headline (skipped with --no-extra unless noted) it reports: the
 same workload through the fused batch kernel; the other seeded workloads
 (gallager504 FP64, the 12-code mix, stair64800); the layered schedule and
@@ -41,13 +43,15 @@ def parse():
                     help="length of the open-loop serving run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="offered requests per second")
     ap.add_argument("--no-extra", action="store_true", help="skip the batch-path and other-workload timings")
+    ap.add_argument("--profile-every", type=int, default=PROFILE_EVERY,
+                    help="bracket the launches of every N-th timed step with HIP events (kernel durations)")
     ap.add_argument("--copy-probe-mb", type=int, default=512,
                     help="size of the streaming copy that measures achievable HBM bandwidth (0 = skip)")
     return ap.parse_args()
 
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_EVERY = 4  # timed steps per step whose launches are bracketed by HIP events
+PROFILE_EVERY = 10  # timed steps per step whose launches are bracketed by HIP events
 
 # HBM bytes per check-kernel launch on this workload, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE; reads scaled by 2.0 and writes by 1.0,
@@ -129,7 +133,7 @@ def main():
     # steps run without them.
     t0 = time.perf_counter()
     for i in range(args.steps):
-        L.ldpc_profile_enable(i % PROFILE_EVERY == 0)
+        L.ldpc_profile_enable(i % args.profile_every == 0)
         step(i)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -139,6 +143,20 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     coded_bits = F * n
     value = coded_bits * args.steps / elapsed / 1e6
+
+    # Per-step device times (an event pair around each step), after the timed
+    # region and apart from it: median and spread of the same step.
+    step_ms = []
+    for i in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step(i)
+        e1.record()
+        step_ms.append((e0, e1))
+    torch.cuda.synchronize()
+    step_ms = sorted(a.elapsed_time(b) for a, b in step_ms)
+    per_step = {"median_ms": step_ms[len(step_ms) // 2], "min_ms": step_ms[0], "max_ms": step_ms[-1],
+                "steps": len(step_ms), "median_mbps": coded_bits / (step_ms[len(step_ms) // 2] * 1e-3) / 1e6}
 
     # Roofline of the dominant kernel.  Algorithmic bytes of one check-node
     # launch over F frames: read r (4E, not on the first iteration), write r
@@ -169,7 +187,7 @@ def main():
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                 "traffic_unit": "bytes per launch", "traffic_profile": CHECK_TRAFFIC["profile"] if traffic else None,
                 "launch_ms": avg_ms, "launches": kcount, "bytes_per_launch": bytes_per_launch,
-                "timed_launches": f"HIP events on every launch of every {PROFILE_EVERY}th timed step"}
+                "timed_launches": f"HIP events on every launch of every {args.profile_every}th timed step"}
     kernels = {k: {"ms_total": v[0], "launches": v[1]} for k, v in prof.items() if v[1]}
 
     other_path = None
@@ -208,6 +226,7 @@ def main():
                                + (" (layered schedule: 10 passes)" if args.path == "layered" else ""),
                    "path": args.path, "frames": F, "n": n, "edges": E, "iterations": T},
         "info_mbps": k_info * F * args.steps / elapsed / 1e6,
+        "per_step": per_step,
         "roofline": roofline,
         "kernels": kernels,
         "batch_path": other_path,
@@ -607,10 +626,19 @@ def cpu_baseline(batches, T, seconds):
         frames += per_batch
     wall = time.perf_counter() - t0
     snrs = "/".join(f"{b.ebn0_db:g}" for b in batches)
+    # the same oracle on one thread, over a smaller sample (about a tenth of the time)
+    one = max(1, int(seconds / 10 / max(per_frame * threads, 1e-9)))
+    one = min(one, batches[0].llr.shape[0])
+    t1 = time.perf_counter()
+    oracle.decode(code, batches[2].llr[:one], T, False, nthreads=1, want_trace=False)
+    wall1 = time.perf_counter() - t1
     return {"value": frames * code.n / wall / 1e6, "unit": "Mbit/s", "cores": threads, "kind": "oracle",
             "sample": f"first {per_batch} of 4096 frames of each of the {snrs} dB batches ({frames} frames), "
                       f"{T} iterations, FP64, {threads} OpenMP threads, {wall:.1f} s wall "
-                      f"({wall * threads:.0f} core-seconds)"}
+                      f"({wall * threads:.0f} core-seconds)",
+            "single_thread": {"value": one * code.n / wall1 / 1e6, "unit": "Mbit/s", "cores": 1,
+                              "sample": f"first {one} frames of the {batches[2].ebn0_db:g} dB batch, {T} iterations, "
+                                        f"FP64, 1 thread, {wall1:.1f} s wall"}}
 
 if __name__ == "__main__":
     main()
