@@ -70,11 +70,14 @@ extern "C" {
 typedef enum {
     LDPC_OK = 0,
     LDPC_EINVAL = -1,       /* invalid argument; nothing was enqueued or written */
-    LDPC_ENOMEM = -2,       /* device or host allocation failed */
-    LDPC_EDEVICE = -3,      /* HIP runtime error */
+    LDPC_ENOMEM = -2,       /* device or host allocation (or host thread creation) failed */
+    LDPC_EDEVICE = -3,      /* HIP runtime error, or an unexpected internal failure */
     LDPC_EBUSY = -4,        /* resource temporarily unavailable (server full) */
     LDPC_EUNSUPPORTED = -5  /* valid but outside this build's limits */
 } ldpc_status;
+
+/* Every function reports failure through its status; no C++ exception
+ * leaves the library. */
 
 typedef enum { LDPC_F32 = 0, LDPC_F64 = 1 } ldpc_dtype;
 
@@ -280,6 +283,9 @@ ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_server *out);
  * than the arena / group cap; EBUSY when max_queue requests are waiting.
  * If the device launch of a request's group fails, the request still
  * completes, with every iteration count set to -1 (counted in stats.failed).
+ * If the scheduler itself runs out of host memory, every admitted group is
+ * let finish on the device, every request not yet done completes that way,
+ * and later submits return LDPC_ENOMEM.
  * Tickets stay valid until the server is destroyed.
  */
 ldpc_status ldpc_server_submit(ldpc_server server, int32_t code_id, int32_t frames, int32_t max_iter, uint32_t flags,

@@ -262,7 +262,7 @@ using namespace ldpc;
 
 extern "C" ldpc_status ldpc_batch_workspace_bytes(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype,
                                                   size_t *bytes)
-{
+try {
     if (!bytes)
         return LDPC_EINVAL;
     const ldpc_status st = validate_jobs(jobs, njobs, dtype);
@@ -273,11 +273,13 @@ extern "C" ldpc_status ldpc_batch_workspace_bytes(const ldpc_job *jobs, int32_t 
     plan(jobs, njobs, dtype, groups, plain);
     *bytes = batch_bytes(jobs, groups, plain, dtype);
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_decode_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, void *workspace,
                                          size_t workspace_bytes, void *stream)
-{
+try {
     const ldpc_status st = validate_jobs(jobs, njobs, dtype);
     if (st != LDPC_OK)
         return st;
@@ -307,19 +309,23 @@ extern "C" ldpc_status ldpc_decode_batch(const ldpc_job *jobs, int32_t njobs, ld
             return r;
     }
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_batch_set_threads(int32_t threads)
-{
+try {
     if (threads < 64 || threads > 512 || threads % 64 != 0)
         return LDPC_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_threads = threads;
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_batch_fits_fused(ldpc_code code, ldpc_dtype dtype, size_t *lds_bytes)
-{
+try {
     if (!code || (dtype != LDPC_F32 && dtype != LDPC_F64))
         return LDPC_EINVAL;
     if (!code_on_current_device(code))
@@ -328,6 +334,8 @@ extern "C" ldpc_status ldpc_batch_fits_fused(ldpc_code code, ldpc_dtype dtype, s
     if (lds_bytes)
         *lds_bytes = f.lds;
     return f.ok ? LDPC_OK : LDPC_EUNSUPPORTED;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 namespace {
@@ -358,7 +366,7 @@ ldpc_status snapshot(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, hipStre
 extern "C" ldpc_status ldpc_autotune_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, void *workspace,
                                            size_t workspace_bytes, void *stream, int32_t *best_threads,
                                            double *best_ms)
-{
+try {
     const ldpc_status st = validate_jobs(jobs, njobs, dtype);
     if (st != LDPC_OK)
         return st;
@@ -418,4 +426,6 @@ extern "C" ldpc_status ldpc_autotune_batch(const ldpc_job *jobs, int32_t njobs, 
     if (best_ms)
         *best_ms = best_t;
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }

@@ -196,7 +196,7 @@ extern "C" const char *ldpc_status_str(ldpc_status s)
 
 extern "C" ldpc_status ldpc_code_from_csr(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
                                           ldpc_code *out)
-{
+try {
     if (!out)
         return LDPC_EINVAL;
     HostLayout h;
@@ -217,10 +217,12 @@ extern "C" ldpc_status ldpc_code_from_csr(int32_t m, int32_t n, const int32_t *r
     }
     *out = c;
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_code_from_qc(int32_t mb, int32_t nb, int32_t Z, const int32_t *shifts, ldpc_code *out)
-{
+try {
     if (!out || !shifts || mb < 1 || nb < 1 || Z < 1)
         return LDPC_EINVAL;
     if (static_cast<int64_t>(mb) * Z > INT32_MAX / 2 || static_cast<int64_t>(nb) * Z > INT32_MAX / 2)
@@ -295,10 +297,12 @@ extern "C" ldpc_status ldpc_code_from_qc(int32_t mb, int32_t nb, int32_t Z, cons
     c->h_qc_tab = std::move(tab);
     *out = c;
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_code_info(ldpc_code code, int32_t *m, int32_t *n, int64_t *edges)
-{
+try {
     if (!code)
         return LDPC_EINVAL;
     if (m)
@@ -308,10 +312,12 @@ extern "C" ldpc_status ldpc_code_info(ldpc_code code, int32_t *m, int32_t *n, in
     if (edges)
         *edges = code->E;
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_code_layers(ldpc_code code, int32_t *nlayers, int32_t *min_rows, int32_t *max_rows)
-{
+try {
     if (!code)
         return LDPC_EINVAL;
     const int32_t L = static_cast<int32_t>(code->layer_dmax.size());
@@ -328,10 +334,12 @@ extern "C" ldpc_status ldpc_code_layers(ldpc_code code, int32_t *nlayers, int32_
     if (max_rows)
         *max_rows = hi;
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" void ldpc_code_destroy(ldpc_code code)
-{
+try {
     if (!code)
         return;
     if (code->d_mem) {
@@ -343,4 +351,5 @@ extern "C" void ldpc_code_destroy(ldpc_code code)
             (void)hipSetDevice(prev);
     }
     delete code;
+} catch (...) {
 }

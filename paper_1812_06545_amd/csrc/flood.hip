@@ -397,27 +397,31 @@ bool minsum_params_ok(double scale, double offset)
 
 extern "C" ldpc_status ldpc_workspace_bytes(ldpc_code code, ldpc_dtype dtype, int32_t frames, int32_t max_iter,
                                             size_t *bytes)
-{
+try {
     if (!code || !bytes || frames < 0 || frames > LDPC_MAX_FRAMES || max_iter < 0 ||
         (dtype != LDPC_F32 && dtype != LDPC_F64))
         return LDPC_EINVAL;
     *bytes = ldpc::stream_workspace_bytes(code, dtype, frames, max_iter);
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_decode(ldpc_code code, ldpc_dtype dtype, int32_t frames, int32_t max_iter,
                                    uint32_t flags, const void *llr, uint8_t *bits, int32_t *iters, void *posterior,
                                    void *workspace, size_t workspace_bytes, void *stream)
-{
+try {
     return ldpc_decode_minsum(code, dtype, frames, max_iter, flags, 1.0f, 0.0f, llr, bits, iters, posterior,
                               workspace, workspace_bytes, stream);
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_decode_minsum(ldpc_code code, ldpc_dtype dtype, int32_t frames, int32_t max_iter,
                                           uint32_t flags, float ms_scale, float ms_offset, const void *llr,
                                           uint8_t *bits, int32_t *iters, void *posterior, void *workspace,
                                           size_t workspace_bytes, void *stream)
-{
+try {
     if (!code || frames < 0 || frames > LDPC_MAX_FRAMES || max_iter < 0 ||
         (flags & ~(LDPC_EARLY_STOP | LDPC_LAYERED | LDPC_MIN_SUM)) != 0 || (dtype != LDPC_F32 && dtype != LDPC_F64) ||
         !ldpc::minsum_params_ok(ms_scale, ms_offset))
@@ -434,4 +438,6 @@ extern "C" ldpc_status ldpc_decode_minsum(ldpc_code code, ldpc_dtype dtype, int3
         return LDPC_EINVAL;
     return ldpc::stream_decode(code, dtype, frames, max_iter, flags, llr, bits, iters, posterior, workspace,
                                static_cast<hipStream_t>(stream), ms_scale, ms_offset);
+} catch (...) {
+    return ldpc::status_of_exception();
 }

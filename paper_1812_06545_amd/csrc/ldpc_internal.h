@@ -6,6 +6,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <new>
+#include <stdexcept>
+#include <system_error>
 #include <vector>
 
 #include "ldpc.h"
@@ -16,6 +19,30 @@
         if (ldpc_e_ != hipSuccess)               \
             return LDPC_EDEVICE;                 \
     } while (0)
+
+namespace ldpc {
+
+// No C++ exception crosses the C interface: every entry point is a
+// function-try-block whose handler calls this (inside the handler, so the
+// exception in flight is rethrown and classified).  Host allocation and
+// thread-creation failures become LDPC_ENOMEM; nothing else is expected to
+// throw, and anything that does is reported as LDPC_EDEVICE.
+inline ldpc_status status_of_exception() noexcept
+{
+    try {
+        throw;
+    } catch (const std::bad_alloc &) {
+        return LDPC_ENOMEM;
+    } catch (const std::length_error &) {
+        return LDPC_ENOMEM;
+    } catch (const std::system_error &) {
+        return LDPC_ENOMEM;
+    } catch (...) {
+        return LDPC_EDEVICE;
+    }
+}
+
+}  // namespace ldpc
 
 // A code handle: H in device memory, in two layouts.
 //   CSR/CSC (every code): edges numbered in CSR order (rows ascending,

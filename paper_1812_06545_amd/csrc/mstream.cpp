@@ -73,7 +73,7 @@ struct Worker {
 extern "C" ldpc_status ldpc_mstream_run(ldpc_code code, int32_t workers, int32_t frames_per_batch, int32_t batches,
                                         int32_t max_iter, uint32_t flags, int32_t blocking_sync, const float *llr,
                                         uint8_t *bits, int32_t *iters, ldpc_mstream_stats *stats)
-{
+try {
     if (!code || workers < 1 || workers > 64 || frames_per_batch < 1 || frames_per_batch > LDPC_MAX_FRAMES ||
         batches < 0 || max_iter < 0 || (flags & ~(LDPC_EARLY_STOP | LDPC_LAYERED | LDPC_MIN_SUM)) != 0 ||
         (batches > 0 && (!llr || !bits || !iters)))
@@ -172,4 +172,6 @@ extern "C" ldpc_status ldpc_mstream_run(ldpc_code code, int32_t workers, int32_t
         stats->online_cores = static_cast<int32_t>(cores);
     }
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }

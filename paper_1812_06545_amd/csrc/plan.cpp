@@ -12,7 +12,7 @@ struct ldpc_plan_s {
 
 extern "C" ldpc_status ldpc_plan_create(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, void *workspace,
                                         size_t workspace_bytes, ldpc_plan *out)
-{
+try {
     if (!out)
         return LDPC_EINVAL;
     size_t need = 0;
@@ -47,20 +47,24 @@ extern "C" ldpc_status ldpc_plan_create(const ldpc_job *jobs, int32_t njobs, ldp
     }
     *out = p;
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_plan_launch(ldpc_plan plan, void *stream)
-{
+try {
     if (!plan)
         return LDPC_EINVAL;
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
         return LDPC_EINVAL;
     return hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? LDPC_OK : LDPC_EDEVICE;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" void ldpc_plan_destroy(ldpc_plan plan)
-{
+try {
     if (!plan)
         return;
     if (plan->exec)
@@ -68,4 +72,5 @@ extern "C" void ldpc_plan_destroy(ldpc_plan plan)
     if (plan->graph)
         (void)hipGraphDestroy(plan->graph);
     delete plan;
+} catch (...) {
 }

@@ -83,6 +83,8 @@ ldpc_status launch_copy16(void *dst, const void *src, size_t bytes, hipStream_t 
 }  // namespace ldpc
 
 extern "C" ldpc_status ldpc_copy_probe(void *dst, const void *src, size_t bytes, void *stream)
-{
+try {
     return ldpc::launch_copy16(dst, src, bytes, static_cast<hipStream_t>(stream));
+} catch (...) {
+    return ldpc::status_of_exception();
 }

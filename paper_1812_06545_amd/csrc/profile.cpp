@@ -68,13 +68,15 @@ ldpc::ProfScope::~ProfScope()
 }
 
 extern "C" ldpc_status ldpc_profile_enable(int enable)
-{
+try {
     g_enabled.store(enable ? 1 : 0);
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_profile_collect(double *ms, int64_t *counts)
-{
+try {
     std::vector<Record> recs;
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -104,4 +106,6 @@ extern "C" ldpc_status ldpc_profile_collect(double *ms, int64_t *counts)
             counts[k] = cnt[k];
     }
     return st;
+} catch (...) {
+    return ldpc::status_of_exception();
 }

@@ -110,19 +110,15 @@ class CopyPool {
     explicit CopyPool(int helpers)
     {
         parts_.resize(static_cast<size_t>(helpers) + 1);
-        for (int i = 0; i < helpers; ++i)
-            threads_.emplace_back([this, i] { loop(i + 1); });
-    }
-    ~CopyPool()
-    {
-        {
-            std::lock_guard<std::mutex> lk(mu_);
-            stop_ = true;
+        try {
+            for (int i = 0; i < helpers; ++i)
+                threads_.emplace_back([this, i] { loop(i + 1); });
+        } catch (...) {
+            shut_down();  // helpers started so far must be joined before the members go
+            throw;
         }
-        go_.notify_all();
-        for (std::thread &t : threads_)
-            t.join();
     }
+    ~CopyPool() { shut_down(); }
 
     void run(const std::vector<Item> &items)
     {
@@ -166,6 +162,18 @@ class CopyPool {
     }
 
   private:
+    void shut_down()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        go_.notify_all();
+        for (std::thread &t : threads_)
+            t.join();
+        threads_.clear();
+    }
+
     void loop(size_t me)
     {
         uint64_t seen = 0;
@@ -241,6 +249,7 @@ struct ldpc_server_s {
     std::unordered_map<uint64_t, Request *> by_ticket;
     uint64_t next_ticket = 1;
     bool stop = false;
+    bool broken = false;  // the scheduler hit a host allocation failure: requests fail from then on
     std::thread sched;
     std::unique_ptr<CopyPool> copies;  // used by the scheduler thread only
     std::vector<CopyPool::Item> copy_items;
@@ -252,6 +261,9 @@ struct ldpc_server_s {
     int64_t group_frames_sum = 0;
 
     void run();
+    void schedule(std::unique_lock<std::mutex> &lk);
+    void fail_request(Request *r, int64_t t);
+    void fail_everything(std::unique_lock<std::mutex> &lk);
     bool reap(std::unique_lock<std::mutex> &lk);
     bool admit(std::unique_lock<std::mutex> &lk);
     void free_all();
@@ -424,10 +436,8 @@ bool ldpc_server_s::admit(std::unique_lock<std::mutex> &lk)
     return any;
 }
 
-void ldpc_server_s::run()
+void ldpc_server_s::schedule(std::unique_lock<std::mutex> &lk)
 {
-    (void)hipSetDevice(device);
-    std::unique_lock<std::mutex> lk(mu);
     for (;;) {
         reap(lk);
         admit(lk);
@@ -438,6 +448,63 @@ void ldpc_server_s::run()
             cv_work.wait_for(lk, std::chrono::microseconds(20));
         else
             cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+    }
+}
+
+// A request completes as failed: every iteration count -1 (under the lock).
+// One that already completed keeps its results.
+void ldpc_server_s::fail_request(Request *r, int64_t t)
+{
+    if (r->state == kDone)
+        return;
+    std::fill(r->iters, r->iters + r->frames, -1);
+    r->done_ns = t;
+    r->state = kDone;
+    st.failed += 1;
+}
+
+// After an exception in the scheduler (a host allocation failure): let every
+// admitted group finish on the device, fail its requests and every queued
+// one, and keep failing new ones until the server is destroyed.  Nothing
+// here allocates.
+void ldpc_server_s::fail_everything(std::unique_lock<std::mutex> &lk)
+{
+    if (!lk.owns_lock())
+        lk.lock();
+    broken = true;
+    for (Slot &s : slots) {
+        if (s.reqs.empty() && !s.busy)
+            continue;
+        lk.unlock();
+        (void)hipStreamSynchronize(s.stream);
+        lk.lock();
+        const int64_t t = now_ns();
+        for (Request *r : s.reqs)
+            fail_request(r, t);
+        s.reqs.clear();
+        s.busy = false;
+    }
+    for (;;) {
+        const int64_t t = now_ns();
+        for (Request *r : queue)
+            fail_request(r, t);
+        queue.clear();
+        cv_done.notify_all();
+        if (stop)
+            return;
+        cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+    }
+}
+
+void ldpc_server_s::run()
+{
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu, std::defer_lock);
+    try {
+        lk.lock();
+        schedule(lk);
+    } catch (...) {
+        fail_everything(lk);
     }
 }
 
@@ -464,29 +531,34 @@ void ldpc_server_s::free_all()
 
 using namespace ldpc;
 
+namespace {
+// Releases a server that was never handed out (no scheduler thread yet).
+struct ServerRelease {
+    void operator()(ldpc_server_s *s) const
+    {
+        s->free_all();
+        delete s;
+    }
+};
+}  // namespace
+
 extern "C" ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_server *out)
-{
+try {
     if (!cfg || !out || cfg->ncodes < 1 || cfg->ncodes > 64 || !cfg->codes || cfg->max_inflight < 1 ||
         cfg->max_inflight > 8 || cfg->max_group_frames < 1 || cfg->max_queue < 1 || cfg->mem_budget_bytes == 0)
         return LDPC_EINVAL;
-    auto *sv = new (std::nothrow) ldpc_server_s();
-    if (!sv)
-        return LDPC_ENOMEM;
-    if (hipGetDevice(&sv->device) != hipSuccess) {
-        delete sv;
+    // owned here until it is handed out: every early return (and any
+    // exception) releases whatever was set up so far
+    std::unique_ptr<ldpc_server_s, ServerRelease> sv(new ldpc_server_s());
+    if (hipGetDevice(&sv->device) != hipSuccess)
         return LDPC_EDEVICE;
-    }
     int32_t nmin = INT32_MAX;
     for (int32_t i = 0; i < cfg->ncodes; ++i) {
         ldpc_code c = cfg->codes[i];
-        if (!c || !code_on_current_device(c)) {
-            delete sv;
+        if (!c || !code_on_current_device(c))
             return LDPC_EINVAL;
-        }
-        if (ldpc_batch_fits_fused(c, LDPC_F32, nullptr) != LDPC_OK) {
-            delete sv;
+        if (ldpc_batch_fits_fused(c, LDPC_F32, nullptr) != LDPC_OK)
             return LDPC_EUNSUPPORTED;
-        }
         sv->codes.push_back(c);
         sv->code_n.push_back(c->n);
         nmin = std::min(nmin, c->n);
@@ -501,26 +573,16 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_serve
     const size_t host_bytes = 2 * llr_bytes + align_up(static_cast<size_t>(frames_cap) * 4, 256) +
                               static_cast<size_t>(elems_cap);
     void *d = nullptr, *h = nullptr, *dh = nullptr;
-    if (elems_cap < 4) {
-        delete sv;
+    if (elems_cap < 4)
         return LDPC_EINVAL;
-    }
-    if (hipMalloc(&d, llr_bytes) != hipSuccess) {
-        delete sv;
+    if (hipMalloc(&d, llr_bytes) != hipSuccess)
         return LDPC_ENOMEM;
-    }
-    if (hipHostMalloc(&h, host_bytes, hipHostMallocDefault) != hipSuccess) {
-        (void)hipFree(d);
-        delete sv;
-        return LDPC_ENOMEM;
-    }
     sv->d_llr = static_cast<float *>(d);
+    if (hipHostMalloc(&h, host_bytes, hipHostMallocDefault) != hipSuccess)
+        return LDPC_ENOMEM;
     sv->h_llr = static_cast<float *>(h);  // owns the pinned block (freed through it)
-    if (hipHostGetDevicePointer(&dh, h, 0) != hipSuccess) {
-        sv->free_all();
-        delete sv;
+    if (hipHostGetDevicePointer(&dh, h, 0) != hipSuccess)
         return LDPC_EDEVICE;
-    }
     auto carve = [&](void *base, float *&llr, float *&post, int32_t *&it, uint8_t *&bits) {
         char *p = static_cast<char *>(base);
         llr = reinterpret_cast<float *>(p);
@@ -538,11 +600,8 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_serve
         s.ws_bytes = ws_bytes;
         if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
-            hipMalloc(&s.ws, ws_bytes) != hipSuccess) {
-            sv->free_all();
-            delete sv;
+            hipMalloc(&s.ws, ws_bytes) != hipSuccess)
             return LDPC_ENOMEM;
-        }
     }
     // Warm-up: on every slot's stream, the staging copy at a small and a large
     // size, then one frame of every code for one iteration.  The runtime sets
@@ -555,11 +614,8 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_serve
     std::memset(sv->h_llr, 0, big);  // the copies below leave zero LLRs for the warm-up decodes
     for (Slot &s : sv->slots) {
         for (const size_t len : {std::min<size_t>(big, 4096), big})
-            if (launch_link_copy16(sv->d_llr, sv->dh_llr, len, kLinkCopyBlocks, s.stream) != LDPC_OK) {
-                sv->free_all();
-                delete sv;
+            if (launch_link_copy16(sv->d_llr, sv->dh_llr, len, kLinkCopyBlocks, s.stream) != LDPC_OK)
                 return LDPC_EDEVICE;
-            }
         for (size_t i = 0; i < sv->codes.size(); ++i) {
             if (sv->code_n[i] > std::min<int64_t>(elems_cap, 1 << 16))
                 continue;  // requests for such a code are refused at submit anyway
@@ -571,38 +627,34 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_serve
             j.bits = sv->dh_bits;
             j.iters = sv->dh_iters;
             const ldpc_status rc = ldpc_decode_batch(&j, 1, LDPC_F32, s.ws, s.ws_bytes, s.stream);
-            if (rc != LDPC_OK) {
-                sv->free_all();
-                delete sv;
+            if (rc != LDPC_OK)
                 return rc;
-            }
         }
-        if (hipStreamSynchronize(s.stream) != hipSuccess) {
-            sv->free_all();
-            delete sv;
+        if (hipStreamSynchronize(s.stream) != hipSuccess)
             return LDPC_EDEVICE;
-        }
     }
     const unsigned hw = std::thread::hardware_concurrency();
     sv->copies.reset(new CopyPool(static_cast<int>(std::min(3u, hw > 4 ? hw / 4 : 0u))));
-    sv->sched = std::thread([sv] { sv->run(); });
-    *out = sv;
+    ldpc_server_s *raw = sv.get();
+    sv->sched = std::thread([raw] { raw->run(); });
+    *out = sv.release();
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_server_submit(ldpc_server sv, int32_t code_id, int32_t frames, int32_t max_iter,
                                           uint32_t flags, const float *llr, uint8_t *bits, int32_t *iters,
                                           float *posterior, int64_t arrival_ns, uint64_t *ticket)
-{
+try {
     if (!sv || !ticket || code_id < 0 || code_id >= static_cast<int32_t>(sv->codes.size()) || frames < 1 ||
         max_iter < 0 || (flags & ~LDPC_EARLY_STOP) != 0 || !llr || !bits || !iters)
         return LDPC_EINVAL;
     const int64_t need = static_cast<int64_t>(frames) * sv->code_n[code_id];
     if (frames > sv->max_group_frames || align4(need) > sv->elems.capacity())
         return LDPC_EINVAL;
-    auto *r = new (std::nothrow) Request();
-    if (!r)
-        return LDPC_ENOMEM;
+    std::unique_ptr<Request> owned(new Request());
+    Request *r = owned.get();
     r->code_id = code_id;
     r->frames = frames;
     r->max_iter = max_iter;
@@ -614,23 +666,32 @@ extern "C" ldpc_status ldpc_server_submit(ldpc_server sv, int32_t code_id, int32
     r->arrival_ns = arrival_ns > 0 ? arrival_ns : now_ns();
     {
         std::lock_guard<std::mutex> lk(sv->mu);
-        if (sv->stop || static_cast<int32_t>(sv->queue.size()) >= sv->max_queue) {
-            delete r;
+        if (sv->broken)
+            return LDPC_ENOMEM;
+        if (sv->stop || static_cast<int32_t>(sv->queue.size()) >= sv->max_queue)
             return LDPC_EBUSY;
+        // insert into the ticket map, then the queue; undo the first if the second throws
+        const auto ins = sv->by_ticket.emplace(sv->next_ticket, r);
+        try {
+            sv->queue.push_back(r);
+        } catch (...) {
+            sv->by_ticket.erase(ins.first);
+            throw;
         }
+        owned.release();  // owned by the server from here on
         r->ticket = sv->next_ticket++;
-        sv->by_ticket[r->ticket] = r;
-        sv->queue.push_back(r);
         sv->st.submitted += 1;
         sv->st.max_queue_depth = std::max<int64_t>(sv->st.max_queue_depth, static_cast<int64_t>(sv->queue.size()));
         *ticket = r->ticket;
     }
     sv->cv_work.notify_one();
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_server_poll(ldpc_server sv, uint64_t ticket, int32_t *done)
-{
+try {
     if (!sv || !done)
         return LDPC_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
@@ -640,10 +701,12 @@ extern "C" ldpc_status ldpc_server_poll(ldpc_server sv, uint64_t ticket, int32_t
     const int s = it->second->state;
     *done = (s == kDone || s == kCancelled) ? 1 : 0;
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_server_wait(ldpc_server sv, uint64_t ticket, double timeout_ms)
-{
+try {
     if (!sv)
         return LDPC_EINVAL;
     std::unique_lock<std::mutex> lk(sv->mu);
@@ -654,10 +717,12 @@ extern "C" ldpc_status ldpc_server_wait(ldpc_server sv, uint64_t ticket, double 
     const bool ok = sv->cv_done.wait_for(lk, std::chrono::microseconds(static_cast<int64_t>(timeout_ms * 1e3)),
                                          [&] { return r->state == kDone || r->state == kCancelled; });
     return ok ? LDPC_OK : LDPC_EBUSY;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_server_cancel(ldpc_server sv, uint64_t ticket)
-{
+try {
     if (!sv)
         return LDPC_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
@@ -672,10 +737,12 @@ extern "C" ldpc_status ldpc_server_cancel(ldpc_server sv, uint64_t ticket)
     sv->st.cancelled += 1;
     sv->cv_done.notify_all();
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" ldpc_status ldpc_server_stats_get(ldpc_server sv, ldpc_server_stats *out, int reset)
-{
+try {
     if (!sv || !out)
         return LDPC_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
@@ -700,10 +767,12 @@ extern "C" ldpc_status ldpc_server_stats_get(ldpc_server sv, ldpc_server_stats *
         sv->group_frames_sum = 0;
     }
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
 }
 
 extern "C" void ldpc_server_destroy(ldpc_server sv)
-{
+try {
     if (!sv)
         return;
     {
@@ -715,4 +784,5 @@ extern "C" void ldpc_server_destroy(ldpc_server sv)
         sv->sched.join();
     sv->free_all();
     delete sv;
+} catch (...) {
 }
