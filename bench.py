@@ -65,6 +65,20 @@ CHECK_TRAFFIC = {
 }
 CHECK_SOURCES = ("flood_kernels.h", "spa_math.h", "check_f32_d24.hip")
 
+# The check kernel is co-limited by VALU issue.  Wavefront VALU instructions
+# per launch on this workload, from the SQ_INSTS_VALU counter run (same
+# source hash, same averaging), and the transcendentals among them (exp2 and
+# a reciprocal per edge forward, a reciprocal and log2 back: 4 per edge and
+# 64-frame chunk).  Issue peak: 1024 SIMDs x 2.4 GHz / 4 cycles per wave64
+# instruction; a transcendental occupies its SIMD four times as long.
+CHECK_VALU = {
+    "insts_per_launch": 44.25e6,
+    "trans_per_edge_chunk": 4,
+    "source_sha256": CHECK_TRAFFIC["source_sha256"],
+    "profile": "profiles/check_variable_qc1944_plain.md",
+}
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4  # wavefront instructions per second
+
 
 def check_source_hash():
     import hashlib
@@ -188,6 +202,13 @@ def main():
                 "traffic_unit": "bytes per launch", "traffic_profile": CHECK_TRAFFIC["profile"] if traffic else None,
                 "launch_ms": avg_ms, "launches": kcount, "bytes_per_launch": bytes_per_launch,
                 "timed_launches": f"HIP events on every launch of every {args.profile_every}th timed step"}
+    if args.path == "plain" and kcount and check_source_hash() == CHECK_VALU["source_sha256"]:
+        insts = CHECK_VALU["insts_per_launch"]
+        slots = insts + 3 * CHECK_VALU["trans_per_edge_chunk"] * E * (F // 64)
+        roofline["valu"] = {"achieved": insts / (avg_ms * 1e-3) / 1e9, "peak": VALU_ISSUE_PEAK / 1e9,
+                            "unit": "G wavefront instructions/s", "frac": insts / (avg_ms * 1e-3) / VALU_ISSUE_PEAK,
+                            "frac_transcendentals_4x": slots / (avg_ms * 1e-3) / VALU_ISSUE_PEAK,
+                            "insts_per_launch": insts, "profile": CHECK_VALU["profile"]}
     kernels = {k: {"ms_total": v[0], "launches": v[1]} for k, v in prof.items() if v[1]}
 
     other_path = None
