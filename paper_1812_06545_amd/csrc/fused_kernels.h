@@ -66,11 +66,16 @@ struct Batch {
     Job jobs[kMaxJobs];
 };
 
+// One message-sized LDS word per thread (up to 512), between the messages r
+// and the posteriors: the target of dummy-edge stores, so that a half row's
+// stores need no exec-mask branch and its loads can all be issued first.
+constexpr int kDummySlots = 512;
+
 // LDS bytes a workgroup needs for one frame of this code.
 __host__ __device__ inline size_t frame_lds_bytes(int64_t E, int32_t n, int32_t words, int32_t nblocks, int32_t mb,
                                                   size_t tsize)
 {
-    const size_t msg = (static_cast<size_t>(E) + static_cast<size_t>(n)) * tsize;
+    const size_t msg = (static_cast<size_t>(E) + kDummySlots + static_cast<size_t>(n)) * tsize;
     return (msg + 15) / 16 * 16 + static_cast<size_t>(words + nblocks + mb) * sizeof(int32_t);
 }
 
@@ -83,10 +88,9 @@ struct RowQC {
     __device__ int32_t ridx(int k) const { return (first_block + k) * Z + r; }
     __device__ int32_t col(int k) const
     {
-        const int32_t w = pack[first_block + k];
-        int32_t c = r + (w >> 16);
-        c = c >= Z ? c - Z : c;
-        return (w & 0xffff) + c;
+        const uint32_t w = static_cast<uint32_t>(pack[first_block + k]);
+        const uint32_t c = static_cast<uint32_t>(r) + (w >> 16);  // in [0, 2Z): min picks c or c - Z
+        return static_cast<int32_t>((w & 0xffffu) + __builtin_elementwise_min(c, c - static_cast<uint32_t>(Z)));
     }
 };
 
@@ -115,13 +119,15 @@ __device__ __forceinline__ ArithF32::Acc pair_swap(const ArithF32::Acc &v)
 // One half of a check row, run-time length dh <= D, as the straight-line
 // body of length D: this lane owns edges k0 .. k0+dh-1 of the row (the first
 // half, or the second), its partner lane the other half.  Edges j >= dh are
-// dummies: they read slot 0 (valid for any code with an edge) and enter as
-// q = +inf, r = 0, whose terms are the exact identity of the combination
-// (t = 1, u = 0 in FP32; phi = 0 in FP64) with a + sign; nothing is written
-// for them.  The forward pass parks (part of) a_k in the edge's own r slot
-// (free once q_k is formed, owned by this lane alone) instead of a register
-// array; after the partner's half combination and sign are exchanged, the
-// backward pass reads a_k back and overwrites the slot with the new message.
+// dummies: they enter as q = +inf, r = 0, whose terms are the exact identity
+// of the combination (t = 1, u = 0 in FP32; phi = 0 in FP64) with a + sign;
+// they read posterior slot 0 and this thread's dummy slot (the values are
+// masked) and write only to the dummy slot.  All of the half row's indices
+// and loads are issued before its arithmetic.  The forward pass parks (part
+// of) a_k in the edge's own r slot (free once q_k is formed, owned by this
+// lane alone) instead of a register array; after the partner's half
+// combination and sign are exchanged, the backward pass reads a_k back and
+// overwrites the slot with the new message.
 template <class A, int D, class Row>
 __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, typename A::T *__restrict__ sR,
                                                const typename A::T *__restrict__ sL, bool first, uint32_t &parity)
@@ -131,20 +137,30 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
     typename A::Keep kp[D];
     typename A::Acc acc = A::identity();
     uint32_t sign = 0, par = 0;
+    const int32_t dslot = static_cast<int32_t>(sL - sR) - kDummySlots + static_cast<int32_t>(threadIdx.x);
+    int32_t ri[D], ci[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         const bool real = j < dh;
-        const int32_t ri = real ? row.ridx(k0 + j) : 0;
-        const T l = sL[real ? row.col(k0 + j) : 0];
-        const T rr = first ? T(0) : sR[ri];
-        const T lv = real ? l : T(__builtin_huge_val());
-        par ^= static_cast<uint32_t>(real && lv < T(0));
-        const T q = first ? lv : lv - (real ? rr : T(0));
+        ri[j] = real ? row.ridx(k0 + j) : dslot;
+        ci[j] = real ? row.col(k0 + j) : 0;
+    }
+    T lv[D], rv[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        lv[j] = sL[ci[j]];
+        rv[j] = first ? T(0) : sR[ri[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const bool real = j < dh;
+        const T l = real ? lv[j] : T(__builtin_huge_val());
+        par ^= static_cast<uint32_t>(real && l < T(0));
+        const T q = first ? l : l - (real ? rv[j] : T(0));
         typename A::Term a_k;
         check_forward<A>(q, a_k, p[j], acc, sign);
         kp[j] = A::keep(a_k);
-        if (real)
-            sR[ri] = A::park(a_k);
+        sR[ri[j]] = A::park(a_k);
     }
     const typename A::Acc s_other = pair_swap(acc);
     const uint32_t sign_total = sign ^ pair_swap(sign);
@@ -153,11 +169,9 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
 #pragma unroll
     for (int j = D - 1; j >= 0; --j) {
         const bool real = j < dh;
-        const int32_t ri = real ? row.ridx(k0 + j) : 0;
-        const typename A::Term a_k = A::unpark(real ? sR[ri] : T(A::kDummyParked), kp[j]);
+        const typename A::Term a_k = A::unpark(real ? sR[ri[j]] : T(A::kDummyParked), kp[j]);
         const T r = check_backward<A>(a_k, p[j], s, s_other, sign_total);
-        if (real)
-            sR[ri] = r;
+        sR[ri[j]] = r;
     }
 }
 
@@ -407,9 +421,9 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
                 const int32_t k0 = cbs[bj];
                 auto edge = [&](int k) {
                     const int32_t b = cblk[k0 + k];
-                    int32_t r = cc - bshift[b];
-                    r = r < 0 ? r + Z : r;
-                    return b * Z + r;
+                    // cc - shift in (-Z, Z); as unsigned, min picks it or it + Z
+                    const uint32_t r = static_cast<uint32_t>(cc - bshift[b]);
+                    return b * Z + static_cast<int32_t>(__builtin_elementwise_min(r, r + static_cast<uint32_t>(Z)));
                 };
                 v = fused_col_dispatch<A, 0>(dwave, edge, cbs[bj + 1] - k0, acc, sR);
             } else {
@@ -564,8 +578,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWaves
     __shared__ long long s_item;
     const Batch &b = *batch;
     T *sR = reinterpret_cast<T *>(smem);
-    T *sL = sR + b.emax;
-    int32_t *sTab = reinterpret_cast<int32_t *>(smem + (static_cast<size_t>(b.emax + b.nmax) * sizeof(T) + 15) / 16 * 16);
+    T *sL = sR + b.emax + kDummySlots;
+    int32_t *sTab = reinterpret_cast<int32_t *>(
+        smem + (static_cast<size_t>(b.emax + kDummySlots + b.nmax) * sizeof(T) + 15) / 16 * 16);
     int cur_code = -1;
     for (;;) {
         if (threadIdx.x == 0)
