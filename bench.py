@@ -146,7 +146,9 @@ def main():
     # steps run without them.
     t0 = time.perf_counter()
     for i in range(args.steps):
-        L.ldpc_profile_enable((i + 1) % args.profile_every == 0)  # never the first step, which follows a host pause
+        # every profile_every-th step counted back from the last one (the
+        # first step, which follows a host pause, only when it is the last)
+        L.ldpc_profile_enable((args.steps - 1 - i) % args.profile_every == 0)
         step(i)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
