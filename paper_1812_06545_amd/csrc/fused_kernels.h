@@ -201,7 +201,8 @@ __device__ __forceinline__ void fused_row_dispatch(int hwave, const Row &row, in
 // posteriors at once, L_n = q_mn + r_mn.  No other row of the layer touches
 // these edges or variables, so the forward pass parks q_k in the variable's
 // own L slot and a_k in the edge's r slot; the backward pass reads both back
-// and writes r_new and q_k + r_new.
+// and writes r_new and q_k + r_new.  Dummy edges read and write only this
+// thread's dummy slot (through both arrays); loads are issued first.
 template <class A, int D, class Row>
 __device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh, typename A::T *__restrict__ sR,
                                                  typename A::T *__restrict__ sL, bool first)
@@ -211,22 +212,31 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh,
     typename A::Keep kp[D];
     typename A::Acc acc = A::identity();
     uint32_t sign = 0;
+    const int32_t dslot = static_cast<int32_t>(sL - sR) - kDummySlots + static_cast<int32_t>(threadIdx.x);
+    const int32_t dslot_l = dslot - static_cast<int32_t>(sL - sR);  // the same word, indexed from sL
+    int32_t ri[D], ci[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         const bool real = j < dh;
-        const int32_t ri = real ? row.ridx(k0 + j) : 0;
-        const int32_t ci = real ? row.col(k0 + j) : 0;
-        const T l = sL[ci];
-        const T rr = first ? T(0) : sR[ri];
-        const T lv = real ? l : T(__builtin_huge_val());
-        const T q = first ? lv : lv - (real ? rr : T(0));
+        ri[j] = real ? row.ridx(k0 + j) : dslot;
+        ci[j] = real ? row.col(k0 + j) : dslot_l;
+    }
+    T lv[D], rv[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        lv[j] = sL[ci[j]];
+        rv[j] = first ? T(0) : sR[ri[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const bool real = j < dh;
+        const T l = real ? lv[j] : T(__builtin_huge_val());
+        const T q = first ? l : l - (real ? rv[j] : T(0));
         typename A::Term a_k;
         check_forward<A>(q, a_k, p[j], acc, sign);
         kp[j] = A::keep(a_k);
-        if (real) {
-            sR[ri] = A::park(a_k);
-            sL[ci] = q;
-        }
+        sR[ri[j]] = A::park(a_k);
+        sL[ci[j]] = q;
     }
     const typename A::Acc s_other = pair_swap(acc);
     const uint32_t sign_total = sign ^ pair_swap(sign);
@@ -234,15 +244,11 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh,
 #pragma unroll
     for (int j = D - 1; j >= 0; --j) {
         const bool real = j < dh;
-        const int32_t ri = real ? row.ridx(k0 + j) : 0;
-        const typename A::Term a_k = A::unpark(real ? sR[ri] : T(A::kDummyParked), kp[j]);
+        const typename A::Term a_k = A::unpark(real ? sR[ri[j]] : T(A::kDummyParked), kp[j]);
         const T r = check_backward<A>(a_k, p[j], s, s_other, sign_total);
-        if (real) {
-            const int32_t ci = row.col(k0 + j);
-            const T q = sL[ci];
-            sR[ri] = r;
-            sL[ci] = q + r;
-        }
+        const T q = sL[ci[j]];
+        sR[ri[j]] = r;
+        sL[ci[j]] = q + r;
     }
 }
 
@@ -279,16 +285,29 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, type
     MinState<T> st;
     min_init(st);
     uint32_t par = 0;
+    // dummy edges read and write only this thread's dummy slot, and enter as
+    // q = +inf, which leaves the minimum state unchanged
+    const int32_t dslot = static_cast<int32_t>(sL - sR) - kDummySlots + static_cast<int32_t>(threadIdx.x);
+    const int32_t dslot_l = dslot - static_cast<int32_t>(sL - sR);
+    int32_t ri[D], ci[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         const bool real = j < dh;
-        const int32_t ri = real ? row.ridx(k0 + j) : 0;
-        const T l = sL[real ? row.col(k0 + j) : 0];
-        const T rr = first ? T(0) : sR[ri];
-        par ^= static_cast<uint32_t>(real && l < T(0));
-        q[j] = first ? l : l - rr;
-        if (real)
-            min_add(st, q[j], k0 + j);
+        ri[j] = real ? row.ridx(k0 + j) : dslot;
+        ci[j] = real ? row.col(k0 + j) : dslot_l;
+    }
+    T lv[D], rv[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        lv[j] = sL[ci[j]];
+        rv[j] = first ? T(0) : sR[ri[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const bool real = j < dh;
+        par ^= static_cast<uint32_t>(real && lv[j] < T(0));
+        q[j] = real ? (first ? lv[j] : lv[j] - rv[j]) : T(__builtin_huge_val());
+        min_add(st, q[j], k0 + j);
     }
     const T o_m1 = pair_swap(st.m1), o_m2 = pair_swap(st.m2);
     const int32_t o_idx = static_cast<int32_t>(pair_swap(static_cast<uint32_t>(st.idx)));
@@ -298,12 +317,10 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, type
         parity |= par ^ pair_swap(par);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        if (j < dh) {
-            const T r = min_message<A>(st, q[j], k0 + j, scale, offset);
-            sR[row.ridx(k0 + j)] = r;
-            if (LAYERED)
-                sL[row.col(k0 + j)] = q[j] + r;
-        }
+        const T r = min_message<A>(st, q[j], k0 + j, scale, offset);
+        sR[ri[j]] = r;
+        if (LAYERED)
+            sL[ci[j]] = q[j] + r;
     }
 }
 
