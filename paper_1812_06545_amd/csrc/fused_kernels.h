@@ -76,7 +76,7 @@ __host__ __device__ inline size_t frame_lds_bytes(int64_t E, int32_t n, int32_t 
                                                   size_t tsize)
 {
     const size_t msg = (static_cast<size_t>(E) + kDummySlots + static_cast<size_t>(n)) * tsize;
-    return (msg + 15) / 16 * 16 + static_cast<size_t>(words + nblocks + mb) * sizeof(int32_t);
+    return (msg + 15) / 16 * 16 + static_cast<size_t>(words + 2 * nblocks + mb) * sizeof(int32_t);
 }
 
 // Index view of one check row in slot order.
@@ -369,12 +369,12 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
     const int32_t m = c.m, n = c.n, Z = c.Z;
     const T *llr = static_cast<const T *>(job.llr) + f * n;
     // QC tables in LDS: [row_blk_start mb+1][blk_col][blk_shift][col_blk_start nb+1][col_blk][pack][brow_order]
+    //                   [column pack]
     const int32_t *rbs = sTab;
-    const int32_t *bshift = sTab + (c.mb + 1) + c.nblocks;
-    const int32_t *cbs = bshift + c.nblocks;
-    const int32_t *cblk = cbs + (c.nb + 1);
+    const int32_t *cbs = sTab + (c.mb + 1) + 2 * c.nblocks;
     const int32_t *pack = sTab + c.words;
     const int32_t *border = pack + c.nblocks;
+    const int32_t *cpack = border + c.mb;  // per block-column slot: (block * Z) | (shift << 16)
 
     for (int j = tid; j < n; j += NT)
         sL[j] = llr[j] * T(A::kIn);
@@ -437,10 +437,11 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
                 const int32_t cc = j - bj * Z;
                 const int32_t k0 = cbs[bj];
                 auto edge = [&](int k) {
-                    const int32_t b = cblk[k0 + k];
+                    const uint32_t w = static_cast<uint32_t>(cpack[k0 + k]);
                     // cc - shift in (-Z, Z); as unsigned, min picks it or it + Z
-                    const uint32_t r = static_cast<uint32_t>(cc - bshift[b]);
-                    return b * Z + static_cast<int32_t>(__builtin_elementwise_min(r, r + static_cast<uint32_t>(Z)));
+                    const uint32_t r = static_cast<uint32_t>(cc) - (w >> 16);
+                    return static_cast<int32_t>((w & 0xffffu) +
+                                                __builtin_elementwise_min(r, r + static_cast<uint32_t>(Z)));
                 };
                 v = fused_col_dispatch<A, 0>(dwave, edge, cbs[bj + 1] - k0, acc, sR);
             } else {
@@ -623,6 +624,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWaves
                     sTab[c.words + w] = (bcol[w] * c.Z) | (bsh[w] << 16);
                 for (int w = threadIdx.x; w < c.mb; w += blockDim.x)
                     sTab[c.words + c.nblocks + w] = c.brow_order[w];
+                // the column phase's view: block-column slot w holds block cb[w]
+                const int32_t *cb = bsh + c.nblocks + (c.nb + 1);
+                for (int w = threadIdx.x; w < c.nblocks; w += blockDim.x)
+                    sTab[c.words + c.nblocks + c.mb + w] = (cb[w] * c.Z) | (bsh[cb[w]] << 16);
             }
             __syncthreads();
         }
