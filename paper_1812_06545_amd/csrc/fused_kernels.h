@@ -76,7 +76,7 @@ __host__ __device__ inline size_t frame_lds_bytes(int64_t E, int32_t n, int32_t 
                                                   size_t tsize)
 {
     const size_t msg = (static_cast<size_t>(E) + kDummySlots + static_cast<size_t>(n)) * tsize;
-    return (msg + 15) / 16 * 16 + static_cast<size_t>(words + 2 * nblocks + mb) * sizeof(int32_t);
+    return (msg + 15) / 16 * 16 + static_cast<size_t>(words + 2 * nblocks + mb + 1) * sizeof(int32_t);
 }
 
 // Index view of one check row in slot order.
@@ -325,8 +325,12 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, type
 }
 
 // Column sum L = Lch + sum of r in ascending row order, run-time degree dv <= D
-// (dummy edges read slot 0 and are not added).
-template <class A, int D, class Edge>
+// (dummy edges read a valid slot and are not added).  SAFE0: the edge table
+// has a readable first slot even for an empty column (the circulant tables
+// in LDS end with a spare word), so dummies read the column's first edge
+// unconditionally and no load needs an exec-mask branch; otherwise they read
+// message slot 0.
+template <class A, int D, bool SAFE0, class Edge>
 __device__ __forceinline__ typename A::T fused_col(const Edge &edge, int dv, typename A::T acc,
                                                    const typename A::T *__restrict__ sR)
 {
@@ -334,14 +338,14 @@ __device__ __forceinline__ typename A::T fused_col(const Edge &edge, int dv, typ
     T rv[D > 0 ? D : 1];
 #pragma unroll
     for (int k = 0; k < D; ++k)
-        rv[k] = sR[k < dv ? edge(k) : 0];
+        rv[k] = SAFE0 ? sR[edge(k < dv ? k : 0)] : sR[k < dv ? edge(k) : 0];
 #pragma unroll
     for (int k = 0; k < D; ++k)
         acc = k < dv ? acc + rv[k] : acc;
     return acc;
 }
 
-template <class A, int D, class Edge>
+template <class A, int D, bool SAFE0, class Edge>
 __device__ __forceinline__ typename A::T fused_col_dispatch(int dwave, const Edge &edge, int dv, typename A::T acc,
                                                             const typename A::T *__restrict__ sR)
 {
@@ -351,8 +355,8 @@ __device__ __forceinline__ typename A::T fused_col_dispatch(int dwave, const Edg
         return acc;
     } else if constexpr (D <= 16) {
         if (dwave == D)
-            return fused_col<A, D>(edge, dv, acc, sR);
-        return fused_col_dispatch<A, D + 1>(dwave, edge, dv, acc, sR);
+            return fused_col<A, D, SAFE0>(edge, dv, acc, sR);
+        return fused_col_dispatch<A, D + 1, SAFE0>(dwave, edge, dv, acc, sR);
     } else {
         for (int k = 0; k < dv; ++k)
             acc += sR[edge(k)];
@@ -443,11 +447,11 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
                     return static_cast<int32_t>((w & 0xffffu) +
                                                 __builtin_elementwise_min(r, r + static_cast<uint32_t>(Z)));
                 };
-                v = fused_col_dispatch<A, 0>(dwave, edge, cbs[bj + 1] - k0, acc, sR);
+                v = fused_col_dispatch<A, 0, true>(dwave, edge, cbs[bj + 1] - k0, acc, sR);
             } else {
                 const int32_t k0 = c.col_ptr[j];
                 auto edge = [&](int k) { return c.col_edge[k0 + k]; };
-                v = fused_col_dispatch<A, 0>(dwave, edge, c.col_ptr[j + 1] - k0, acc, sR);
+                v = fused_col_dispatch<A, 0, false>(dwave, edge, c.col_ptr[j + 1] - k0, acc, sR);
             }
             sL[j] = v;
         }
@@ -628,6 +632,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWaves
                 const int32_t *cb = bsh + c.nblocks + (c.nb + 1);
                 for (int w = threadIdx.x; w < c.nblocks; w += blockDim.x)
                     sTab[c.words + c.nblocks + c.mb + w] = (cb[w] * c.Z) | (bsh[cb[w]] << 16);
+                if (threadIdx.x == 0)  // a readable word past the end: first slot of an empty column
+                    sTab[c.words + 2 * c.nblocks + c.mb] = 0;
             }
             __syncthreads();
         }

@@ -156,6 +156,32 @@ def test_fused_small_and_degenerate_codes(L):
                 assert np.array_equal(bits, pb) and np.array_equal(iters, pi) and np.array_equal(post, pp)
 
 
+def test_fused_qc_with_empty_base_rows_and_columns(L):
+    """Circulant codes whose base matrix has empty block-columns (first,
+    middle, last) and an empty block-row: the fused kernel's column phase
+    reads a spare table word for empty columns and its row phase skips empty
+    rows; results equal the oracle and the plain path bit for bit."""
+    rng = np.random.default_rng(17)
+    Z = 27
+    shifts = rng.integers(0, Z, size=(4, 10)).astype(np.int32)
+    shifts[:, [0, 4, 9]] = -1          # empty block-columns, the last one included
+    shifts[2, :] = -1                  # an empty block-row
+    shifts[0, 1] = shifts[1, 3] = -1   # some ordinary holes
+    code = codes.qc_expand(shifts, Z, "qc with empty base rows and columns")
+    h = L.Code.from_workload(code)
+    fits, _ = L.ldpc_batch_fits_fused(h, L.LDPC_F32)
+    assert fits
+    llr = rng.normal(0.8, 2.0, size=(131, code.n)).astype(np.float32)
+    for es in (False, True):
+        for T in (1, 6):
+            _log(f"[gpu] fused {code.name} T={T} es={es}")
+            bits, iters, post = _np(_batch(L, [(h, llr)], es=es, T=T)[0])
+            ref = oracle.decode(code, llr, T, es)
+            compare(ref, bits, iters, post, np.float32, f"fused {code.name}")
+            pb, pi, pp = _plain(L, h, llr, T, es)
+            assert np.array_equal(bits, pb) and np.array_equal(iters, pi) and np.array_equal(post, pp)
+
+
 def test_fused_noiseless_zero_iterations(L):
     b = configs.qc1944(2.0, frames=40)
     h = L.Code.from_workload(b.code)
