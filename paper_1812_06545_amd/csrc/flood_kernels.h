@@ -41,6 +41,24 @@ __device__ __forceinline__ void st_lane(T *base, uint32_t lane_off, T v)
 {
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + lane_off) = v;
 }
+// Gathers of a chunk's posteriors through one buffer resource: the lane
+// offset is the vector offset and the row's column (times the column
+// stride) the scalar offset, so no gathered load needs vector address
+// arithmetic.  The resource covers exactly the chunk's n x 64 posteriors
+// (a load outside it would return 0; none is made).
+constexpr int32_t kBufferWord3 = 0x00020000;  // raw 32-bit access, gfx9-family layout
+template <class T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const T *base, int32_t n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(base), 0, n * kChunk * static_cast<int32_t>(sizeof(T)),
+                                             kBufferWord3);
+}
+__device__ __forceinline__ float ld_gather(__amdgpu_buffer_rsrc_t rsrc, uint32_t lane_off, int32_t col, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                         rsrc, static_cast<int32_t>(lane_off), col * kChunk * 4, 0));
+}
+
 // Non-temporal forms for the streamed messages r (read once and written once
 // per launch, no reuse inside it); the gathered posteriors keep the cached forms.
 template <class T>
@@ -60,14 +78,19 @@ __device__ __forceinline__ void st_lane_nt(T *base, uint32_t lane_off, T v)
 // evaluated here (two independent chains).
 template <class A, int D, bool FIRST, bool ES>
 __device__ __forceinline__ void check_row(const int32_t *__restrict__ cols, const typename A::T *__restrict__ L,
-                                          typename A::T *__restrict__ Rrow, uint32_t off, uint32_t &parity)
+                                          int32_t n, typename A::T *__restrict__ Rrow, uint32_t off,
+                                          uint32_t &parity)
 {
     using T = typename A::T;
     constexpr int H = (D + 1) / 2;
+    const __amdgpu_buffer_rsrc_t rsrc = chunk_rsrc(L, n);
     T lv[D], rv[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        lv[k] = ld_lane(L + cols[k] * kChunk, off);
+        if constexpr (std::is_same<T, float>::value)
+            lv[k] = ld_gather(rsrc, off, cols[k], T(0));
+        else
+            lv[k] = ld_lane(L + cols[k] * kChunk, off);
         rv[k] = FIRST ? T(0) : ld_lane_nt(Rrow + k * kChunk, off);
     }
     typename A::Term a[D];
@@ -139,16 +162,16 @@ __device__ __forceinline__ void check_row_guarded(const int32_t *__restrict__ co
 // is that of its largest body, hence one kernel per degree bucket DB.
 template <class A, int D, int DB, bool FIRST, bool ES>
 __device__ __forceinline__ void check_row_exact(int d, const int32_t *__restrict__ cols,
-                                                const typename A::T *__restrict__ L, typename A::T *__restrict__ Rrow,
-                                                uint32_t off, uint32_t &parity)
+                                                const typename A::T *__restrict__ L, int32_t n,
+                                                typename A::T *__restrict__ Rrow, uint32_t off, uint32_t &parity)
 {
     if constexpr (D < DB) {
         if (d == D)
-            check_row<A, D, FIRST, ES>(cols, L, Rrow, off, parity);
+            check_row<A, D, FIRST, ES>(cols, L, n, Rrow, off, parity);
         else
-            check_row_exact<A, D + 1, DB, FIRST, ES>(d, cols, L, Rrow, off, parity);
+            check_row_exact<A, D + 1, DB, FIRST, ES>(d, cols, L, n, Rrow, off, parity);
     } else {
-        check_row<A, DB, FIRST, ES>(cols, L, Rrow, off, parity);
+        check_row<A, DB, FIRST, ES>(cols, L, n, Rrow, off, parity);
     }
 }
 
@@ -180,7 +203,7 @@ __global__ __launch_bounds__(256) void k_check(const int32_t *__restrict__ row_p
     const T *Lc = L + static_cast<int64_t>(chunk) * n * kChunk;
     if (d > 0) {
         if constexpr (EXACT)
-            check_row_exact<A, 1, DB, FIRST, ES>(d, col_idx + e0, Lc, Rrow, off, parity);
+            check_row_exact<A, 1, DB, FIRST, ES>(d, col_idx + e0, Lc, n, Rrow, off, parity);
         else
             check_row_guarded<A, DB, FIRST, ES>(col_idx + e0, d, Lc, Rrow, off, parity);
     }

@@ -84,8 +84,10 @@ struct ArithF32 {
     __device__ static __forceinline__ Acc merge(Acc a, Acc b) { return Acc{a.P * b.P, oplus(a.Q, b.Q)}; }
     __device__ static __forceinline__ float message(Acc x)
     {
-        float z = (x.P + x.P) * __builtin_amdgcn_rcpf(x.Q);
-        z = __builtin_fminf(z, 0x1p100f);  // Q -> 0: keeps the result finite (about 100) before the clamp
+        // Q = 0 (a degree-1 row, or every other edge certain) gives z = +inf,
+        // w = +inf, c = 0 and log2 = +inf, which the clamp turns into R_MAX.
+        // (P = 0 forces Q = 1, so z is never 0 * inf.)
+        const float z = (x.P + x.P) * __builtin_amdgcn_rcpf(x.Q);
         const float w = 1.0f + z;
         float c = (1.0f - w) + z;
         c = (z < 1.0f) ? c : 0.0f;
