@@ -58,6 +58,11 @@ __device__ __forceinline__ float ld_gather(__amdgpu_buffer_rsrc_t rsrc, uint32_t
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
                                          rsrc, static_cast<int32_t>(lane_off), col * kChunk * 4, 0));
 }
+__device__ __forceinline__ void st_scatter(__amdgpu_buffer_rsrc_t rsrc, uint32_t lane_off, int32_t col, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rsrc, static_cast<int32_t>(lane_off),
+                                          col * kChunk * 4, 0);
+}
 
 // Non-temporal forms for the streamed messages r (read once and written once
 // per launch, no reuse inside it); the gathered posteriors keep the cached forms.

@@ -25,6 +25,9 @@ using flood::ld_lane_nt;
 using flood::map_block;
 using flood::st_lane;
 using flood::st_lane_nt;
+using flood::chunk_rsrc;
+using flood::ld_gather;
+using flood::st_scatter;
 
 // One check row of compile-time degree D: all loads first, then the forward
 // and backward sweeps; each new message and its posterior are stored as soon
@@ -32,15 +35,20 @@ using flood::st_lane_nt;
 // are all 0.  Messages stream with non-temporal accesses; posteriors, which
 // later layers gather, stay cached.
 template <class A, int D, bool FIRST>
-__device__ __forceinline__ void layer_row(const int32_t *__restrict__ cols, typename A::T *__restrict__ L,
+__device__ __forceinline__ void layer_row(const int32_t *__restrict__ cols, typename A::T *__restrict__ L, int32_t n,
                                           typename A::T *__restrict__ Rrow, uint32_t off)
 {
     using T = typename A::T;
+    constexpr bool kBuf = std::is_same<T, float>::value;  // posterior gathers and scatters by buffer access
     constexpr int H = (D + 1) / 2;
+    const __amdgpu_buffer_rsrc_t rsrc = chunk_rsrc(L, n);
     T q[D], rv[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        q[k] = ld_lane(L + cols[k] * kChunk, off);
+        if constexpr (kBuf)
+            q[k] = ld_gather(rsrc, off, cols[k], T(0));
+        else
+            q[k] = ld_lane(L + cols[k] * kChunk, off);
         rv[k] = FIRST ? T(0) : ld_lane_nt(Rrow + k * kChunk, off);
     }
     typename A::Term a[D];
@@ -58,7 +66,10 @@ __device__ __forceinline__ void layer_row(const int32_t *__restrict__ cols, type
     for (int k = D - 1; k >= 0; --k) {
         const T r = k < H ? check_backward<A>(a[k], p[k], s0, acc1, sign) : check_backward<A>(a[k], p[k], s1, acc0, sign);
         st_lane_nt(Rrow + k * kChunk, off, r);
-        st_lane(L + cols[k] * kChunk, off, q[k] + r);
+        if constexpr (kBuf)
+            st_scatter(rsrc, off, cols[k], q[k] + r);
+        else
+            st_lane(L + cols[k] * kChunk, off, q[k] + r);
     }
 }
 
@@ -109,15 +120,15 @@ __device__ __forceinline__ void layer_row_guarded(const int32_t *__restrict__ co
 // Exact-degree dispatch for d in [D, DB] (straight-line body per degree).
 template <class A, int D, int DB, bool FIRST>
 __device__ __forceinline__ void layer_row_exact(int d, const int32_t *__restrict__ cols, typename A::T *__restrict__ L,
-                                                typename A::T *__restrict__ Rrow, uint32_t off)
+                                                int32_t n, typename A::T *__restrict__ Rrow, uint32_t off)
 {
     if constexpr (D < DB) {
         if (d == D)
-            layer_row<A, D, FIRST>(cols, L, Rrow, off);
+            layer_row<A, D, FIRST>(cols, L, n, Rrow, off);
         else
-            layer_row_exact<A, D + 1, DB, FIRST>(d, cols, L, Rrow, off);
+            layer_row_exact<A, D + 1, DB, FIRST>(d, cols, L, n, Rrow, off);
     } else {
-        layer_row<A, DB, FIRST>(cols, L, Rrow, off);
+        layer_row<A, DB, FIRST>(cols, L, n, Rrow, off);
     }
 }
 
@@ -149,7 +160,7 @@ __global__ __launch_bounds__(256) void k_layer(const int32_t *__restrict__ row_p
     T *Lc = L + static_cast<int64_t>(chunk) * n * kChunk;
     if (d > 0) {
         if constexpr (EXACT)
-            layer_row_exact<A, 1, DB, FIRST>(d, col_idx + e0, Lc, Rrow, off);
+            layer_row_exact<A, 1, DB, FIRST>(d, col_idx + e0, Lc, n, Rrow, off);
         else
             layer_row_guarded<A, DB, FIRST>(col_idx + e0, d, Lc, Rrow, off);
     }
