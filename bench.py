@@ -39,8 +39,10 @@ def parse():
                          "layered: ldpc_decode with the layered schedule (10 passes instead of iterations)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=2.0,
-                    help="length of the open-loop serving run (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the measured open-loop serving run (0 = skip)")
+    ap.add_argument("--serve-warmup", type=float, default=1.0,
+                    help="seconds of the same traffic before the measured run (statistics reset after it)")
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="offered requests per second")
     ap.add_argument("--no-extra", action="store_true", help="skip the batch-path and other-workload timings")
     ap.add_argument("--profile-every", type=int, default=PROFILE_EVERY,
@@ -222,7 +224,8 @@ def main():
     if copy and achieved:
         roofline["frac_of_copy"] = achieved / copy["gbs"]
 
-    serving = serve_run(args.serve_seconds, args.serve_rate) if args.serve_seconds > 0 else None
+    serving = serve_run(args.serve_seconds, args.serve_rate, warmup_s=args.serve_warmup) \
+        if args.serve_seconds > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -556,11 +559,14 @@ def copy_probe(mb):
     return {"bytes": 2 * nbytes, "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
-def serve_run(seconds, rate, max_group_frames=1024, max_inflight=3):
+def serve_run(seconds, rate, max_group_frames=1024, max_inflight=3, warmup_s=0.0):
     """Open-loop serving run: Poisson arrivals of decode requests (1-64 frames
     of one of the 12 QC codes, Eb/N0 uniform in [1, 3] dB per frame, 10
     iterations with early stop) submitted at their scheduled times; latency is
     completion minus scheduled arrival, so a backlog is not hidden.  The
+    first warmup_s seconds of the same traffic run before the measured window:
+    the server's statistics are reset when the schedule crosses into it (a
+    request admitted before and completed after counts in the window).  The
     submitter's own lateness (time past the scheduled arrival when a request
     is handed over) is reported beside the latencies: it is part of them."""
     import ctypes
@@ -575,7 +581,7 @@ def serve_run(seconds, rate, max_group_frames=1024, max_inflight=3):
     handles = [L.Code.from_workload(c) for c in pool.codes]
     llr = [pool.llr_pool(i) for i in range(12)]
     outs = [(np.zeros((64, c.n), np.uint8), np.zeros(64, np.int32)) for c in pool.codes]
-    sched = configs.serve_schedule(seconds, rate)
+    sched = configs.serve_schedule(warmup_s + seconds, rate)
     # every request's host pointers are worked out before the clock starts
     plan = []
     for k, rq in enumerate(sched):
@@ -597,10 +603,21 @@ def serve_run(seconds, rate, max_group_frames=1024, max_inflight=3):
         rejected = 0
         gc.collect()
         gc.disable()
+        reset_at = int(warmup_s * 1e9)
+        window = warmup_s <= 0
+        first = pending = 0
         try:
             t0 = mono() + 2_000_000
+            t_window = t0
             for i, (off, cid, frames, lp, bp, ip) in enumerate(plan):
                 at = t0 + off
+                if not window and off >= reset_at:
+                    t_window = t0 + reset_at
+                    while mono() < t_window:
+                        pass
+                    s0 = L.ldpc_server_stats_get(srv, reset=True)  # the counts up to the reset
+                    pending = s0["submitted"] - s0["completed"] - s0["failed"] - s0["cancelled"]
+                    rejected, first, window = 0, i, True
                 now = mono()
                 while now < at:
                     now = mono()
@@ -608,18 +625,19 @@ def serve_run(seconds, rate, max_group_frames=1024, max_inflight=3):
                 rejected += submit(srv, cid, frames, 10, 1, lp, bp, ip, None, at, ticket_ref) != 0
         finally:
             gc.enable()
-        while True:
+        while True:  # requests still in flight at the reset complete inside the window
             s = L.ldpc_server_stats_get(srv)
-            if s["completed"] + s["failed"] >= s["submitted"]:
+            if s["completed"] + s["failed"] >= s["submitted"] + pending:
                 break
             time.sleep(0.001)
-        wall = (time.monotonic_ns() - t0) / 1e9
+        wall = (time.monotonic_ns() - t_window) / 1e9
     finally:
         L.ldpc_server_destroy(srv)
-    lag_ms = np.sort(lag) / 1e6
+    lag_ms = np.sort(lag[first:]) / 1e6
     return {"workload": "serve: Poisson arrivals, 1-64 frames of one of 12 QC codes (Z 27/54/81 x rate 1/2..5/6), "
                         "Eb/N0 U[1,3] dB, 10 iterations with early stop",
-            "offered_req_per_s": rate, "duration_s": seconds, "requests": s["completed"], "rejected": rejected,
+            "offered_req_per_s": rate, "duration_s": seconds, "warmup_s": warmup_s, "requests": s["completed"],
+            "rejected": rejected,
             "failed": s["failed"], "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "p999_ms": s["p999_ms"],
             "max_ms": s["max_ms"], "mbps": s["bits_completed"] / wall / 1e6, "launches": s["launches"],
             "mean_group_frames": s["mean_group_frames"], "max_queue_depth": s["max_queue_depth"],
