@@ -745,9 +745,24 @@ extern "C" ldpc_status ldpc_server_stats_get(ldpc_server sv, ldpc_server_stats *
 try {
     if (!sv || !out)
         return LDPC_EINVAL;
-    std::lock_guard<std::mutex> lk(sv->mu);
-    ldpc_server_stats s = sv->st;
-    std::vector<double> v = sv->lat_ms;
+    // Only the snapshot is taken under the lock (a swap when resetting): the
+    // percentiles are computed afterwards, so submitters and the scheduler
+    // are not held up for the O(n) work.
+    ldpc_server_stats s;
+    std::vector<double> v;
+    int64_t group_frames = 0;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        s = sv->st;
+        group_frames = sv->group_frames_sum;
+        if (reset) {
+            v.swap(sv->lat_ms);
+            sv->st = ldpc_server_stats{};
+            sv->group_frames_sum = 0;
+        } else {
+            v = sv->lat_ms;
+        }
+    }
     auto pct = [&](double q) {
         if (v.empty())
             return 0.0;
@@ -759,13 +774,8 @@ try {
     s.p99_ms = pct(0.99);
     s.p999_ms = pct(0.999);
     s.max_ms = v.empty() ? 0.0 : *std::max_element(v.begin(), v.end());
-    s.mean_group_frames = s.launches ? static_cast<double>(sv->group_frames_sum) / static_cast<double>(s.launches) : 0.0;
+    s.mean_group_frames = s.launches ? static_cast<double>(group_frames) / static_cast<double>(s.launches) : 0.0;
     *out = s;
-    if (reset) {
-        sv->st = ldpc_server_stats{};
-        sv->lat_ms.clear();
-        sv->group_frames_sum = 0;
-    }
     return LDPC_OK;
 } catch (...) {
     return ldpc::status_of_exception();
