@@ -27,7 +27,6 @@
 #include <memory>
 #include <mutex>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "ldpc_internal.h"
@@ -246,7 +245,13 @@ struct ldpc_server_s {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request *> queue;
-    std::unordered_map<uint64_t, Request *> by_ticket;
+    // request of ticket t at by_ticket[t - 1]: tickets are consecutive, and a
+    // deque grows in fixed blocks (no rehash or bulk move under the lock)
+    std::deque<Request *> by_ticket;
+    Request *find_ticket(uint64_t t) const
+    {
+        return t >= 1 && t <= by_ticket.size() ? by_ticket[static_cast<size_t>(t - 1)] : nullptr;
+    }
     uint64_t next_ticket = 1;
     bool stop = false;
     bool broken = false;  // the scheduler hit a host allocation failure: requests fail from then on
@@ -257,7 +262,7 @@ struct ldpc_server_s {
 
     // statistics (guarded by mu)
     ldpc_server_stats st{};
-    std::vector<double> lat_ms;
+    std::deque<double> lat_ms;  // grows in fixed blocks: no bulk move under the lock
     int64_t group_frames_sum = 0;
 
     void run();
@@ -524,8 +529,8 @@ void ldpc_server_s::free_all()
         (void)hipFree(d_llr);
     if (h_llr)
         (void)hipHostFree(h_llr);
-    for (auto &kv : by_ticket)
-        delete kv.second;
+    for (Request *r : by_ticket)
+        delete r;
     by_ticket.clear();
 }
 
@@ -671,11 +676,11 @@ try {
         if (sv->stop || static_cast<int32_t>(sv->queue.size()) >= sv->max_queue)
             return LDPC_EBUSY;
         // insert into the ticket map, then the queue; undo the first if the second throws
-        const auto ins = sv->by_ticket.emplace(sv->next_ticket, r);
+        sv->by_ticket.push_back(r);  // at index next_ticket - 1
         try {
             sv->queue.push_back(r);
         } catch (...) {
-            sv->by_ticket.erase(ins.first);
+            sv->by_ticket.pop_back();
             throw;
         }
         owned.release();  // owned by the server from here on
@@ -695,10 +700,10 @@ try {
     if (!sv || !done)
         return LDPC_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
-    auto it = sv->by_ticket.find(ticket);
-    if (it == sv->by_ticket.end())
+    Request *const found = sv->find_ticket(ticket);
+    if (!found)
         return LDPC_EINVAL;
-    const int s = it->second->state;
+    const int s = found->state;
     *done = (s == kDone || s == kCancelled) ? 1 : 0;
     return LDPC_OK;
 } catch (...) {
@@ -710,10 +715,10 @@ try {
     if (!sv)
         return LDPC_EINVAL;
     std::unique_lock<std::mutex> lk(sv->mu);
-    auto it = sv->by_ticket.find(ticket);
-    if (it == sv->by_ticket.end())
+    Request *const found = sv->find_ticket(ticket);
+    if (!found)
         return LDPC_EINVAL;
-    Request *r = it->second;
+    Request *r = found;
     const bool ok = sv->cv_done.wait_for(lk, std::chrono::microseconds(static_cast<int64_t>(timeout_ms * 1e3)),
                                          [&] { return r->state == kDone || r->state == kCancelled; });
     return ok ? LDPC_OK : LDPC_EBUSY;
@@ -726,10 +731,10 @@ try {
     if (!sv)
         return LDPC_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
-    auto it = sv->by_ticket.find(ticket);
-    if (it == sv->by_ticket.end())
+    Request *const found = sv->find_ticket(ticket);
+    if (!found)
         return LDPC_EINVAL;
-    Request *r = it->second;
+    Request *r = found;
     if (r->state != kQueued)
         return LDPC_EBUSY;
     sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), r));
@@ -749,7 +754,7 @@ try {
     // percentiles are computed afterwards, so submitters and the scheduler
     // are not held up for the O(n) work.
     ldpc_server_stats s;
-    std::vector<double> v;
+    std::deque<double> v;
     int64_t group_frames = 0;
     {
         std::lock_guard<std::mutex> lk(sv->mu);
