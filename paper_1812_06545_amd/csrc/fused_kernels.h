@@ -22,8 +22,10 @@
 // message is computed with exactly the operations and rounding of the plain
 // path (bit-identical results).
 //
-// LDS per workgroup: r for every edge, the posterior L for every variable,
-// and the code's circulant-block tables (QC codes).
+// LDS per workgroup: r for every edge, one dummy-edge slot per thread, the
+// posterior L for every variable, and the code's circulant-block tables (QC
+// codes; row and column views, and a spare word that keeps the first slot
+// of an empty block-column readable).
 #pragma once
 
 #include <type_traits>
