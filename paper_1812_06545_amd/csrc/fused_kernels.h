@@ -22,8 +22,8 @@
 // message is computed with exactly the operations and rounding of the plain
 // path (bit-identical results).
 //
-// LDS per workgroup: r for every edge, one dummy-edge slot per thread, the
-// posterior L for every variable, and the code's circulant-block tables (QC
+// LDS per workgroup: r for every edge, a word holding +inf, one dummy-edge
+// slot per thread, the posterior L for every variable, and the code's circulant-block tables (QC
 // codes; row and column views, and a spare word that keeps the first slot
 // of an empty block-column readable).
 #pragma once
@@ -72,12 +72,17 @@ struct Batch {
 // and the posteriors: the target of dummy-edge stores, so that a half row's
 // stores need no exec-mask branch and its loads can all be issued first.
 constexpr int kDummySlots = 512;
+// Index, relative to the posteriors, of one word just before the dummy slots
+// that holds +inf: a flooding half row reads a dummy edge's posterior there,
+// so that q = +inf - (old message) = +inf and the parity bit of +inf (0) need
+// no select.
+constexpr int kInfSlot = -(kDummySlots + 1);
 
 // LDS bytes a workgroup needs for one frame of this code.
 __host__ __device__ inline size_t frame_lds_bytes(int64_t E, int32_t n, int32_t words, int32_t nblocks, int32_t mb,
                                                   size_t tsize)
 {
-    const size_t msg = (static_cast<size_t>(E) + kDummySlots + static_cast<size_t>(n)) * tsize;
+    const size_t msg = (static_cast<size_t>(E) + 1 + kDummySlots + static_cast<size_t>(n)) * tsize;
     return (msg + 15) / 16 * 16 + static_cast<size_t>(words + 2 * nblocks + mb + 1) * sizeof(int32_t);
 }
 
@@ -145,7 +150,7 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
     for (int j = 0; j < D; ++j) {
         const bool real = j < dh;
         ri[j] = real ? row.ridx(k0 + j) : dslot;
-        ci[j] = real ? row.col(k0 + j) : 0;
+        ci[j] = real ? row.col(k0 + j) : kInfSlot;
     }
     T lv[D], rv[D];
 #pragma unroll
@@ -153,12 +158,14 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
         lv[j] = sL[ci[j]];
         rv[j] = first ? T(0) : sR[ri[j]];
     }
+    // A dummy edge reads l = +inf; its slot holds a finite value (a parked
+    // term or a clamped message) written by this thread in an earlier
+    // iteration, so q = +inf and the edge adds nothing to the parity.
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        const bool real = j < dh;
-        const T l = real ? lv[j] : T(__builtin_huge_val());
-        par ^= static_cast<uint32_t>(real && l < T(0));
-        const T q = first ? l : l - (real ? rv[j] : T(0));
+        const T l = lv[j];
+        par ^= static_cast<uint32_t>(l < T(0));
+        const T q = first ? l : l - rv[j];
         typename A::Term a_k;
         check_forward<A>(q, a_k, p[j], acc, sign);
         kp[j] = A::keep(a_k);
@@ -602,9 +609,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWaves
     __shared__ long long s_item;
     const Batch &b = *batch;
     T *sR = reinterpret_cast<T *>(smem);
-    T *sL = sR + b.emax + kDummySlots;
+    T *sL = sR + b.emax + 1 + kDummySlots;
     int32_t *sTab = reinterpret_cast<int32_t *>(
-        smem + (static_cast<size_t>(b.emax + kDummySlots + b.nmax) * sizeof(T) + 15) / 16 * 16);
+        smem + (static_cast<size_t>(b.emax + 1 + kDummySlots + b.nmax) * sizeof(T) + 15) / 16 * 16);
+    if (threadIdx.x == 0)  // published by the first barrier of the item loop
+        sL[kInfSlot] = T(__builtin_huge_val());
     int cur_code = -1;
     for (;;) {
         if (threadIdx.x == 0)
