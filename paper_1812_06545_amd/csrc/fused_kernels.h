@@ -24,8 +24,8 @@
 //
 // LDS per workgroup: r for every edge, a word holding +inf, one dummy-edge
 // slot per thread, the posterior L for every variable, and the code's circulant-block tables (QC
-// codes; row and column views, and a spare word that keeps the first slot
-// of an empty block-column readable).
+// codes; row and column views, and spare zero words after the column view
+// so that a column body may read past its own entries).
 #pragma once
 
 #include <type_traits>
@@ -77,13 +77,19 @@ constexpr int kDummySlots = 512;
 // so that q = +inf - (old message) = +inf and the parity bit of +inf (0) need
 // no select.
 constexpr int kInfSlot = -(kDummySlots + 1);
+// Zero words after the circulant column table: a column body of length D
+// reads table slots k0 .. k0 + D - 1 whatever the column's degree, which for
+// the last block-columns runs up to D - 1 words past the table's end.  A zero
+// word decodes to message index cc < Z, a valid slot.  Exact column bodies go
+// up to degree 16.
+constexpr int kColSpare = 16;
 
 // LDS bytes a workgroup needs for one frame of this code.
 __host__ __device__ inline size_t frame_lds_bytes(int64_t E, int32_t n, int32_t words, int32_t nblocks, int32_t mb,
                                                   size_t tsize)
 {
     const size_t msg = (static_cast<size_t>(E) + 1 + kDummySlots + static_cast<size_t>(n)) * tsize;
-    return (msg + 15) / 16 * 16 + static_cast<size_t>(words + 2 * nblocks + mb + 1) * sizeof(int32_t);
+    return (msg + 15) / 16 * 16 + static_cast<size_t>(words + 2 * nblocks + mb + kColSpare) * sizeof(int32_t);
 }
 
 // Index view of one check row in slot order.
@@ -334,20 +340,21 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, type
 }
 
 // Column sum L = Lch + sum of r in ascending row order, run-time degree dv <= D
-// (dummy edges read a valid slot and are not added).  SAFE0: the edge table
-// has a readable first slot even for an empty column (the circulant tables
-// in LDS end with a spare word), so dummies read the column's first edge
-// unconditionally and no load needs an exec-mask branch; otherwise they read
-// message slot 0.
+// (dummy edges read a valid slot and are not added).  SAFE0: every table
+// slot up to D - 1 past the column's start is readable and decodes to a valid
+// message index (the circulant tables in LDS end with kColSpare zero words),
+// so all D slots are read unconditionally at constant offsets; otherwise
+// dummies read message slot 0.
 template <class A, int D, bool SAFE0, class Edge>
 __device__ __forceinline__ typename A::T fused_col(const Edge &edge, int dv, typename A::T acc,
                                                    const typename A::T *__restrict__ sR)
 {
     using T = typename A::T;
+    static_assert(!SAFE0 || D <= kColSpare, "column body longer than the spare words cover");
     T rv[D > 0 ? D : 1];
 #pragma unroll
     for (int k = 0; k < D; ++k)
-        rv[k] = SAFE0 ? sR[edge(k < dv ? k : 0)] : sR[k < dv ? edge(k) : 0];
+        rv[k] = SAFE0 ? sR[edge(k)] : sR[k < dv ? edge(k) : 0];
 #pragma unroll
     for (int k = 0; k < D; ++k)
         acc = k < dv ? acc + rv[k] : acc;
@@ -362,7 +369,7 @@ __device__ __forceinline__ typename A::T fused_col_dispatch(int dwave, const Edg
         for (int k = 0; k < dv; ++k)
             acc += sR[edge(k)];
         return acc;
-    } else if constexpr (D <= 16) {
+    } else if constexpr (D <= kColSpare) {
         if (dwave == D)
             return fused_col<A, D, SAFE0>(edge, dv, acc, sR);
         return fused_col_dispatch<A, D + 1, SAFE0>(dwave, edge, dv, acc, sR);
@@ -643,8 +650,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWaves
                 const int32_t *cb = bsh + c.nblocks + (c.nb + 1);
                 for (int w = threadIdx.x; w < c.nblocks; w += blockDim.x)
                     sTab[c.words + c.nblocks + c.mb + w] = (cb[w] * c.Z) | (bsh[cb[w]] << 16);
-                if (threadIdx.x == 0)  // a readable word past the end: first slot of an empty column
-                    sTab[c.words + 2 * c.nblocks + c.mb] = 0;
+                if (threadIdx.x < kColSpare)  // readable words past the column table's end
+                    sTab[c.words + 2 * c.nblocks + c.mb + threadIdx.x] = 0;
             }
             __syncthreads();
         }
