@@ -96,6 +96,11 @@ __host__ __device__ inline size_t frame_lds_bytes(int64_t E, int32_t n, int32_t 
 //   QC:  ridx(k) = (rbs + k) * Z + r   (block order),  col(k) from the packed block table
 //   CSR: ridx(k) = e0 + k,             col(k) = col_idx[e0 + k]
 struct RowQC {
+    // The row table in LDS is followed by at least kColSpare readable words
+    // (the block-row order, the column table and its spare words), so col(k)
+    // may be read for any k < kColSpare past a row's blocks: the value is
+    // then some index, which the caller discards.
+    static constexpr bool kReadPast = true;
     int32_t first_block, r, Z;
     const int32_t *pack;  // LDS: (j * Z) | (shift << 16) per block
     __device__ int32_t ridx(int k) const { return (first_block + k) * Z + r; }
@@ -108,11 +113,27 @@ struct RowQC {
 };
 
 struct RowCSR {
+    static constexpr bool kReadPast = false;  // col_idx ends with the last row
     int32_t e0;
     const int32_t *col_idx;
     __device__ int32_t ridx(int k) const { return e0 + k; }
     __device__ int32_t col(int k) const { return col_idx[e0 + k]; }
 };
+
+// Column index of slot k of a half row, or `dummy` for a slot past its real
+// edges.  Where the row view allows it the table is read unconditionally, so
+// the load needs no exec-mask branch.
+template <int D, class Row>
+__device__ __forceinline__ int32_t slot_col(const Row &row, int k, bool real, int32_t dummy)
+{
+    if constexpr (Row::kReadPast) {
+        static_assert(D <= kColSpare, "half row longer than the readable words past the row table");
+        const int32_t c = row.col(k);
+        return real ? c : dummy;
+    } else {
+        return real ? row.col(k) : dummy;
+    }
+}
 
 // Value of the partner lane (lane ^ 32): the other half of the same row.
 // Rows are laid out so that lanes 0..31 of a wavefront hold the first halves
@@ -156,7 +177,7 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
     for (int j = 0; j < D; ++j) {
         const bool real = j < dh;
         ri[j] = real ? row.ridx(k0 + j) : dslot;
-        ci[j] = real ? row.col(k0 + j) : kInfSlot;
+        ci[j] = slot_col<D>(row, k0 + j, real, kInfSlot);
     }
     T lv[D], rv[D];
 #pragma unroll
@@ -234,7 +255,7 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh,
     for (int j = 0; j < D; ++j) {
         const bool real = j < dh;
         ri[j] = real ? row.ridx(k0 + j) : dslot;
-        ci[j] = real ? row.col(k0 + j) : dslot_l;
+        ci[j] = slot_col<D>(row, k0 + j, real, dslot_l);
     }
     T lv[D], rv[D];
 #pragma unroll
@@ -309,7 +330,7 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, type
     for (int j = 0; j < D; ++j) {
         const bool real = j < dh;
         ri[j] = real ? row.ridx(k0 + j) : dslot;
-        ci[j] = real ? row.col(k0 + j) : dslot_l;
+        ci[j] = slot_col<D>(row, k0 + j, real, dslot_l);
     }
     T lv[D], rv[D];
 #pragma unroll
