@@ -153,10 +153,10 @@ __device__ __forceinline__ ArithF32::Acc pair_swap(const ArithF32::Acc &v)
 // One half of a check row, run-time length dh <= D, as the straight-line
 // body of length D: this lane owns edges k0 .. k0+dh-1 of the row (the first
 // half, or the second), its partner lane the other half.  Edges j >= dh are
-// dummies: they enter as q = +inf, r = 0, whose terms are the exact identity
-// of the combination (t = 1, u = 0 in FP32; phi = 0 in FP64) with a + sign;
-// they read posterior slot 0 and this thread's dummy slot (the values are
-// masked) and write only to the dummy slot.  All of the half row's indices
+// dummies: they enter as q = +inf, whose terms are the exact identity of the
+// combination (t = 1, u = 0 in FP32; phi = 0 in FP64) with a + sign; they
+// read the +inf posterior word and this thread's dummy slot, and write only
+// to the dummy slot.  All of the half row's indices
 // and loads are issued before its arithmetic.  The forward pass parks (part
 // of) a_k in the edge's own r slot (free once q_k is formed, owned by this
 // lane alone) instead of a register array; after the partner's half
@@ -202,10 +202,22 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
     const uint32_t sign_total = sign ^ pair_swap(sign);
     parity |= par ^ pair_swap(par);  // a lane may hold several rows: any unsatisfied row counts
     typename A::Acc s = A::identity();
+    // FP64 bodies read the parked value for dummies too (their slot is valid;
+    // the value, possibly a later dummy's message, is replaced), which spares
+    // an exec-mask branch per slot.  FP32 bodies, held to 128 VGPRs, spill
+    // when they do, so there the load stays guarded.
+    constexpr bool kGuardParked = std::is_same<A, ArithF32>::value;
 #pragma unroll
     for (int j = D - 1; j >= 0; --j) {
         const bool real = j < dh;
-        const typename A::Term a_k = A::unpark(real ? sR[ri[j]] : T(A::kDummyParked), kp[j]);
+        T parked;
+        if constexpr (kGuardParked) {
+            parked = real ? sR[ri[j]] : T(A::kDummyParked);
+        } else {
+            const T v = sR[ri[j]];
+            parked = real ? v : T(A::kDummyParked);
+        }
+        const typename A::Term a_k = A::unpark(parked, kp[j]);
         const T r = check_backward<A>(a_k, p[j], s, s_other, sign_total);
         sR[ri[j]] = r;
     }
@@ -280,7 +292,8 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh,
 #pragma unroll
     for (int j = D - 1; j >= 0; --j) {
         const bool real = j < dh;
-        const typename A::Term a_k = A::unpark(real ? sR[ri[j]] : T(A::kDummyParked), kp[j]);
+        const T parked = sR[ri[j]];  // a dummy's slot is valid; its value may be a later dummy's message
+        const typename A::Term a_k = A::unpark(real ? parked : T(A::kDummyParked), kp[j]);
         const T r = check_backward<A>(a_k, p[j], s, s_other, sign_total);
         const T q = sL[ci[j]];
         sR[ri[j]] = r;
