@@ -202,11 +202,11 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
     const uint32_t sign_total = sign ^ pair_swap(sign);
     parity |= par ^ pair_swap(par);  // a lane may hold several rows: any unsatisfied row counts
     typename A::Acc s = A::identity();
-    // FP64 bodies read the parked value for dummies too (their slot is valid;
-    // the value, possibly a later dummy's message, is replaced), which spares
-    // an exec-mask branch per slot.  FP32 bodies, held to 128 VGPRs, spill
-    // when they do, so there the load stays guarded.
-    constexpr bool kGuardParked = std::is_same<A, ArithF32>::value;
+    // The parked value is read for dummies too (their slot is valid; the
+    // value, possibly a later dummy's message, is replaced), which spares an
+    // exec-mask branch per slot.  FP32 bodies are held to 128 VGPRs, and the
+    // long ones (D > 8) spill when they do, so there the load stays guarded.
+    constexpr bool kGuardParked = std::is_same<A, ArithF32>::value && D > 8;
 #pragma unroll
     for (int j = D - 1; j >= 0; --j) {
         const bool real = j < dh;
