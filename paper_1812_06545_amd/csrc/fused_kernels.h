@@ -334,8 +334,8 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, type
     MinState<T> st;
     min_init(st);
     uint32_t par = 0;
-    // dummy edges read and write only this thread's dummy slot, and enter as
-    // q = +inf, which leaves the minimum state unchanged
+    // dummy edges write only this thread's dummy slot and enter as q = +inf,
+    // which leaves the minimum state unchanged
     const int32_t dslot = static_cast<int32_t>(sL - sR) - kDummySlots + static_cast<int32_t>(threadIdx.x);
     const int32_t dslot_l = dslot - static_cast<int32_t>(sL - sR);
     int32_t ri[D], ci[D];
@@ -343,7 +343,10 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, type
     for (int j = 0; j < D; ++j) {
         const bool real = j < dh;
         ri[j] = real ? row.ridx(k0 + j) : dslot;
-        ci[j] = slot_col<D>(row, k0 + j, real, dslot_l);
+        // flooding dummies read the +inf posterior word (see fused_half_row;
+        // a min-sum message is clamped too, so the dummy slot holds a finite
+        // value); layered ones go through the dummy slot, which they write
+        ci[j] = slot_col<D>(row, k0 + j, real, LAYERED ? dslot_l : kInfSlot);
     }
     T lv[D], rv[D];
 #pragma unroll
@@ -354,8 +357,12 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, type
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         const bool real = j < dh;
-        par ^= static_cast<uint32_t>(real && lv[j] < T(0));
-        q[j] = real ? (first ? lv[j] : lv[j] - rv[j]) : T(__builtin_huge_val());
+        if constexpr (LAYERED) {
+            q[j] = real ? (first ? lv[j] : lv[j] - rv[j]) : T(__builtin_huge_val());
+        } else {
+            par ^= static_cast<uint32_t>(lv[j] < T(0));
+            q[j] = first ? lv[j] : lv[j] - rv[j];
+        }
         min_add(st, q[j], k0 + j);
     }
     const T o_m1 = pair_swap(st.m1), o_m2 = pair_swap(st.m2);
