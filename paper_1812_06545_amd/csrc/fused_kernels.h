@@ -73,9 +73,9 @@ struct Batch {
 // stores need no exec-mask branch and its loads can all be issued first.
 constexpr int kDummySlots = 512;
 // Index, relative to the posteriors, of one word just before the dummy slots
-// that holds +inf: a flooding half row reads a dummy edge's posterior there,
-// so that q = +inf - (old message) = +inf and the parity bit of +inf (0) need
-// no select.
+// that holds +inf: half rows read a dummy edge's posterior there, so that
+// q = +inf - (old message) = +inf and the parity bit of +inf (0) need no
+// select; layered half rows write it back unchanged (+inf + r = +inf).
 constexpr int kInfSlot = -(kDummySlots + 1);
 // Zero words after the circulant column table: a column body of length D
 // reads table slots k0 .. k0 + D - 1 whatever the column's degree, which for
@@ -249,8 +249,9 @@ __device__ __forceinline__ void fused_row_dispatch(int hwave, const Row &row, in
 // posteriors at once, L_n = q_mn + r_mn.  No other row of the layer touches
 // these edges or variables, so the forward pass parks q_k in the variable's
 // own L slot and a_k in the edge's r slot; the backward pass reads both back
-// and writes r_new and q_k + r_new.  Dummy edges read and write only this
-// thread's dummy slot (through both arrays); loads are issued first.
+// and writes r_new and q_k + r_new.  Dummy edges keep their messages in this
+// thread's dummy slot and their posterior in the +inf word, which their
+// writes (+inf, and +inf + r) leave unchanged; loads are issued first.
 template <class A, int D, class Row>
 __device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh, typename A::T *__restrict__ sR,
                                                  typename A::T *__restrict__ sL, bool first)
@@ -261,13 +262,12 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh,
     typename A::Acc acc = A::identity();
     uint32_t sign = 0;
     const int32_t dslot = static_cast<int32_t>(sL - sR) - kDummySlots + static_cast<int32_t>(threadIdx.x);
-    const int32_t dslot_l = dslot - static_cast<int32_t>(sL - sR);  // the same word, indexed from sL
     int32_t ri[D], ci[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         const bool real = j < dh;
         ri[j] = real ? row.ridx(k0 + j) : dslot;
-        ci[j] = slot_col<D>(row, k0 + j, real, dslot_l);
+        ci[j] = slot_col<D>(row, k0 + j, real, kInfSlot);
     }
     T lv[D], rv[D];
 #pragma unroll
@@ -277,9 +277,7 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh,
     }
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        const bool real = j < dh;
-        const T l = real ? lv[j] : T(__builtin_huge_val());
-        const T q = first ? l : l - (real ? rv[j] : T(0));
+        const T q = first ? lv[j] : lv[j] - rv[j];  // +inf for a dummy
         typename A::Term a_k;
         check_forward<A>(q, a_k, p[j], acc, sign);
         kp[j] = A::keep(a_k);
@@ -337,16 +335,15 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, type
     // dummy edges write only this thread's dummy slot and enter as q = +inf,
     // which leaves the minimum state unchanged
     const int32_t dslot = static_cast<int32_t>(sL - sR) - kDummySlots + static_cast<int32_t>(threadIdx.x);
-    const int32_t dslot_l = dslot - static_cast<int32_t>(sL - sR);
     int32_t ri[D], ci[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         const bool real = j < dh;
         ri[j] = real ? row.ridx(k0 + j) : dslot;
-        // flooding dummies read the +inf posterior word (see fused_half_row;
-        // a min-sum message is clamped too, so the dummy slot holds a finite
-        // value); layered ones go through the dummy slot, which they write
-        ci[j] = slot_col<D>(row, k0 + j, real, LAYERED ? dslot_l : kInfSlot);
+        // dummies read (and, layered, write back) the +inf posterior word, as
+        // in fused_half_row: a min-sum message is clamped too, so the dummy
+        // slot always holds a finite value
+        ci[j] = slot_col<D>(row, k0 + j, real, kInfSlot);
     }
     T lv[D], rv[D];
 #pragma unroll
@@ -356,13 +353,9 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, type
     }
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        const bool real = j < dh;
-        if constexpr (LAYERED) {
-            q[j] = real ? (first ? lv[j] : lv[j] - rv[j]) : T(__builtin_huge_val());
-        } else {
+        if (!LAYERED)
             par ^= static_cast<uint32_t>(lv[j] < T(0));
-            q[j] = first ? lv[j] : lv[j] - rv[j];
-        }
+        q[j] = first ? lv[j] : lv[j] - rv[j];
         min_add(st, q[j], k0 + j);
     }
     const T o_m1 = pair_swap(st.m1), o_m2 = pair_swap(st.m2);
