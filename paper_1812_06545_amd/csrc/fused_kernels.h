@@ -28,7 +28,9 @@
 // so that a column body may read past its own entries).
 #pragma once
 
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "ldpc_internal.h"
 #include "minsum_kernels.h"
@@ -699,6 +701,64 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWaves
 
 }  // namespace fused
 
+namespace fused {
+
+// Workgroups per CU and CU count for a launch of kernel fn with this LDS size
+// and block size on the current device.  The runtime calls behind them (the
+// kernel's LDS limit, the occupancy query, the device attribute) run once per
+// (kernel, device, LDS bytes, threads) and are cached, not repeated on every
+// launch; the LDS limit is only ever raised.
+inline ldpc_status launch_shape(const void *fn, size_t lds, int threads, int &per_cu, int &cus)
+{
+    struct Shape {
+        const void *fn;
+        int dev;
+        size_t lds;
+        int threads, per_cu, cus;
+    };
+    struct Limit {
+        const void *fn;
+        int dev;
+        size_t lds;
+    };
+    static std::mutex mu;
+    static std::vector<Shape> shapes;
+    static std::vector<Limit> limits;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return LDPC_EDEVICE;
+    std::lock_guard<std::mutex> lk(mu);
+    for (const Shape &e : shapes) {
+        if (e.fn == fn && e.dev == dev && e.lds == lds && e.threads == threads) {
+            per_cu = e.per_cu;
+            cus = e.cus;
+            return LDPC_OK;
+        }
+    }
+    Limit *lim = nullptr;
+    for (Limit &l : limits)
+        if (l.fn == fn && l.dev == dev)
+            lim = &l;
+    if (lim == nullptr || lim->lds < lds) {
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+            return LDPC_EUNSUPPORTED;
+        if (lim == nullptr)
+            limits.push_back(Limit{fn, dev, lds});
+        else
+            lim->lds = lds;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
+        return LDPC_EUNSUPPORTED;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return LDPC_EDEVICE;
+    if (shapes.size() >= 256)  // batches of many different code mixes: start over
+        shapes.clear();
+    shapes.push_back(Shape{fn, dev, lds, threads, per_cu, cus});
+    return LDPC_OK;
+}
+
+}  // namespace fused
+
 // Launcher of the fused kernel for codes of row degree <= DB (one
 // translation unit per dtype and bucket).
 // The caller has already written the batch table to d_batch and reset *counter.
@@ -713,17 +773,11 @@ ldpc_status launch_fused_bucket(const fused::Batch &batch, fused::Batch *d_batch
                                              hipStream_t s)                                                      \
     {                                                                                                            \
         auto kern = fused::k_fused<A_, DB_>;                                                                     \
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                                            \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes)) !=      \
-            hipSuccess)                                                                                          \
-            return LDPC_EUNSUPPORTED;                                                                            \
-        int per_cu = 0, dev = 0, cus = 0;                                                                        \
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds_bytes) != hipSuccess ||     \
-            per_cu < 1)                                                                                          \
-            return LDPC_EUNSUPPORTED;                                                                            \
-        if (hipGetDevice(&dev) != hipSuccess ||                                                                  \
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)              \
-            return LDPC_EDEVICE;                                                                                 \
+        int per_cu = 0, cus = 0;                                                                                 \
+        const ldpc_status shape_rc =                                                                             \
+            fused::launch_shape(reinterpret_cast<const void *>(kern), lds_bytes, threads, per_cu, cus);          \
+        if (shape_rc != LDPC_OK)                                                                                 \
+            return shape_rc;                                                                                     \
         const int64_t grid = std::min<int64_t>(batch.nitems, static_cast<int64_t>(per_cu) * cus);               \
         ProfScope ps(LDPC_KERNEL_FUSED, s);                                                                      \
         LDPC_LAUNCH(ps, kern, dim3(static_cast<unsigned>(grid)), dim3(threads), static_cast<uint32_t>(lds_bytes), \
