@@ -334,8 +334,8 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, type
     MinState<T> st;
     min_init(st);
     uint32_t par = 0;
-    // dummy edges write only this thread's dummy slot and enter as q = +inf,
-    // which leaves the minimum state unchanged
+    // dummy edges enter as q = +inf, which leaves the minimum state
+    // unchanged, and store their messages in this thread's dummy slot
     const int32_t dslot = static_cast<int32_t>(sL - sR) - kDummySlots + static_cast<int32_t>(threadIdx.x);
     int32_t ri[D], ci[D];
 #pragma unroll
