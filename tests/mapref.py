@@ -45,3 +45,27 @@ def _lse(v):
 def dense_syndrome(code, bits: np.ndarray) -> np.ndarray:
     H = code.to_dense().astype(np.int64)
     return (np.atleast_2d(bits).astype(np.int64) @ H.T) % 2
+
+
+def depth1_tree(code, root: int):
+    """The depth-1 computation tree of variable `root`: the root joined to
+    each of its checks, and every other variable of those checks as a fresh
+    leaf (a variable met through two checks appears twice).  Returns the tree
+    as a code (the root is variable 0) and, per tree variable, the variable
+    of `code` it copies.  One flooding iteration at the root sees exactly
+    this tree, so its posterior there is the tree's exact MAP."""
+    from workloads.codes import Code
+
+    H = code.to_dense()
+    src = [root]
+    rows = []
+    for m in np.flatnonzero(H[:, root]):
+        members = [0]
+        for j in np.flatnonzero(H[m]):
+            if j == root:
+                continue
+            members.append(len(src))
+            src.append(int(j))
+        rows.append(members)
+    tree = Code.from_row_lists(len(rows), len(src), rows, f"depth-1 tree of {root}")
+    return tree, np.array(src)

@@ -33,6 +33,36 @@ Pins (each names what it fixes):
   stop_iteration    with early stop, iters is the first t whose hard decision
                     (taken from the early-stop-off run truncated at t) has a
                     zero syndrome by an independent dense product, else T.
+  cond_spc          the conditioning output A_n = |Lch_n| + sum_m |r_mn| on a
+                    single parity check, whose one message is the exact MAP
+                    value minus the channel term (brute force), clamp included.
+  cond_chain        A_n on a repetition chain once every message has settled:
+                    the two messages into variable j are the sums of the
+                    channel LLRs on either side of it, so
+                    A_j = |Lch_j| + |sum_{i<j} Lch_i| + |sum_{i>j} Lch_i|
+                    (mixed signs, so a dropped absolute value or a wrong
+                    column shows).
+  cond_bound        on noisy frames: |Lch| <= A, |posterior| <= A (triangle
+                    inequality) and A - |Lch| <= degree * R_MAX.
+  min_abs_trace     the trace min_n |L_n| at decision point t equals that of
+                    the early-stop-off run truncated at t, for t <= iters;
+                    NaN after the frame stopped; t = 0 is min |Lch|.
+  hamming_first_iteration  Hamming(7,4) (a graph with 4-cycles): after one
+                    iteration the posterior of every bit equals exact MAP on
+                    its depth-1 computation tree (brute force), for all 112
+                    single-error patterns at |L| = 1.5, 2, 3 and random LLRs.
+  hamming_regression  Hamming(7,4), all 112 single-error patterns, 20
+                    iterations with early stop, against exact MAP of the code:
+                    |L| = 2: every pattern is corrected within 2 iterations;
+                    |L| = 3 and 4: an error on the weight-3 column is turned,
+                    in iteration 1, into the weight-3 codeword that the
+                    depth-1 tree MAP decisions predict (MAP corrects it), the
+                    other patterns are corrected; |L| = 1.5: errors on weight-1
+                    and weight-2 columns never clear the syndrome (20
+                    iterations), while an error on the weight-3 column is
+                    corrected in iteration 1.  Beyond iteration 1 these are
+                    regression values of the decoding dynamics on a graph
+                    with cycles (no closed form).
 """
 from __future__ import annotations
 
@@ -41,7 +71,7 @@ import math
 import numpy as np
 
 from workloads import channel, codes, configs
-from mapref import all_codewords, dense_syndrome, map_llr
+from mapref import all_codewords, dense_syndrome, depth1_tree, map_llr
 
 R_MAX = 20.0
 
@@ -189,5 +219,109 @@ def stop_iteration(dec):
     assert (es["iters"] == first).all()
 
 
+def cond_spc(dec):
+    for n, seed in ((3, 63), (6, 64)):
+        code = codes.single_parity_check(n)
+        llr = _rng(seed).normal(0.0, 2.0, size=(5, n))
+        r = map_llr(code, llr) - llr  # the check's message (Gallager's lemma)
+        for T in (1, 2):
+            out = dec(code, llr, T, False)
+            np.testing.assert_allclose(out["cond"], np.abs(llr) + np.abs(r), rtol=1e-9, atol=1e-9,
+                                       err_msg=f"A_n on SPC n={n} T={T}")
+    out = dec(codes.single_parity_check(2), np.array([[30.0, 30.0], [-30.0, 30.0]]), 1, False)
+    np.testing.assert_allclose(out["cond"], np.full((2, 2), 50.0), rtol=1e-12, atol=1e-12)
+
+
+def cond_chain(dec):
+    for n, seed in ((5, 61), (8, 62)):
+        code = codes.repetition_chain(n)
+        llr = _rng(seed).uniform(-2.0, 2.0, size=(4, n))
+        cs = np.cumsum(llr, axis=1)
+        left = cs - llr                      # sum_{i<j}
+        right = cs[:, -1:] - cs              # sum_{i>j}
+        want = np.abs(llr) + np.abs(left) + np.abs(right)
+        assert (np.abs(left + llr + right) < want - 1e-3).any(), "inputs of one sign test nothing"
+        out = dec(code, llr, n + 2, False)
+        np.testing.assert_allclose(out["cond"], want, rtol=1e-9, atol=1e-9, err_msg=f"A_n on chain n={n}")
+
+
+def cond_bound(dec):
+    code, cw, llr = _gallager_noisy(12, 38, ebn0=1.5)
+    out = dec(code, llr, 7, False)
+    A = out["cond"]
+    assert (A >= np.abs(llr)).all()
+    assert (np.abs(out["posterior"]) <= A * (1 + 1e-12)).all()
+    assert (A - np.abs(llr) <= code.col_degrees() * R_MAX * (1 + 1e-12)).all()
+    assert (A > np.abs(out["posterior"]) * (1 + 1e-6)).any(), "no cancellation anywhere: the bound tests nothing"
+
+
+def min_abs_trace(dec):
+    code, cw, llr = _gallager_noisy(16, 39, ebn0=1.8)
+    T = 10
+    es = dec(code, llr, T, True)
+    tr = es["min_abs"]
+    assert tr.shape == (llr.shape[0], T + 1)
+    assert (es["iters"] < T).sum() >= 3 and (es["iters"] >= 2).sum() >= 3
+    np.testing.assert_array_equal(tr[:, 0], np.abs(llr).min(axis=1))
+    for t in range(1, T + 1):
+        want = np.abs(dec(code, llr, t, False)["posterior"]).min(axis=1)
+        ran = es["iters"] >= t
+        np.testing.assert_array_equal(tr[ran, t], want[ran], err_msg=f"min |L| trace at t={t}")
+        assert np.isnan(tr[~ran, t]).all(), f"trace entry after the stop at t={t}"
+    fixed = dec(code, llr, T, False)
+    np.testing.assert_array_equal(fixed["min_abs"][:, T], np.abs(fixed["posterior"]).min(axis=1))
+
+
+def _hamming_single_errors(A):
+    """Every codeword of Hamming(7,4) at reliability A with one bit's sign
+    flipped: (codewords, flipped positions, LLRs), 112 frames."""
+    code = codes.hamming74()
+    cw = all_codewords(code)
+    C = np.repeat(cw, 7, axis=0)
+    P = np.tile(np.arange(7), len(cw))
+    llr = A * (1.0 - 2.0 * C.astype(np.float64))
+    llr[np.arange(len(P)), P] *= -1.0
+    return code, C, P, llr
+
+
+def hamming_first_iteration(dec):
+    trees = [depth1_tree(codes.hamming74(), j) for j in range(7)]
+    inputs = [_hamming_single_errors(A)[3] for A in (1.5, 2.0, 3.0)]
+    inputs.append(_rng(65).normal(0.5, 1.5, size=(20, 7)))
+    for llr in inputs:
+        out = dec(codes.hamming74(), llr, 1, False)
+        for j, (tree, src) in enumerate(trees):
+            want = map_llr(tree, llr[:, src])[:, 0]
+            np.testing.assert_allclose(out["posterior"][:, j], want, rtol=1e-9, atol=1e-9,
+                                       err_msg=f"Hamming(7,4) bit {j} after one iteration")
+
+
+def hamming_regression(dec):
+    weight = codes.hamming74().to_dense().sum(axis=0)
+    for A in (1.5, 2.0, 3.0, 4.0):
+        code, C, P, llr = _hamming_single_errors(A)
+        map_bits = (map_llr(code, llr) < 0).astype(np.uint8)
+        assert (map_bits == C).all(), "MAP corrects every single error"
+        out = dec(code, llr, 20, True)
+        ok = (out["bits"] == C).all(axis=1)
+        w = weight[P]
+        if A == 2.0:
+            assert ok.all() and (out["iters"] <= 2).all(), f"|L|=2: {out['iters']}"
+        elif A >= 3.0:
+            assert ok[w < 3].all() and (out["iters"][w < 3] <= 2).all()
+            sel = np.flatnonzero(w == 3)
+            # iteration 1 by the depth-1 tree MAP of every bit, then the decision
+            trees = [depth1_tree(code, j) for j in range(7)]
+            post1 = np.stack([map_llr(t, llr[sel][:, s])[:, 0] for t, s in trees], axis=1)
+            pred = (post1 < 0).astype(np.uint8)
+            assert (dense_syndrome(code, pred) == 0).all()
+            assert ((pred ^ C[sel]).sum(axis=1) == 3).all(), "the predicted word is a weight-3 neighbour"
+            assert (out["iters"][sel] == 1).all() and (out["bits"][sel] == pred).all(), f"|L|={A} weight-3 column"
+        else:
+            assert (~ok[w < 3]).all() and (out["iters"][w < 3] == 20).all(), f"|L|=1.5: {out['iters']}"
+            assert ok[w == 3].all() and (out["iters"][w == 3] == 1).all()
+
+
 ALL = [spc_map, repetition_sum, tree_map, clamp, noiseless, zero_iter, zero_posterior, symmetry, zero_syndrome,
-       prefix, fixed_iters, stop_iteration]
+       prefix, fixed_iters, stop_iteration, cond_spc, cond_chain, cond_bound, min_abs_trace, hamming_first_iteration,
+       hamming_regression]

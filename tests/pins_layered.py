@@ -25,8 +25,9 @@ Layered-specific pins (each names what it fixes):
                     the paper cites as its reason for the schedule).
 The schedule-independent pins of ``pins`` (SPC MAP after one pass, clamp,
 noiseless, zero iterations, zero posterior, symmetry, zero syndrome, prefix,
-fixed iterations, stop iteration) also hold for the layered schedule and are run
-against it too.
+fixed iterations, stop iteration, and the conditioning output A_n and the
+min |L| trace: single parity check, settled chain, bounds, truncated runs) also
+hold for the layered schedule and are run against it too.
 """
 from __future__ import annotations
 
@@ -111,5 +112,6 @@ def faster_than_flooding(dec):
 
 LAYERED = [chain_forward, chain_backward, tree_map, row_order, faster_than_flooding]
 SHARED = [pins.spc_map, pins.clamp, pins.noiseless, pins.zero_iter, pins.zero_posterior, pins.symmetry,
-          pins.zero_syndrome, pins.prefix, pins.fixed_iters, pins.stop_iteration]
+          pins.zero_syndrome, pins.prefix, pins.fixed_iters, pins.stop_iteration, pins.cond_spc, pins.cond_chain,
+          pins.cond_bound, pins.min_abs_trace]
 ALL = LAYERED + SHARED

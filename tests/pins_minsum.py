@@ -71,6 +71,9 @@ def spc_closed_form(dec):
                 out = dec(code, llr, 1, False, scale=scale, offset=offset, schedule=sched)
                 np.testing.assert_allclose(out["posterior"], want, rtol=0, atol=1e-12,
                                            err_msg=f"SPC n={n} scale={scale} offset={offset} {sched}")
+                # A_n = |Lch_n| + |r_n|, the message being the posterior minus the channel term
+                np.testing.assert_allclose(out["cond"], np.abs(llr) + np.abs(want - llr), rtol=0, atol=1e-12,
+                                           err_msg=f"A_n on SPC n={n} scale={scale} offset={offset} {sched}")
 
 
 def tree_maxlog(dec):
@@ -132,5 +135,6 @@ def _both(check, scale=1.0):
 MINSUM = [spc_closed_form, tree_maxlog, chain_sums, homogeneous]
 SHARED = ([_both(c) for c in (pins.clamp, pins.noiseless, pins.zero_iter, pins.zero_posterior, pins.symmetry,
                               pins.zero_syndrome, pins.fixed_iters, pins.stop_iteration)]
-          + [_both(c, 0.75) for c in (pins.zero_syndrome, pins.prefix, pins.stop_iteration)])
+          + [_both(c, 0.75) for c in (pins.zero_syndrome, pins.prefix, pins.stop_iteration, pins.min_abs_trace)]
+          + [_both(c) for c in (pins.cond_chain, pins.cond_bound)])
 ALL = MINSUM + SHARED

@@ -42,6 +42,10 @@ MUTANTS = {
     "iters_off_by_one": ("t_done = t;", "t_done = t - 1;"),
     "no_initial_stop": ("if (early_stop && layered_syndrome_is_zero(m, row_ptr, col_idx, x)) {\n        t_done = 0;",
                         "if (0) {\n        t_done = 0;"),
+    "cond_message_signed": ("cond[col_idx[e]] += fabs(r[e]);", "cond[col_idx[e]] += r[e];"),
+    "cond_channel_signed": ("cond[j] = fabs(llr[j]);", "cond[j] = llr[j];"),
+    "min_abs_signed": ("if (fabs(L[j]) < v)\n            v = fabs(L[j]);", "if (L[j] < v)\n            v = L[j];"),
+    "min_abs_shifted": ("min_abs[t] = layered_min_abs(n, L);", "min_abs[t - 1] = layered_min_abs(n, L);"),
     "messages_not_reset": ("        r[e] = 0.0;\n    if (min_abs)", "        r[e] = r[e];\n    if (min_abs)"),
 }
 

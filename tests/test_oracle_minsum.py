@@ -41,6 +41,12 @@ MUTANTS = {
                                 "                        L[g->col_idx[e]] = q[e];"),
     "channel_dropped": ("                    double s = llr[j];", "                    double s = 0.0;"),
     "iters_off_by_one": ("                t_done = t;", "                t_done = t - 1;"),
+    "cond_message_signed": ("a += fabs(r[g->col_edge[k]]);", "a += r[g->col_edge[k]];"),
+    "cond_wrong_column": ("for (int32_t k = g->col_ptr[j]; k < g->col_ptr[j + 1]; ++k)\n                a += fabs",
+                          "for (int32_t k = g->col_ptr[(j + 1) % n]; k < g->col_ptr[(j + 1) % n + 1]; ++k)\n"
+                          "                a += fabs"),
+    "min_abs_signed": ("if (fabs(L[j]) < v)\n            v = fabs(L[j]);", "if (L[j] < v)\n            v = L[j];"),
+    "min_abs_shifted": ("min_abs[t] = ms_min_abs(n, L);", "min_abs[t - 1] = ms_min_abs(n, L);"),
 }
 
 

@@ -29,6 +29,13 @@ MUTANTS = {
                         "if (0) {\n        t_done = 0;"),
     "stale_decision": ("x[j] = (uint8_t)(L[j] < 0.0);\n            if (min_abs)",
                        "x[j] = (uint8_t)(q[g->col_ptr[j]] < 0.0);\n            if (min_abs)"),
+    "cond_message_unsigned_dropped": ("a += fabs(r[g->col_edge[k]]);", "a += r[g->col_edge[k]];"),
+    "cond_channel_dropped": ("double a = fabs(llr[j]);", "double a = 0.0;"),
+    "cond_wrong_column": ("for (int32_t k = g->col_ptr[j]; k < g->col_ptr[j + 1]; ++k)\n                a += fabs",
+                          "for (int32_t k = g->col_ptr[(j + 1) % n]; k < g->col_ptr[(j + 1) % n + 1]; ++k)\n"
+                          "                a += fabs"),
+    "min_abs_signed": ("if (fabs(L[j]) < v)\n            v = fabs(L[j]);", "if (L[j] < v)\n            v = L[j];"),
+    "min_abs_shifted": ("min_abs[t] = min_abs_of(n, L);", "min_abs[t - 1] = min_abs_of(n, L);"),
     "first_edge_dropped_in_sum": ("for (int32_t k = g->col_ptr[j]; k < g->col_ptr[j + 1]; ++k)\n                    s += r",
                                   "for (int32_t k = g->col_ptr[j] + 1; k < g->col_ptr[j + 1]; ++k)\n                    s += r"),
 }
