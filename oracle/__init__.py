@@ -21,7 +21,7 @@ import os
 
 import numpy as np
 
-from .build import LIB, compile_oracle
+from .build import LIB, LIB_LD, compile_long_double, compile_oracle
 
 R_MAX = 20.0  # clamp on check-to-variable messages (a reading: the paper gives none)
 
@@ -51,6 +51,22 @@ def _load(path: str = LIB):
             return lib
         _lib = lib
     return _lib
+
+
+_lib_ld = None
+
+
+def long_double_lib():
+    """The flooding sum-product oracle with its check node evaluated in 80-bit
+    long double (each message rounded to double): the same definition at
+    higher precision, for bounding the double oracle's own rounding and for
+    tight FP64 comparisons.  Pass it as ``decode(..., lib=...)``."""
+    global _lib_ld
+    if _lib_ld is None:
+        if not os.path.exists(LIB_LD):
+            compile_long_double()
+        _lib_ld = _load(LIB_LD)
+    return _lib_ld
 
 
 def _ptr(a):

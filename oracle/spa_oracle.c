@@ -34,6 +34,23 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Precision of the check-node evaluation (the tanh terms, their product and
+ * 2 atanh).  Double by default.  The build also compiles a copy with
+ * ORACLE_CHECK_LD defined, which evaluates the same expressions in x87 80-bit
+ * long double and rounds each message to double: the same definition at
+ * higher precision, used to measure the rounding of the double version (near
+ * the clamp 2 atanh(p) with p close to 1 loses digits) and to hold FP64 GPU
+ * results to a tighter bound than that rounding allows. */
+#ifdef ORACLE_CHECK_LD
+typedef long double chk_real;
+#define CHK_TANH tanhl
+#define CHK_ATANH atanhl
+#else
+typedef double chk_real;
+#define CHK_TANH tanh
+#define CHK_ATANH atanh
+#endif
+
 #define ORACLE_EINVAL (-1)
 #define ORACLE_ENOMEM (-2)
 
@@ -68,7 +85,7 @@ struct graph {
 
 static void decode_one_frame(const struct graph *g, const double *llr, int max_iter, int early_stop,
                              double r_max, uint8_t *bits, int32_t *iters, double *posterior,
-                             double *cond, double *min_abs, double *q, double *r, double *th,
+                             double *cond, double *min_abs, double *q, double *r, chk_real *th,
                              double *L, uint8_t *x)
 {
     const int m = g->m, n = g->n;
@@ -98,13 +115,13 @@ static void decode_one_frame(const struct graph *g, const double *llr, int max_i
             for (int i = 0; i < m; ++i) {
                 const int32_t e0 = g->row_ptr[i], e1 = g->row_ptr[i + 1];
                 for (int32_t e = e0; e < e1; ++e)
-                    th[e] = tanh(q[e] / 2.0);
+                    th[e] = CHK_TANH((chk_real)q[e] / 2);
                 for (int32_t e = e0; e < e1; ++e) {
-                    double p = 1.0;
+                    chk_real p = 1;
                     for (int32_t o = e0; o < e1; ++o)
                         if (o != e)
                             p *= th[o];
-                    double v = 2.0 * atanh(p);
+                    double v = (double)(2 * CHK_ATANH(p));
                     if (v > r_max)
                         v = r_max;
                     if (v < -r_max)
@@ -206,7 +223,7 @@ int oracle_spa_decode(int m, int n, const int32_t *row_ptr, const int32_t *col_i
     {
         double *q = (double *)malloc(((size_t)E + 1) * sizeof(double));
         double *r = (double *)malloc(((size_t)E + 1) * sizeof(double));
-        double *th = (double *)malloc(((size_t)E + 1) * sizeof(double));
+        chk_real *th = (chk_real *)malloc(((size_t)E + 1) * sizeof(chk_real));
         double *L = (double *)malloc((size_t)n * sizeof(double));
         uint8_t *x = (uint8_t *)malloc((size_t)n);
         int ok = q && r && th && L && x;

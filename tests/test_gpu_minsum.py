@@ -10,8 +10,9 @@ FP32 (base-2 LLR units, offset scaled by log2 e): min-sum amplifies rounding
 differences quickly on frames that do not converge (test_oracle_minsum pins
 the spread of FP32-sized noise in the FP64 oracle), so FP32 is held to the
 1e-4 bar only up to the horizon where that spread stays well below it
-(flooding: 4 iterations, layered: 1 pass), and on converging inputs (5 dB,
-early stop) at full length.  The fused kernel's min-sum jobs must equal the
+(flooding: 4 iterations, layered: 1 pass), on converging inputs (5 dB,
+early stop) at full length, and at the benchmark's horizon (10 flooding
+iterations) to the wider bar that the measured spread there allows.  The fused kernel's min-sum jobs must equal the
 plain path bit for bit in both precisions.
 """
 import sys
@@ -20,7 +21,8 @@ import numpy as np
 import pytest
 
 import oracle
-from parity_util import compare
+from mapref import dense_syndrome
+from parity_util import TOL_MS_FLOOD10, compare
 from workloads import channel, codes, configs
 
 pytestmark = pytest.mark.gpu
@@ -51,7 +53,7 @@ def gpu_ms(L, handle, llr, T, es, layered, scale, offset):
     return bits.cpu().numpy(), iters.cpu().numpy(), post.cpu().numpy()
 
 
-def check(L, code, llr, T, es, layered, scale, offset, where, handle=None, tol=1e-4):
+def check(L, code, llr, T, es, layered, scale, offset, where, handle=None, tol=1e-4, rel_gate=False):
     sched = "layered" if layered else "flooding"
     _log(f"[gpu] min-sum {where}: {sched} n={code.n} frames={llr.shape[0]} T={T} es={es} "
          f"scale={scale} offset={offset} dtype={llr.dtype}")
@@ -65,7 +67,7 @@ def check(L, code, llr, T, es, layered, scale, offset, where, handle=None, tol=1
         assert np.array_equal(post, ref["posterior"]), f"{where} {sched}: posteriors differ"
         _log(f"[gpu] min-sum {where}: bit-identical to the oracle")
     else:
-        stats = compare(ref, bits, iters, post, llr.dtype, f"min-sum {where} {sched}", tol=tol)
+        stats = compare(ref, bits, iters, post, llr.dtype, f"min-sum {where} {sched}", tol=tol, rel_gate=rel_gate)
         _log(f"[gpu] min-sum {where}: {stats}")
     return (bits, iters, post), ref
 
@@ -75,6 +77,23 @@ def check(L, code, llr, T, es, layered, scale, offset, where, handle=None, tol=1
 def test_qc1944_fp32_short_horizon(L, layered, scale, offset):
     b = configs.qc1944(2.0, frames=100)
     check(L, b.code, b.llr, 1 if layered else 4, False, layered, scale, offset, "qc1944 2dB x100")
+
+
+@pytest.mark.parametrize("scale,offset", RULES)
+def test_qc1944_fp32_benchmark_horizon(L, scale, offset):
+    """The benchmark's min-sum run (qc1944, 2.0 dB, 10 flooding iterations,
+    no early stop): posteriors within TOL_MS_FLOOD10 (FP32 rounding spreads
+    them by up to 2.1e-3 there: test_oracle_minsum pins it below half the
+    bar), iteration counts equal, and bits identical wherever |L_ref|
+    exceeds the bar relative to A_n.  10 layered passes are compared for
+    validity only (the same noise moves their posteriors by order 1)."""
+    b = configs.qc1944(2.0, frames=200)
+    h = L.Code.from_workload(b.code)
+    check(L, b.code, b.llr, 10, False, False, scale, offset, "qc1944 2dB x200 10 it", handle=h,
+          tol=TOL_MS_FLOOD10, rel_gate=True)
+    bits, iters, _ = gpu_ms(L, h, b.llr, 10, True, True, scale, offset)
+    stopped = iters < 10
+    assert (dense_syndrome(b.code, bits[stopped]) == 0).all() and (iters[~stopped] == 10).all()
 
 
 @pytest.mark.parametrize("scale,offset", RULES)

@@ -1,12 +1,15 @@
 """GPU test of the multi-stream baseline (the paper's W workers x F frames
-structure, Section III-C): every batch's outputs equal ldpc_decode of the
-same frames, bit for bit, whatever worker decoded it; argument errors are
-refused before anything runs."""
+structure, Section III-C): every batch's outputs match the oracle (bits and
+iteration counts under the parity rule; the path returns no posteriors) and
+equal ldpc_decode of the same frames, bit for bit, whatever worker decoded
+it; argument errors are refused before anything runs."""
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
+from parity_util import compare
 from workloads import configs
 
 pytestmark = pytest.mark.gpu
@@ -30,12 +33,14 @@ def test_mstream_matches_single_decode(L, workers, frames, batches, layered):
     bits = np.zeros((frames * batches, b.code.n), np.uint8)
     iters = np.full(frames * batches, -1, np.int32)
     flags = L.LDPC_EARLY_STOP | (L.LDPC_LAYERED if layered else 0)
+    ref = oracle.decode(b.code, llr, 10, True, nthreads=8, schedule="layered" if layered else "flooding")
     for blocking in (1, 0):
         rc, stats = L.ldpc_mstream_run(h, workers, frames, batches, 10, flags, blocking, llr, bits, iters)
         print(f"[gpu] mstream W={workers} F={frames} B={batches} blocking={blocking}: rc={rc} {stats}", flush=True)
         sys.stdout.flush()
         assert rc == 0
         assert stats["wall_ms"] > 0 and stats["cpu_ms"] >= 0
+        print(f"[gpu]   oracle: {compare(ref, bits, iters, None, np.float32, 'mstream')}", flush=True)
         for k in range(batches):
             sl = slice(k * frames, (k + 1) * frames)
             rb, ri, _ = L.decode(h, torch.from_numpy(llr[sl]).cuda(), 10, early_stop=True, layered=layered,

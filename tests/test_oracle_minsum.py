@@ -123,3 +123,18 @@ def test_fp32_rounding_horizon(tmp_path):
         assert _spread(lib, b.code, b.llr, 1, "layered", scale, offset) < 0.5e-4
     assert _spread(lib, b.code, b.llr, 10, "flooding", 1.0, 0.0) > 1e-4
     assert _spread(lib, b.code, b.llr, 3, "layered", 1.0, 0.0) > 1e-4
+
+
+def test_fp32_benchmark_horizon(tmp_path):
+    """Justifies the bar of the FP32 min-sum parity test at the benchmark's
+    horizon (qc1944, 2.0 dB, 10 flooding iterations, no early stop): the
+    FP32-sized noise spread of every correction tested stays below half of
+    TOL_MS_FLOOD10 (measured 2.3e-4 normalised, 2.1e-3 plain, 3.7e-4
+    offset), while 10 layered passes spread by order 1, where posteriors of
+    unconverged frames cannot be compared at all."""
+    from parity_util import TOL_MS_FLOOD10
+    lib = _noisy_minsum_lib(tmp_path)
+    b = configs.qc1944(2.0, frames=100)
+    for scale, offset in ((1.0, 0.0), (0.75, 0.0), (1.0, 0.5)):
+        assert _spread(lib, b.code, b.llr, 10, "flooding", scale, offset) < 0.5 * TOL_MS_FLOOD10
+    assert _spread(lib, b.code, b.llr, 10, "layered", 0.75, 0.0) > 0.1

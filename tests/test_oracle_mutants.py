@@ -17,9 +17,9 @@ from oracle.build import SRC, compile_oracle
 
 MUTANTS = {
     "self_in_product": ("if (o != e)", "if (1)"),
-    "no_half_in_tanh": ("th[e] = tanh(q[e] / 2.0);", "th[e] = tanh(q[e]);"),
-    "no_factor_two": ("double v = 2.0 * atanh(p);", "double v = atanh(p);"),
-    "sign_flip": ("double v = 2.0 * atanh(p);", "double v = -2.0 * atanh(p);"),
+    "no_half_in_tanh": ("th[e] = CHK_TANH((chk_real)q[e] / 2);", "th[e] = CHK_TANH((chk_real)q[e]);"),
+    "no_factor_two": ("double v = (double)(2 * CHK_ATANH(p));", "double v = (double)CHK_ATANH(p);"),
+    "sign_flip": ("double v = (double)(2 * CHK_ATANH(p));", "double v = (double)(-2 * CHK_ATANH(p));"),
     "drop_channel_term": ("double s = llr[j];", "double s = 0.0;"),
     "no_extrinsic": ("q[g->col_edge[k]] = s - r[g->col_edge[k]];", "q[g->col_edge[k]] = s;"),
     "decision_le": ("x[j] = (uint8_t)(L[j] < 0.0);", "x[j] = (uint8_t)(L[j] <= 0.0);"),

@@ -16,6 +16,9 @@ Constructions
 * ``staircase_irregular``  rate-1/2 irregular code with a dual-diagonal parity
   part (variable degrees 8 / 3 / 2 on 1/5, 3/10, 1/2 of the columns), check
   degree 7 (one row of degree 6), no 4-cycles.
+* ``qc_row_degrees`` / ``random_rows``  codes with chosen row degrees (QC
+  with given block-row degrees; CSR with degrees drawn from a range and
+  optionally one dense column), for covering every kernel body size.
 * small fixtures: single parity check, repetition chain, Hamming(7,4),
   random cycle-free Tanner graphs.
 """
@@ -277,6 +280,49 @@ def qc_expand(shifts: np.ndarray, Z: int, name: str = "") -> Code:
 def qc_code(mb: int, nb: int, Z: int, seed: int, empty_frac: float = 0.3) -> Code:
     s = qc_base(mb, nb, Z, empty_frac, seed)
     return qc_expand(s, Z, f"qc {mb}x{nb} Z={Z} seed={seed}")
+
+
+def qc_row_degrees(degrees, nb: int, Z: int, seed: int) -> Code:
+    """QC code whose block-row i has exactly degrees[i] non-empty blocks (at
+    distinct base columns drawn uniformly), shifts uniform in [0, Z): a code
+    with chosen row degrees, e.g. a dense block-row.  Redrawn until no base
+    column is empty."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    assert all(1 <= d <= nb for d in degrees)
+    for _ in range(1000):
+        s = -np.ones((len(degrees), nb), dtype=np.int32)
+        for i, d in enumerate(degrees):
+            cols = rng.choice(nb, size=d, replace=False)
+            s[i, cols] = rng.integers(0, Z, size=d)
+        if (s >= 0).any(axis=0).all():
+            return qc_expand(s, Z, f"qc rows {list(degrees)} nb={nb} Z={Z} seed={seed}")
+    raise ValueError("block-row degrees leave a base column empty in every draw")
+
+
+def random_rows(m: int, n: int, dmin: int, dmax: int, seed: int, dense_col: bool = False) -> Code:
+    """Irregular code (CSR only): row i joins d_i ~ U{dmin..dmax} distinct
+    columns; with dense_col, column 0 is in every row (a column of degree m).
+    The other columns are dealt from a sequence of shuffled decks (each a
+    seeded permutation of them), so every column is used once before any is
+    used twice; a column already in the row is skipped for the next one."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    first = 1 if dense_col else 0
+    degrees = rng.integers(dmin, dmax + 1, size=m)
+    assert dmax <= n and int(degrees.sum()) - first * m >= n - first, "too few edges to cover every column"
+    deck: list = []
+    rows = []
+    for d in degrees:
+        row = [0] if dense_col else []
+        while len(row) < d:
+            if not deck:
+                deck = (first + rng.permutation(n - first)).tolist()
+            c = deck.pop()
+            if c in row:
+                deck.insert(0, c)
+                continue
+            row.append(c)
+        rows.append(sorted(row))
+    return Code.from_row_lists(m, n, rows, f"random rows {dmin}-{dmax} m={m} n={n} seed={seed}")
 
 
 def staircase_irregular(n: int, seed: int) -> Code:
