@@ -89,9 +89,13 @@ typedef enum { LDPC_F32 = 0, LDPC_F64 = 1 } ldpc_dtype;
  * FP64 tanh/atanh evaluation accurate). */
 #define LDPC_R_MAX 20.0
 
-/* Limits of this build. */
+/* Limits of this build.  Edges and variables are bounded so that the
+ * kernels' 32-bit offsets into a 64-frame chunk (edge x 64 values, variable
+ * x 64 doubles) cannot overflow. */
 #define LDPC_MAX_ROW_DEGREE 64
 #define LDPC_MAX_FRAMES (1 << 24)
+#define LDPC_MAX_EDGES ((1 << 25) - 1)
+#define LDPC_MAX_VARIABLES ((1 << 22) - 1)
 
 typedef struct ldpc_code_s *ldpc_code;
 
@@ -107,7 +111,8 @@ const char *ldpc_status_str(ldpc_status status);
  * The matrix is copied to the current device; the caller keeps its arrays.
  * Rows may be empty (always satisfied); columns may be empty (L = L_ch).
  * Errors: EINVAL for bad sizes, out-of-range or duplicate columns, NULL
- * pointers; EUNSUPPORTED for a row degree above LDPC_MAX_ROW_DEGREE;
+ * pointers; EUNSUPPORTED for a row degree above LDPC_MAX_ROW_DEGREE, more
+ * than LDPC_MAX_EDGES edges or more than LDPC_MAX_VARIABLES columns;
  * ENOMEM / EDEVICE on allocation or copy failure.  *out is set only on OK.
  */
 ldpc_status ldpc_code_from_csr(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,

@@ -32,6 +32,10 @@ ldpc_status build_host_layout(int32_t m, int32_t n, const int32_t *row_ptr, cons
     const int64_t E = row_ptr[m];
     if (E > 0 && !col_idx)
         return LDPC_EINVAL;
+    // The kernels index a 64-frame chunk's messages and posteriors with
+    // 32-bit byte and element offsets (edge x 64, variable x 64 x 8 bytes).
+    if (E > LDPC_MAX_EDGES || n > LDPC_MAX_VARIABLES)
+        return LDPC_EUNSUPPORTED;
     h.m = m;
     h.n = n;
     h.row_ptr.assign(row_ptr, row_ptr + m + 1);
@@ -128,6 +132,34 @@ void layer_tables(const HostLayout &h, std::vector<int32_t> &layer_ptr, std::vec
     }
 }
 
+// FNV-1a over the code's sizes, lifting size and row and column degree
+// histograms: codes of one shape (whatever their edge placement) share it.
+uint64_t shape_hash(const HostLayout &h, int32_t Z)
+{
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&x](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            x ^= (v >> (8 * b)) & 0xffu;
+            x *= 1099511628211ull;
+        }
+    };
+    mix(static_cast<uint64_t>(h.m));
+    mix(static_cast<uint64_t>(h.n));
+    mix(static_cast<uint64_t>(h.col_idx.size()));
+    mix(static_cast<uint64_t>(Z));
+    std::vector<int64_t> rows(h.max_row_deg + 1, 0), cols(h.max_col_deg + 1, 0);
+    for (int32_t i = 0; i < h.m; ++i)
+        rows[h.row_ptr[i + 1] - h.row_ptr[i]]++;
+    for (int32_t j = 0; j < h.n; ++j)
+        cols[h.col_ptr[j + 1] - h.col_ptr[j]]++;
+    for (int64_t v : rows)
+        mix(static_cast<uint64_t>(v));
+    mix(~0ull);
+    for (int64_t v : cols)
+        mix(static_cast<uint64_t>(v));
+    return x;
+}
+
 ldpc_status upload(const HostLayout &h, const std::vector<int32_t> *qc_tab, const std::vector<int32_t> &row_blk_start,
                    int32_t Z, ldpc_code_s *c)
 {
@@ -170,6 +202,7 @@ ldpc_status upload(const HostLayout &h, const std::vector<int32_t> *qc_tab, cons
     c->E = static_cast<int64_t>(h.col_idx.size());
     c->max_row_deg = h.max_row_deg;
     c->max_col_deg = h.max_col_deg;
+    c->shape_hash = shape_hash(h, Z);
     return LDPC_OK;
 }
 

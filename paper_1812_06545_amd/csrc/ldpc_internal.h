@@ -89,6 +89,9 @@ struct ldpc_code_s {
     // rows [layer_ptr[l], layer_ptr[l+1]); layer_dmax[l] its largest degree.
     std::vector<int32_t> layer_ptr, layer_dmax;
     const int32_t *d_layer_ptr = nullptr;  // device copy of layer_ptr
+    // Hash of the code's shape (sizes, lifting size, row and column degree
+    // histograms): the key of tuning choices, which depend on shape only.
+    uint64_t shape_hash = 0;
 };
 
 namespace ldpc {
@@ -108,7 +111,8 @@ bool code_on_current_device(const ldpc_code_s *c);
 // Otherwise both events are null and LDPC_LAUNCH is a plain launch.
 class ProfScope {
   public:
-    ProfScope(ldpc_kernel_kind kind, hipStream_t stream);
+    // enabled = false: no timing for this launch, whatever the global setting.
+    ProfScope(ldpc_kernel_kind kind, hipStream_t stream, bool enabled = true);
     ~ProfScope();
     ProfScope(const ProfScope &) = delete;
     ProfScope &operator=(const ProfScope &) = delete;

@@ -42,9 +42,9 @@ bool capturing(hipStream_t s)
 
 }  // namespace
 
-ldpc::ProfScope::ProfScope(ldpc_kernel_kind kind, hipStream_t stream)
+ldpc::ProfScope::ProfScope(ldpc_kernel_kind kind, hipStream_t stream, bool enabled)
 {
-    if (!g_enabled.load(std::memory_order_relaxed) || capturing(stream))
+    if (!enabled || !g_enabled.load(std::memory_order_relaxed) || capturing(stream))
         return;
     start_ = take_event();
     stop_ = start_ ? take_event() : nullptr;

@@ -88,3 +88,18 @@ def test_minsum_and_mstream_argument_errors_without_device():
                                   None) == L.LDPC_EINVAL
     assert lib.ldpc_mstream_run(None, 1, 64, 1, 10, 0, 1, None, None, None, None) == L.LDPC_EINVAL
 
+
+
+def test_code_limits_of_32bit_offsets():
+    """Codes whose chunk offsets would overflow the kernels' 32-bit index
+    arithmetic are refused at creation (before any device call)."""
+    lib = L.library()
+    out = ctypes.c_void_p()
+    ci = np.arange(4, dtype=np.int32)
+    rp = np.array([0, 1 << 25], np.int32)  # 2^25 edges: one more than LDPC_MAX_EDGES
+    assert lib.ldpc_code_from_csr(1, 10, rp.ctypes.data, ci.ctypes.data, ctypes.byref(out)) == L.LDPC_EUNSUPPORTED
+    rp = np.array([0, 2], np.int32)
+    assert lib.ldpc_code_from_csr(1, 1 << 22, rp.ctypes.data, ci.ctypes.data,
+                                  ctypes.byref(out)) == L.LDPC_EUNSUPPORTED
+    assert out.value is None
+
