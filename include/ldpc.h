@@ -216,6 +216,28 @@ ldpc_status ldpc_decode_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt
                               size_t workspace_bytes, void *stream);
 
 /*
+ * ldpc_decode_batch for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same jobs, results (bit for bit) and errors as
+ * ldpc_decode_batch, without a workspace: the batch tables and work counters
+ * live in a static device array of the library (LDPC_NOALLOC_MAX_GROUPS
+ * slices of about 4 KiB each, about 64 KiB, held on every device the call
+ * runs on until the process ends).  The call allocates nothing, on the
+ * device or the host, and creates no events (ldpc_profile_* does not time
+ * it).  Every job's code must fit the fused kernel (ldpc_batch_fits_fused)
+ * and the jobs must pack into at most LDPC_NOALLOC_MAX_GROUPS launches (24
+ * jobs and 16 codes per launch, fewer if the codes' LDS needs add up);
+ * otherwise LDPC_EUNSUPPORTED and nothing is enqueued.  The array is shared
+ * by every call on a device: calls whose work overlaps on one device
+ * (different streams, or threads) race on it and must be serialised by the
+ * caller, e.g. by using one stream.  Each launch rewrites its slice (table
+ * and counter) with a kernel before using it, so nothing must be cleared
+ * between calls.
+ */
+#define LDPC_NOALLOC_MAX_GROUPS 16
+ldpc_status ldpc_decode_batch_noalloc(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, void *stream);
+
+/*
  * Plans: the launch sequence of ldpc_decode_batch for these jobs, captured
  * once in a HIP graph (kernel nodes only) and replayed by ldpc_plan_launch.
  * The job buffers and the workspace are fixed at creation and must outlive

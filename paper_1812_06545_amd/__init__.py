@@ -27,6 +27,7 @@ LDPC_EARLY_STOP = 1
 LDPC_LAYERED = 2
 LDPC_MIN_SUM = 4
 LDPC_R_MAX = 20.0
+LDPC_NOALLOC_MAX_GROUPS = 16
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1812_06545_amd.build` "
@@ -64,6 +65,7 @@ _sig("ldpc_decode_minsum", ctypes.c_int, [_P, ctypes.c_int, _I32, _I32, ctypes.c
 _sig("ldpc_batch_workspace_bytes", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int,
                                                   ctypes.POINTER(ctypes.c_size_t)])
 _sig("ldpc_decode_batch", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, _P, ctypes.c_size_t, _P])
+_sig("ldpc_decode_batch_noalloc", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, _P])
 class ldpc_server_cfg(ctypes.Structure):
     _fields_ = [("ncodes", _I32), ("codes", ctypes.POINTER(_P)), ("mem_budget_bytes", ctypes.c_size_t),
                 ("max_inflight", _I32), ("max_group_frames", _I32), ("max_queue", _I32)]
@@ -260,6 +262,11 @@ def ldpc_decode_batch(jobs, dtype, workspace, workspace_bytes, stream=None) -> i
     arr = _jobs_array(jobs)
     return _lib.ldpc_decode_batch(arr, len(jobs), _dtype_code(dtype), _ptr(workspace), int(workspace_bytes),
                                   _stream_handle(stream))
+
+
+def ldpc_decode_batch_noalloc(jobs, dtype, stream=None) -> int:
+    arr = _jobs_array(jobs)
+    return _lib.ldpc_decode_batch_noalloc(arr, len(jobs), _dtype_code(dtype), _stream_handle(stream))
 
 
 def ldpc_plan_create(jobs, dtype, workspace, workspace_bytes) -> int:

@@ -11,7 +11,6 @@
 #include <cstring>
 #include <map>
 #include <mutex>
-#include <string>
 #include <vector>
 
 #include "fused_kernels.h"
@@ -20,22 +19,34 @@ namespace ldpc {
 namespace {
 
 std::mutex g_mu;
-int g_threads = 512;                // workgroup size of the fused kernel (set by ldpc_batch_set_threads)
-std::map<std::string, int> g_tuned;  // batch shape -> workgroup size chosen by ldpc_autotune_batch
+int g_threads = 512;                 // workgroup size of the fused kernel (set by ldpc_batch_set_threads)
+std::map<uint64_t, int> g_tuned;     // batch shape key -> workgroup size chosen by ldpc_autotune_batch
 
-// Shape of a batch for the tuning table: dtype and, per job, the code (by
-// address), frames rounded up to a power of two, iteration cap and flags.
-std::string shape_key(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt)
+// Shape of a batch for the tuning table: a hash of the dtype and, per job,
+// the code's shape (sizes and degree histograms, not its address), frames
+// rounded up to a power of two, the iteration cap and the flags.  Computed
+// without allocating.
+uint64_t shape_key(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt)
 {
-    std::string k = std::to_string(static_cast<int>(dt));
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&x](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            x ^= (v >> (8 * b)) & 0xffu;
+            x *= 1099511628211ull;
+        }
+    };
+    mix(static_cast<uint64_t>(dt));
+    mix(static_cast<uint64_t>(njobs));
     for (int32_t i = 0; i < njobs; ++i) {
-        int64_t f = 1;
-        while (f < jobs[i].frames)
+        uint64_t f = 1;
+        while (f < static_cast<uint64_t>(jobs[i].frames))
             f <<= 1;
-        k += ':' + std::to_string(reinterpret_cast<uintptr_t>(jobs[i].code)) + ',' + std::to_string(f) + ',' +
-             std::to_string(jobs[i].max_iter) + ',' + std::to_string(jobs[i].flags);
+        mix(jobs[i].code->shape_hash);
+        mix(f);
+        mix(static_cast<uint64_t>(jobs[i].max_iter));
+        mix(jobs[i].flags);
     }
-    return k;
+    return x;
 }
 
 int threads_for(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt)
@@ -81,17 +92,27 @@ FusedFit fused_fit(const ldpc_code_s *c, ldpc_dtype dt, size_t limit)
     return r;
 }
 
+// One fused launch: up to kMaxJobs jobs over up to kMaxCodes codes (fixed
+// storage, so planning needs no heap).
 struct Group {
-    std::vector<int32_t> jobs;
-    std::vector<const ldpc_code_s *> codes;
+    int32_t njobs = 0, ncodes = 0;
+    int32_t jobs[fused::kMaxJobs];
+    const ldpc_code_s *codes[fused::kMaxCodes];
     int bucket = 0;
     // maxima over the group's codes: the LDS layout is sized by them
     int64_t emax = 0;
     int32_t nmax = 0, words = 0, nblocks = 0, mb = 0;
     size_t lds(size_t tsize) const { return fused::frame_lds_bytes(emax, nmax, words, nblocks, mb, tsize); }
+    int code_index(const ldpc_code_s *c) const
+    {
+        for (int32_t k = 0; k < ncodes; ++k)
+            if (codes[k] == c)
+                return k;
+        return -1;
+    }
     void add_code(const ldpc_code_s *c)
     {
-        codes.push_back(c);
+        codes[ncodes++] = c;
         emax = std::max<int64_t>(emax, c->E);
         nmax = std::max(nmax, c->n);
         words = std::max(words, c->is_qc ? c->qc_words : 0);
@@ -100,38 +121,49 @@ struct Group {
     }
 };
 
-// Greedy packing of the fusable jobs, in order, into launch groups.
-void plan(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, std::vector<Group> &groups,
-          std::vector<int32_t> &plain)
+constexpr int kPlanNotFused = -1;  // a job's code does not fit the fused kernel and no plain list was given
+constexpr int kPlanTooMany = -2;   // more than max_groups launch groups would be needed
+
+// Greedy packing of the fusable jobs, in order, into launch groups (at most
+// max_groups).  Jobs whose code does not fit go to plain[] (*nplain of them),
+// or, with plain == nullptr, make the plan fail.  Returns the group count or
+// kPlanNotFused / kPlanTooMany.
+int plan(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, Group *groups, int max_groups, int32_t *plain,
+         int32_t *nplain)
 {
     const size_t limit = lds_limit();
+    const size_t tsize = dt == LDPC_F64 ? sizeof(double) : sizeof(float);
+    int ng = 0;
+    if (nplain)
+        *nplain = 0;
     for (int32_t i = 0; i < njobs; ++i) {
         if (jobs[i].frames == 0)
             continue;
         const FusedFit fit = fused_fit(jobs[i].code, dt, limit);
         if (!fit.ok) {
-            plain.push_back(i);
+            if (!plain)
+                return kPlanNotFused;
+            plain[(*nplain)++] = i;
             continue;
         }
-        const size_t tsize = dt == LDPC_F64 ? sizeof(double) : sizeof(float);
-        bool need_new = groups.empty() || static_cast<int>(groups.back().jobs.size()) == fused::kMaxJobs;
-        if (!need_new) {
-            const Group &g = groups.back();
-            const bool new_code = std::find(g.codes.begin(), g.codes.end(), jobs[i].code) == g.codes.end();
-            if (new_code) {
-                Group trial = g;
-                trial.add_code(jobs[i].code);
-                need_new = static_cast<int>(g.codes.size()) == fused::kMaxCodes || trial.lds(tsize) > limit;
-            }
+        bool need_new = ng == 0 || groups[ng - 1].njobs == fused::kMaxJobs;
+        if (!need_new && groups[ng - 1].code_index(jobs[i].code) < 0) {
+            Group trial = groups[ng - 1];
+            trial.add_code(jobs[i].code);
+            need_new = groups[ng - 1].ncodes == fused::kMaxCodes || trial.lds(tsize) > limit;
         }
-        if (need_new)
-            groups.emplace_back();
-        Group &g = groups.back();
-        g.jobs.push_back(i);
-        if (std::find(g.codes.begin(), g.codes.end(), jobs[i].code) == g.codes.end())
+        if (need_new) {
+            if (ng == max_groups)
+                return kPlanTooMany;
+            groups[ng++] = Group{};
+        }
+        Group &g = groups[ng - 1];
+        g.jobs[g.njobs++] = i;
+        if (g.code_index(jobs[i].code) < 0)
             g.add_code(jobs[i].code);
         g.bucket = std::max(g.bucket, fit.bucket);
     }
+    return ng;
 }
 
 constexpr size_t kGroupBytes = (sizeof(fused::Batch) + 255) / 256 * 256 + 256;
@@ -169,13 +201,14 @@ ldpc_status validate_jobs(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype)
     return LDPC_OK;
 }
 
-size_t batch_bytes(const ldpc_job *jobs, const std::vector<Group> &groups, const std::vector<int32_t> &plain,
-                   ldpc_dtype dtype)
+size_t batch_bytes(const ldpc_job *jobs, int ngroups, const int32_t *plain, int32_t nplain, ldpc_dtype dtype)
 {
     size_t stream = 0;
-    for (int32_t i : plain)
-        stream = std::max(stream, stream_workspace_bytes(jobs[i].code, dtype, jobs[i].frames, jobs[i].max_iter));
-    return groups.size() * kGroupBytes + stream;
+    for (int32_t k = 0; k < nplain; ++k) {
+        const ldpc_job &j = jobs[plain[k]];
+        stream = std::max(stream, stream_workspace_bytes(j.code, dtype, j.frames, j.max_iter));
+    }
+    return static_cast<size_t>(ngroups) * kGroupBytes + stream;
 }
 
 fused::Code code_entry(const ldpc_code_s *c)
@@ -202,14 +235,17 @@ fused::Code code_entry(const ldpc_code_s *c)
     return e;
 }
 
+// Writes group g's batch table into ws (kGroupBytes: the table, then the
+// work counter in its last 256 bytes) with a kernel, and launches the fused
+// kernel on it.  profile: as launch_fused_bucket.
 template <class A>
-ldpc_status launch_group(const ldpc_job *jobs, const Group &g, char *ws, int threads, hipStream_t s)
+ldpc_status launch_group(const ldpc_job *jobs, const Group &g, char *ws, int threads, hipStream_t s, bool profile)
 {
     fused::Batch b{};
-    b.njobs = static_cast<int32_t>(g.jobs.size());
-    b.ncodes = static_cast<int32_t>(g.codes.size());
+    b.njobs = g.njobs;
+    b.ncodes = g.ncodes;
     int32_t nblocks_max = 0;
-    for (size_t k = 0; k < g.codes.size(); ++k) {
+    for (int32_t k = 0; k < g.ncodes; ++k) {
         const ldpc_code_s *c = g.codes[k];
         b.codes[k] = code_entry(c);
         b.emax = std::max<int32_t>(b.emax, static_cast<int32_t>(c->E));
@@ -219,10 +255,10 @@ ldpc_status launch_group(const ldpc_job *jobs, const Group &g, char *ws, int thr
         nblocks_max = std::max(nblocks_max, c->is_qc ? c->nblocks : 0);
     }
     int64_t items = 0;
-    for (size_t k = 0; k < g.jobs.size(); ++k) {
+    for (int32_t k = 0; k < g.njobs; ++k) {
         const ldpc_job &j = jobs[g.jobs[k]];
         fused::Job &e = b.jobs[k];
-        e.code = static_cast<int32_t>(std::find(g.codes.begin(), g.codes.end(), j.code) - g.codes.begin());
+        e.code = g.code_index(j.code);
         e.frames = j.frames;
         e.max_iter = j.max_iter;
         e.flags = j.flags;
@@ -241,24 +277,81 @@ ldpc_status launch_group(const ldpc_job *jobs, const Group &g, char *ws, int thr
     auto *d_batch = reinterpret_cast<fused::Batch *>(ws);
     auto *counter = reinterpret_cast<unsigned long long *>(ws + kGroupBytes - 256);
     {
-        ProfScope ps(LDPC_KERNEL_OTHER, s);
+        ProfScope ps(LDPC_KERNEL_OTHER, s, profile);
         LDPC_LAUNCH(ps, k_store_batch, dim3(1), dim3(256), 0, s, b, d_batch, counter);
     }
     switch (g.bucket) {
-    case 8: return launch_fused_bucket<A, 8>(b, d_batch, counter, lds, threads, s);
-    case 16: return launch_fused_bucket<A, 16>(b, d_batch, counter, lds, threads, s);
+    case 8: return launch_fused_bucket<A, 8>(b, d_batch, counter, lds, threads, s, profile);
+    case 16: return launch_fused_bucket<A, 16>(b, d_batch, counter, lds, threads, s, profile);
     case 24:
         if constexpr (std::is_same<A, ArithF32>::value)
-            return launch_fused_bucket<A, 24>(b, d_batch, counter, lds, threads, s);
-        return launch_fused_bucket<A, 32>(b, d_batch, counter, lds, threads, s);
-    default: return launch_fused_bucket<A, 32>(b, d_batch, counter, lds, threads, s);
+            return launch_fused_bucket<A, 24>(b, d_batch, counter, lds, threads, s, profile);
+        return launch_fused_bucket<A, 32>(b, d_batch, counter, lds, threads, s, profile);
+    default: return launch_fused_bucket<A, 32>(b, d_batch, counter, lds, threads, s, profile);
     }
 }
 
 }  // namespace
 }  // namespace ldpc
 
+// Scratch memory of ldpc_decode_batch_noalloc: the batch tables and work
+// counters of up to LDPC_NOALLOC_MAX_GROUPS launch groups, one kGroupBytes
+// slice each, as ldpc_decode_batch lays them out in its workspace.  Every
+// device holds its own copy for the life of the process.  Host code never
+// uses this name as an address: it uses the per-device address that
+// hipGetSymbolAddress returns (noalloc_scratch).
+constexpr size_t kNoallocScratchBytes = static_cast<size_t>(LDPC_NOALLOC_MAX_GROUPS) * ldpc::kGroupBytes;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace ldpc {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device, once looked up
+
+// The current device's address of `scratch`, looked up on the first call
+// on each device (with that device current) and kept.
+ldpc_status noalloc_scratch(char **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0)
+        return LDPC_EDEVICE;
+    if (dev >= kMaxDevices)
+        return LDPC_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return LDPC_EDEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<char *>(g_scratch_ptr[dev]);
+    return LDPC_OK;
+}
+
+}  // namespace
+}  // namespace ldpc
+
 using namespace ldpc;
+
+namespace {
+
+// The full plan of a batch: launch groups and the jobs for the plain path.
+struct FullPlan {
+    std::vector<Group> groups;
+    std::vector<int32_t> plain;
+    int ngroups = 0;
+    int32_t nplain = 0;
+    void make(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype)
+    {
+        groups.resize(std::max(njobs, 1));
+        plain.resize(std::max(njobs, 1));
+        ngroups = plan(jobs, njobs, dtype, groups.data(), static_cast<int>(groups.size()), plain.data(), &nplain);
+    }
+};
+
+}  // namespace
 
 extern "C" ldpc_status ldpc_batch_workspace_bytes(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype,
                                                   size_t *bytes)
@@ -268,10 +361,9 @@ try {
     const ldpc_status st = validate_jobs(jobs, njobs, dtype);
     if (st != LDPC_OK)
         return st;
-    std::vector<Group> groups;
-    std::vector<int32_t> plain;
-    plan(jobs, njobs, dtype, groups, plain);
-    *bytes = batch_bytes(jobs, groups, plain, dtype);
+    FullPlan p;
+    p.make(jobs, njobs, dtype);
+    *bytes = batch_bytes(jobs, p.ngroups, p.plain.data(), p.nplain, dtype);
     return LDPC_OK;
 } catch (...) {
     return ldpc::status_of_exception();
@@ -283,10 +375,9 @@ try {
     const ldpc_status st = validate_jobs(jobs, njobs, dtype);
     if (st != LDPC_OK)
         return st;
-    std::vector<Group> groups;
-    std::vector<int32_t> plain;
-    plan(jobs, njobs, dtype, groups, plain);
-    const size_t need = batch_bytes(jobs, groups, plain, dtype);
+    FullPlan p;
+    p.make(jobs, njobs, dtype);
+    const size_t need = batch_bytes(jobs, p.ngroups, p.plain.data(), p.nplain, dtype);
     if (need == 0)
         return LDPC_OK;
     if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
@@ -294,19 +385,50 @@ try {
     const int threads = threads_for(jobs, njobs, dtype);
     const hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
-    for (const Group &g : groups) {
-        const ldpc_status r = dtype == LDPC_F64 ? launch_group<ArithF64>(jobs, g, ws, threads, s)
-                                                : launch_group<ArithF32>(jobs, g, ws, threads, s);
+    for (int gi = 0; gi < p.ngroups; ++gi) {
+        const Group &g = p.groups[gi];
+        const ldpc_status r = dtype == LDPC_F64 ? launch_group<ArithF64>(jobs, g, ws, threads, s, true)
+                                                : launch_group<ArithF32>(jobs, g, ws, threads, s, true);
         if (r != LDPC_OK)
             return r;
         ws += kGroupBytes;
     }
-    for (int32_t i : plain) {
-        const ldpc_job &j = jobs[i];
+    for (int32_t k = 0; k < p.nplain; ++k) {
+        const ldpc_job &j = jobs[p.plain[k]];
         const ldpc_status r = stream_decode(j.code, dtype, j.frames, j.max_iter, j.flags, j.llr, j.bits, j.iters,
                                             j.posterior, ws, s, j.ms_scale, j.ms_offset);
         if (r != LDPC_OK)
             return r;
+    }
+    return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
+}
+
+extern "C" ldpc_status ldpc_decode_batch_noalloc(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype,
+                                                 void *stream)
+try {
+    const ldpc_status st = validate_jobs(jobs, njobs, dtype);
+    if (st != LDPC_OK)
+        return st;
+    Group groups[LDPC_NOALLOC_MAX_GROUPS];
+    const int ng = plan(jobs, njobs, dtype, groups, LDPC_NOALLOC_MAX_GROUPS, nullptr, nullptr);
+    if (ng < 0)
+        return LDPC_EUNSUPPORTED;  // a code too large for the fused kernel, or more groups than the scratch holds
+    if (ng == 0)
+        return LDPC_OK;
+    char *ws = nullptr;
+    const ldpc_status sc = noalloc_scratch(&ws);
+    if (sc != LDPC_OK)
+        return sc;
+    const int threads = threads_for(jobs, njobs, dtype);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int gi = 0; gi < ng; ++gi) {
+        const ldpc_status r = dtype == LDPC_F64 ? launch_group<ArithF64>(jobs, groups[gi], ws, threads, s, false)
+                                                : launch_group<ArithF32>(jobs, groups[gi], ws, threads, s, false);
+        if (r != LDPC_OK)
+            return r;
+        ws += kGroupBytes;
     }
     return LDPC_OK;
 } catch (...) {
@@ -372,7 +494,7 @@ try {
         return st;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     static const int kCandidates[] = {64, 128, 192, 256, 384, 512};
-    const std::string key = shape_key(jobs, njobs, dtype);
+    const uint64_t key = shape_key(jobs, njobs, dtype);
     std::vector<char> ref, cur;
     int best = 0;
     double best_t = 0.0;

@@ -707,7 +707,10 @@ namespace fused {
 // and block size on the current device.  The runtime calls behind them (the
 // kernel's LDS limit, the occupancy query, the device attribute) run once per
 // (kernel, device, LDS bytes, threads) and are cached, not repeated on every
-// launch; the LDS limit is only ever raised.
+// launch; the LDS limit is only ever raised.  The caches are fixed-size
+// tables (no heap allocation on any call): when the shape table is full it
+// starts over, and a kernel missing from the full limit table has its limit
+// set on every launch of a new shape.
 inline ldpc_status launch_shape(const void *fn, size_t lds, int threads, int &per_cu, int &cus)
 {
     struct Shape {
@@ -721,14 +724,17 @@ inline ldpc_status launch_shape(const void *fn, size_t lds, int threads, int &pe
         int dev;
         size_t lds;
     };
+    constexpr int kShapes = 256, kLimits = 128;
     static std::mutex mu;
-    static std::vector<Shape> shapes;
-    static std::vector<Limit> limits;
+    static Shape shapes[kShapes];
+    static Limit limits[kLimits];
+    static int nshapes = 0, nlimits = 0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
         return LDPC_EDEVICE;
     std::lock_guard<std::mutex> lk(mu);
-    for (const Shape &e : shapes) {
+    for (int i = 0; i < nshapes; ++i) {
+        const Shape &e = shapes[i];
         if (e.fn == fn && e.dev == dev && e.lds == lds && e.threads == threads) {
             per_cu = e.per_cu;
             cus = e.cus;
@@ -736,24 +742,24 @@ inline ldpc_status launch_shape(const void *fn, size_t lds, int threads, int &pe
         }
     }
     Limit *lim = nullptr;
-    for (Limit &l : limits)
-        if (l.fn == fn && l.dev == dev)
-            lim = &l;
+    for (int i = 0; i < nlimits; ++i)
+        if (limits[i].fn == fn && limits[i].dev == dev)
+            lim = &limits[i];
     if (lim == nullptr || lim->lds < lds) {
         if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
             return LDPC_EUNSUPPORTED;
-        if (lim == nullptr)
-            limits.push_back(Limit{fn, dev, lds});
-        else
+        if (lim != nullptr)
             lim->lds = lds;
+        else if (nlimits < kLimits)
+            limits[nlimits++] = Limit{fn, dev, lds};
     }
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
         return LDPC_EUNSUPPORTED;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return LDPC_EDEVICE;
-    if (shapes.size() >= 256)  // batches of many different code mixes: start over
-        shapes.clear();
-    shapes.push_back(Shape{fn, dev, lds, threads, per_cu, cus});
+    if (nshapes == kShapes)  // batches of many different code mixes: start over
+        nshapes = 0;
+    shapes[nshapes++] = Shape{fn, dev, lds, threads, per_cu, cus};
     return LDPC_OK;
 }
 
@@ -762,15 +768,17 @@ inline ldpc_status launch_shape(const void *fn, size_t lds, int threads, int &pe
 // Launcher of the fused kernel for codes of row degree <= DB (one
 // translation unit per dtype and bucket).
 // The caller has already written the batch table to d_batch and reset *counter.
+// profile = false keeps the launch out of ldpc_profile_* timing (whose event
+// pool may create events).
 template <class A, int DB>
 ldpc_status launch_fused_bucket(const fused::Batch &batch, fused::Batch *d_batch, unsigned long long *counter,
-                                size_t lds_bytes, int threads, hipStream_t s);
+                                size_t lds_bytes, int threads, hipStream_t s, bool profile);
 
 #define LDPC_DEFINE_FUSED_BUCKET(A_, DB_)                                                                        \
     template <>                                                                                                  \
     ldpc_status launch_fused_bucket<A_, DB_>(const fused::Batch &batch, fused::Batch *d_batch,                  \
                                              unsigned long long *counter, size_t lds_bytes, int threads,        \
-                                             hipStream_t s)                                                      \
+                                             hipStream_t s, bool profile)                                        \
     {                                                                                                            \
         auto kern = fused::k_fused<A_, DB_>;                                                                     \
         int per_cu = 0, cus = 0;                                                                                 \
@@ -779,7 +787,7 @@ ldpc_status launch_fused_bucket(const fused::Batch &batch, fused::Batch *d_batch
         if (shape_rc != LDPC_OK)                                                                                 \
             return shape_rc;                                                                                     \
         const int64_t grid = std::min<int64_t>(batch.nitems, static_cast<int64_t>(per_cu) * cus);               \
-        ProfScope ps(LDPC_KERNEL_FUSED, s);                                                                      \
+        ProfScope ps(LDPC_KERNEL_FUSED, s, profile);                                                             \
         LDPC_LAUNCH(ps, kern, dim3(static_cast<unsigned>(grid)), dim3(threads), static_cast<uint32_t>(lds_bytes), \
                     s, d_batch, counter);                                                                        \
         return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EDEVICE;                                         \

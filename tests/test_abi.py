@@ -103,3 +103,11 @@ def test_code_limits_of_32bit_offsets():
                                   ctypes.byref(out)) == L.LDPC_EUNSUPPORTED
     assert out.value is None
 
+
+def test_noalloc_batch_argument_errors_without_device():
+    lib = L.library()
+    assert lib.ldpc_decode_batch_noalloc(None, 0, 0, None) == L.LDPC_OK
+    assert lib.ldpc_decode_batch_noalloc(None, -1, 0, None) == L.LDPC_EINVAL
+    assert lib.ldpc_decode_batch_noalloc(None, 0, 7, None) == L.LDPC_EINVAL
+    job = L.ldpc_job(None, 4, 10, 0, None, None, None, None)
+    assert lib.ldpc_decode_batch_noalloc(ctypes.byref(job), 1, 0, None) == L.LDPC_EINVAL
