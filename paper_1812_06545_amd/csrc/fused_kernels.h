@@ -203,7 +203,7 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
     const typename A::Acc s_other = pair_swap(acc);
     const uint32_t sign_total = sign ^ pair_swap(sign);
     parity |= par ^ pair_swap(par);  // a lane may hold several rows: any unsatisfied row counts
-    typename A::Acc s = A::identity();
+    typename A::Acc s = A::seed(s_other);
     // The parked value is read for dummies too (their slot is valid; the
     // value, possibly a later dummy's message, is replaced), which spares an
     // exec-mask branch per slot.  FP32 bodies are held to 128 VGPRs, and the
@@ -220,7 +220,7 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
             parked = real ? v : T(A::kDummyParked);
         }
         const typename A::Term a_k = A::unpark(parked, kp[j]);
-        const T r = check_backward<A>(a_k, p[j], s, s_other, sign_total);
+        const T r = check_backward<A>(a_k, p[j], s, sign_total);
         sR[ri[j]] = r;
     }
 }
@@ -288,13 +288,13 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh,
     }
     const typename A::Acc s_other = pair_swap(acc);
     const uint32_t sign_total = sign ^ pair_swap(sign);
-    typename A::Acc s = A::identity();
+    typename A::Acc s = A::seed(s_other);
 #pragma unroll
     for (int j = D - 1; j >= 0; --j) {
         const bool real = j < dh;
         const T parked = sR[ri[j]];  // a dummy's slot is valid; its value may be a later dummy's message
         const typename A::Term a_k = A::unpark(real ? parked : T(A::kDummyParked), kp[j]);
-        const T r = check_backward<A>(a_k, p[j], s, s_other, sign_total);
+        const T r = check_backward<A>(a_k, p[j], s, sign_total);
         const T q = sL[ci[j]];
         sR[ri[j]] = r;
         sL[ci[j]] = q + r;

@@ -61,10 +61,10 @@ __device__ __forceinline__ void layer_row(const int32_t *__restrict__ cols, type
             q[k] = q[k] - rv[k];
         check_forward<A>(q[k], a[k], p[k], k < H ? acc0 : acc1, sign);
     }
-    typename A::Acc s0 = A::identity(), s1 = A::identity();
+    typename A::Acc s0 = A::seed(acc1), s1 = A::seed(acc0);
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) {
-        const T r = k < H ? check_backward<A>(a[k], p[k], s0, acc1, sign) : check_backward<A>(a[k], p[k], s1, acc0, sign);
+        const T r = k < H ? check_backward<A>(a[k], p[k], s0, sign) : check_backward<A>(a[k], p[k], s1, sign);
         st_lane_nt(Rrow + k * kChunk, off, r);
         if constexpr (kBuf)
             st_scatter(rsrc, off, cols[k], q[k] + r);
@@ -105,12 +105,12 @@ __device__ __forceinline__ void layer_row_guarded(const int32_t *__restrict__ co
                 check_forward<A>(q[k], a[k], p[k], acc1, sign);
         }
     }
-    typename A::Acc s0 = A::identity(), s1 = A::identity();
+    typename A::Acc s0 = A::seed(acc1), s1 = A::seed(acc0);
 #pragma unroll
     for (int k = DMAX - 1; k >= 0; --k) {
         if (k < d) {
-            const T r = k < h ? check_backward<A>(a[k], p[k], s0, acc1, sign)
-                              : check_backward<A>(a[k], p[k], s1, acc0, sign);
+            const T r = k < h ? check_backward<A>(a[k], p[k], s0, sign)
+                              : check_backward<A>(a[k], p[k], s1, sign);
             st_lane_nt(Rrow + k * kChunk, off, r);
             st_lane(L + cols[k] * kChunk, off, q[k] + r);
         }

@@ -12,8 +12,11 @@
 //     Acc   identity()     the empty combination;
 //     Acc   add(Acc, Term) combination grown by one edge;
 //     Acc   merge(Acc, Acc) combination of two disjoint edge sets;
-//     T     message(Acc)   |r| from the combination of the other edges,
-//                          clamped to R_MAX.
+//     Acc   seed(Acc)      a combination in the form message() takes it
+//                          (FP32: its product doubled), applied once per
+//                          half row to the other half's combination;
+//     T     message(Acc)   |r| from the seeded combination of the other
+//                          edges, clamped to R_MAX.
 //
 // FP32 (base-2 LLR units: every LLR is multiplied by log2(e) on entry and by
 // ln 2 on exit) uses the product form directly.  An edge carries
@@ -24,9 +27,12 @@
 // a (+) b = a + b - ab = 1 - (1 - a)(1 - b), so that Q stays accurate when P is
 // close to 1 (confident rows) just as P does when it is small.  The message
 // is 2 atanh(P) = log2((1 + P) / Q) = log2(1 + 2P / Q), with the rounding
-// error of w = fl(1 + z) added back (c = (1 - w) + z is exact for z < 1),
-// which keeps weak messages accurate.  Per edge: exp2 and one reciprocal
-// forward, one reciprocal and log2 back.
+// error of w = fl(1 + z) added back (c = (1 - w) + z is exact while w <
+// 2^24, and at most 2^-24 for z < 1; it is clamped to that bound, which
+// leaves it exact where it matters, weak messages, and harmless elsewhere).
+// The factor 2 of 2P rides on the seed of each half's backward pass, so it
+// costs one operation per half row, not per edge.  Per edge: exp2 and one
+// reciprocal forward, one reciprocal and log2 back.
 //
 // FP64 uses the equivalent phi form with libm-quality exp / expm1 / log1p:
 //     phi(x) = -ln tanh(x/2) = log1p(2 e^-x / (1 - e^-x)),
@@ -66,15 +72,18 @@ struct ArithF32 {
         // which t (a small factor of P, the size of a weak message) needs;
         // there d comes from the Taylor series of -expm1(-x ln 2) (5 terms:
         // truncation below 1e-8 relative for x < 1/8).
-        float p = __builtin_fmaf(-x, 1.33335581e-3f, 9.61812911e-3f);   // ln2^5/120, ln2^4/24
-        p = __builtin_fmaf(-x, p, 5.55041087e-2f);                       // ln2^3/6
-        p = __builtin_fmaf(-x, p, 2.40226507e-1f);                       // ln2^2/2
-        p = __builtin_fmaf(-x, p, 6.93147181e-1f);                       // ln2
-        const float d = (x < 0.125f) ? x * p : 1.0f - e;
-        const float ri = __builtin_amdgcn_rcpf(1.0f + e);
+        // Everything is formed at half scale, d/2 and 2/(1 + e), which
+        // scales by powers of two only (the same roundings) and saves the
+        // doubling of e in u = 2e/(1 + e).
+        float p = __builtin_fmaf(-x, 0.5f * 1.33335581e-3f, 0.5f * 9.61812911e-3f);  // ln2^5/120, ln2^4/24
+        p = __builtin_fmaf(-x, p, 0.5f * 5.55041087e-2f);                             // ln2^3/6
+        p = __builtin_fmaf(-x, p, 0.5f * 2.40226507e-1f);                             // ln2^2/2
+        p = __builtin_fmaf(-x, p, 0.5f * 6.93147181e-1f);                             // ln2
+        const float dh = (x < 0.125f) ? x * p : __builtin_fmaf(e, -0.5f, 0.5f);     // d / 2
+        const float ri2 = __builtin_amdgcn_rcpf(__builtin_fmaf(e, 0.5f, 0.5f));     // 2 / (1 + e)
         Term k;
-        k.t = mag_with_sign_of(d * ri, q);
-        k.u = (e + e) * ri;
+        k.t = mag_with_sign_of(dh * ri2, q);
+        k.u = e * ri2;
         return k;
     }
     __device__ static __forceinline__ Acc add(Acc a, const Term &k)
@@ -82,15 +91,17 @@ struct ArithF32 {
         return Acc{a.P * __builtin_fabsf(k.t), oplus(a.Q, k.u)};
     }
     __device__ static __forceinline__ Acc merge(Acc a, Acc b) { return Acc{a.P * b.P, oplus(a.Q, b.Q)}; }
+    __device__ static __forceinline__ Acc seed(Acc a) { return Acc{a.P + a.P, a.Q}; }
     __device__ static __forceinline__ float message(Acc x)
     {
-        // Q = 0 (a degree-1 row, or every other edge certain) gives z = +inf,
-        // w = +inf, c = 0 and log2 = +inf, which the clamp turns into R_MAX.
-        // (P = 0 forces Q = 1, so z is never 0 * inf.)
-        const float z = (x.P + x.P) * __builtin_amdgcn_rcpf(x.Q);
+        // x.P is twice the product (seed).  Q = 0 (a degree-1 row, or every
+        // other edge certain) gives z = +inf, w = +inf and log2 = +inf; c is
+        // then NaN or a clamp bound, and either way r is not below R_MAX, so
+        // the final select (false for NaN) returns R_MAX.  P = 0 forces Q = 1,
+        // so z is never 0 * inf.
+        const float z = x.P * __builtin_amdgcn_rcpf(x.Q);
         const float w = 1.0f + z;
-        float c = (1.0f - w) + z;
-        c = (z < 1.0f) ? c : 0.0f;
+        const float c = __builtin_amdgcn_fmed3f((1.0f - w) + z, -0x1p-24f, 0x1p-24f);
         const float r = __builtin_fmaf(c, 1.44269504088896341f, __builtin_amdgcn_logf(w));
         return r < kRmax ? r : kRmax;
     }
@@ -135,6 +146,7 @@ struct ArithF64 {
     __device__ static __forceinline__ Term term(double q) { return mag_with_sign_of(phi(fabs(q)), q); }
     __device__ static __forceinline__ Acc add(Acc a, Term k) { return a + fabs(k); }
     __device__ static __forceinline__ Acc merge(Acc a, Acc b) { return a + b; }
+    __device__ static __forceinline__ Acc seed(Acc a) { return a; }
     __device__ static __forceinline__ double message(Acc x)
     {
         const double r = phi(x);
@@ -167,10 +179,10 @@ struct ArithF64 {
 
 // Exclusive combinations of one check row.  The row's d edges are split at
 // h = ceil(d/2) into halves H0 = [0, h) and H1 = [h, d); for edge k in half
-// H, with p_k the combination of the earlier edges of H (left to right), s_k
-// that of the later edges of H (right to left) and C_other the combination
-// of the other half (left to right),
-//     excl_k = merge(merge(p_k, s_k), C_other).
+// H, with p_k the combination of the earlier edges of H (left to right),
+// C_other the combination of the other half (left to right) and s_k the
+// combination seed(C_other) grown by the later edges of H (right to left),
+//     excl_k = merge(p_k, s_k).
 // Fixing the order lets the fused kernel spread a row over two lanes (one
 // half each, exchanging C and the sign) while the streaming kernels evaluate
 // the same expression in one lane, bit for bit.
@@ -188,14 +200,13 @@ __device__ __forceinline__ void check_forward(typename A::T q, typename A::Term 
 }
 
 // Backward step: outgoing message of an edge from its term, p_k, the half's
-// running suffix s (which then grows), the other half's combination and the
-// row's total sign.
+// running suffix s (started at seed(C_other); it then grows by this edge) and
+// the row's total sign.
 template <class A>
 __device__ __forceinline__ typename A::T check_backward(const typename A::Term &a_k, const typename A::Acc &p_k,
-                                                        typename A::Acc &s, const typename A::Acc &c_other,
-                                                        uint32_t sign_total)
+                                                        typename A::Acc &s, uint32_t sign_total)
 {
-    const typename A::Acc ex = A::merge(A::merge(p_k, s), c_other);
+    const typename A::Acc ex = A::merge(p_k, s);
     s = A::add(s, a_k);
     return A::with_sign(A::message(ex), sign_total ^ A::term_sign(a_k));
 }
