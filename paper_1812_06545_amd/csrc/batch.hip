@@ -69,6 +69,17 @@ size_t lds_limit()
     return static_cast<size_t>(bytes);
 }
 
+// Whether the fused kernel uses the circulant view of a QC code in a dtype
+// of tsize bytes: its row tables pack tsize * j * Z and tsize * s into 16-bit
+// fields, and it divides row and column indices by Z with a multiply-high,
+// exact while index * Z < 2^32 (Z >= 2).  Other codes use the CSR view.
+bool fused_qc_view(const ldpc_code_s *c, size_t tsize)
+{
+    return c->is_qc && c->Z >= 2 && tsize * static_cast<size_t>(c->n) <= 65535 &&
+           tsize * static_cast<size_t>(c->Z) <= 65535 &&
+           static_cast<uint64_t>(std::max(c->m, c->n)) * static_cast<uint64_t>(c->Z) < (1ull << 32);
+}
+
 struct FusedFit {
     bool ok = false;
     int bucket = 0;
@@ -83,11 +94,13 @@ FusedFit fused_fit(const ldpc_code_s *c, ldpc_dtype dt, size_t limit)
         r.bucket = d <= 8 ? 8 : d <= 16 ? 16 : d <= 24 ? 24 : d <= 32 ? 32 : 0;
     else
         r.bucket = d <= 8 ? 8 : d <= 16 ? 16 : d <= 32 ? 32 : 0;
-    if (r.bucket == 0 || c->n >= 65536)
-        return r;
     const size_t tsize = dt == LDPC_F64 ? sizeof(double) : sizeof(float);
-    r.lds = fused::frame_lds_bytes(c->E, c->n, c->is_qc ? c->qc_words : 0, c->is_qc ? c->nblocks : 0,
-                                   c->is_qc ? c->mb : 0, tsize);
+    const bool qc = fused_qc_view(c, tsize);
+    // A QC code's fused slot tables list its rows by block-row degree, which
+    // only the circulant view follows: without it the code takes the plain path.
+    if (r.bucket == 0 || c->n >= 65536 || (c->is_qc && !qc))
+        return r;
+    r.lds = fused::frame_lds_bytes(c->E, c->n, qc ? c->qc_words : 0, qc ? c->nblocks : 0, qc ? c->mb : 0, tsize);
     r.ok = r.lds <= limit;
     return r;
 }
@@ -102,7 +115,8 @@ struct Group {
     // maxima over the group's codes: the LDS layout is sized by them
     int64_t emax = 0;
     int32_t nmax = 0, words = 0, nblocks = 0, mb = 0;
-    size_t lds(size_t tsize) const { return fused::frame_lds_bytes(emax, nmax, words, nblocks, mb, tsize); }
+    size_t tsize = 4;
+    size_t lds() const { return fused::frame_lds_bytes(emax, nmax, words, nblocks, mb, tsize); }
     int code_index(const ldpc_code_s *c) const
     {
         for (int32_t k = 0; k < ncodes; ++k)
@@ -112,12 +126,13 @@ struct Group {
     }
     void add_code(const ldpc_code_s *c)
     {
+        const bool qc = fused_qc_view(c, tsize);
         codes[ncodes++] = c;
         emax = std::max<int64_t>(emax, c->E);
         nmax = std::max(nmax, c->n);
-        words = std::max(words, c->is_qc ? c->qc_words : 0);
-        nblocks = std::max(nblocks, c->is_qc ? c->nblocks : 0);
-        mb = std::max(mb, c->is_qc ? c->mb : 0);
+        words = std::max(words, qc ? c->qc_words : 0);
+        nblocks = std::max(nblocks, qc ? c->nblocks : 0);
+        mb = std::max(mb, qc ? c->mb : 0);
     }
 };
 
@@ -150,12 +165,13 @@ int plan(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, Group *groups, int 
         if (!need_new && groups[ng - 1].code_index(jobs[i].code) < 0) {
             Group trial = groups[ng - 1];
             trial.add_code(jobs[i].code);
-            need_new = groups[ng - 1].ncodes == fused::kMaxCodes || trial.lds(tsize) > limit;
+            need_new = groups[ng - 1].ncodes == fused::kMaxCodes || trial.lds() > limit;
         }
         if (need_new) {
             if (ng == max_groups)
                 return kPlanTooMany;
             groups[ng++] = Group{};
+            groups[ng - 1].tsize = tsize;
         }
         Group &g = groups[ng - 1];
         g.jobs[g.njobs++] = i;
@@ -211,17 +227,20 @@ size_t batch_bytes(const ldpc_job *jobs, int ngroups, const int32_t *plain, int3
     return static_cast<size_t>(ngroups) * kGroupBytes + stream;
 }
 
-fused::Code code_entry(const ldpc_code_s *c)
+fused::Code code_entry(const ldpc_code_s *c, size_t tsize)
 {
+    const bool qc = fused_qc_view(c, tsize);
     fused::Code e{};
     e.m = c->m;
     e.n = c->n;
-    e.Z = c->is_qc ? c->Z : 1;
-    e.nblocks = c->is_qc ? c->nblocks : 0;
-    e.mb = c->is_qc ? c->mb : 0;
-    e.nb = c->is_qc ? c->nb : 0;
-    e.qc = c->is_qc ? 1 : 0;
-    e.words = c->is_qc ? c->qc_words : 0;
+    e.Z = qc ? c->Z : 1;
+    e.nblocks = qc ? c->nblocks : 0;
+    e.mb = qc ? c->mb : 0;
+    e.nb = qc ? c->nb : 0;
+    e.qc = qc ? 1 : 0;
+    e.words = qc ? c->qc_words : 0;
+    e.zmagic = qc ? static_cast<uint32_t>(((1ull << 32) + static_cast<uint64_t>(c->Z) - 1) / static_cast<uint64_t>(c->Z))
+                  : 0u;
     e.tab = c->qc_tab;
     e.row_ptr = c->row_ptr;
     e.col_idx = c->col_idx;
@@ -247,12 +266,12 @@ ldpc_status launch_group(const ldpc_job *jobs, const Group &g, char *ws, int thr
     int32_t nblocks_max = 0;
     for (int32_t k = 0; k < g.ncodes; ++k) {
         const ldpc_code_s *c = g.codes[k];
-        b.codes[k] = code_entry(c);
+        b.codes[k] = code_entry(c, sizeof(typename A::T));
         b.emax = std::max<int32_t>(b.emax, static_cast<int32_t>(c->E));
         b.nmax = std::max(b.nmax, c->n);
-        b.words_max = std::max(b.words_max, c->is_qc ? c->qc_words : 0);
-        b.mb_max = std::max(b.mb_max, c->is_qc ? c->mb : 0);
-        nblocks_max = std::max(nblocks_max, c->is_qc ? c->nblocks : 0);
+        b.words_max = std::max(b.words_max, b.codes[k].words);
+        b.mb_max = std::max(b.mb_max, b.codes[k].mb);
+        nblocks_max = std::max(nblocks_max, b.codes[k].nblocks);
     }
     int64_t items = 0;
     for (int32_t k = 0; k < g.njobs; ++k) {

@@ -22,10 +22,17 @@
 // message is computed with exactly the operations and rounding of the plain
 // path (bit-identical results).
 //
-// LDS per workgroup: r for every edge, a word holding +inf, one dummy-edge
-// slot per thread, the posterior L for every variable, and the code's circulant-block tables (QC
-// codes; row and column views, and spare zero words after the column view
-// so that a column body may read past its own entries).
+// LDS per workgroup (FrameLayout; all accesses by byte offset from its
+// start): the posterior L of every variable, a word holding +inf, one
+// dummy-edge slot per thread, r for every edge, and the code's tables
+// (circulant codes: row and column views, and spare zero words after the
+// column view so that a column body may read past its own entries).
+//
+// Circulant codes keep their messages in a rotated layout: the message of
+// row r of block b, whose shift is s_b, sits at b*Z + ((r + s_b) mod Z),
+// the offset of the edge's column inside its block-column.  A row then
+// finds its message and its posterior from one offset, and a column finds
+// the messages of its blocks without any modular arithmetic.
 #pragma once
 
 #include <mutex>
@@ -45,9 +52,10 @@ constexpr int kMaxJobs = 24;
 // Kernel-argument copy of a code's device layout.
 struct Code {
     int32_t m, n, Z, nblocks;
-    int32_t mb, nb, qc, words;  // words: QC table words (0 for CSR codes)
+    int32_t mb, nb, qc, words;  // qc: use the circulant view (words: QC table words, 0 otherwise)
+    uint32_t zmagic;            // ceil(2^32 / Z): x / Z = mulhi(x, zmagic) for x * Z < 2^32 (qc only, Z >= 2)
     const int32_t *tab, *row_ptr, *col_idx, *col_ptr, *col_edge, *brow_order, *row_gmax, *col_gmax;
-    const int32_t *layer_ptr;  // layered schedule, CSR codes: layer l = rows [layer_ptr[l], layer_ptr[l+1])
+    const int32_t *layer_ptr;  // layered schedule, CSR view: layer l = rows [layer_ptr[l], layer_ptr[l+1])
     int32_t nlayers;
 };
 
@@ -70,77 +78,133 @@ struct Batch {
     Job jobs[kMaxJobs];
 };
 
-// One message-sized LDS word per thread (up to 512), between the messages r
-// and the posteriors: the target of dummy-edge stores, so that a half row's
-// stores need no exec-mask branch and its loads can all be issued first.
+// One message-sized LDS word per thread (up to 512) after the +inf word: the
+// target of dummy-edge stores, so that a half row's stores need no
+// exec-mask branch and its loads can all be issued first.
 constexpr int kDummySlots = 512;
-// Index, relative to the posteriors, of one word just before the dummy slots
-// that holds +inf: half rows read a dummy edge's posterior there, so that
-// q = +inf - (old message) = +inf and the parity bit of +inf (0) need no
-// select; layered half rows write it back unchanged (+inf + r = +inf).
-constexpr int kInfSlot = -(kDummySlots + 1);
 // Zero words after the circulant column table: a column body of length D
 // reads table slots k0 .. k0 + D - 1 whatever the column's degree, which for
 // the last block-columns runs up to D - 1 words past the table's end.  A zero
-// word decodes to message index cc < Z, a valid slot.  Exact column bodies go
-// up to degree 16.
+// word decodes to an offset inside the posteriors, a valid LDS address.
+// Exact column bodies go up to degree 16.
 constexpr int kColSpare = 16;
+
+__host__ __device__ inline uint32_t align16(size_t x) { return static_cast<uint32_t>((x + 15) / 16 * 16); }
+
+// Byte layout of one frame in LDS, for the launch's largest n and E:
+//   [0, n)              posteriors L (message-sized words)
+//   n                   +inf: dummy edges read their posterior there
+//   n + 1 + t           dummy slot of thread t
+//   r0 ..               messages r, one word per edge
+//   t0 ..               the code's tables (int32 words)
+struct FrameLayout {
+    uint32_t r0, t0;
+    size_t bytes;
+};
+__host__ __device__ inline FrameLayout frame_layout(int64_t E, int32_t n, int32_t words, int32_t nblocks, int32_t mb,
+                                                    size_t tsize)
+{
+    FrameLayout f;
+    f.r0 = align16((static_cast<size_t>(n) + 1 + kDummySlots) * tsize);
+    f.t0 = align16(f.r0 + static_cast<size_t>(E) * tsize);
+    f.bytes = f.t0 + static_cast<size_t>(words + 2 * nblocks + mb + kColSpare) * sizeof(int32_t);
+    return f;
+}
 
 // LDS bytes a workgroup needs for one frame of this code.
 __host__ __device__ inline size_t frame_lds_bytes(int64_t E, int32_t n, int32_t words, int32_t nblocks, int32_t mb,
                                                   size_t tsize)
 {
-    const size_t msg = (static_cast<size_t>(E) + 1 + kDummySlots + static_cast<size_t>(n)) * tsize;
-    return (msg + 15) / 16 * 16 + static_cast<size_t>(words + 2 * nblocks + mb + kColSpare) * sizeof(int32_t);
+    return frame_layout(E, n, words, nblocks, mb, tsize).bytes;
 }
 
-// Index view of one check row in slot order.
-//   QC:  ridx(k) = (rbs + k) * Z + r   (block order),  col(k) from the packed block table
-//   CSR: ridx(k) = e0 + k,             col(k) = col_idx[e0 + k]
+// Loads and stores of LDS words by byte offset from the frame's base.
+template <class T>
+__device__ __forceinline__ T lds_ld(const unsigned char *base, uint32_t off)
+{
+    return *reinterpret_cast<const T *>(base + off);
+}
+template <class T>
+__device__ __forceinline__ void lds_st(unsigned char *base, uint32_t off, T v)
+{
+    *reinterpret_cast<T *>(base + off) = v;
+}
+
+__device__ __forceinline__ int32_t div_z(int32_t x, uint32_t zmagic)
+{
+    return static_cast<int32_t>(__umulhi(static_cast<uint32_t>(x), zmagic));
+}
+
+// Byte offsets of the messages and posteriors of one half row.
+//   QC:  slot k of a half row starting at block b0 + k0:
+//        c = tsize * ((r + s) mod Z) for that block's shift s,
+//        message b * Z * tsize + c (rotated layout), posterior j * Z * tsize + c
+//   CSR: slot k is edge e0 + k0 + k (CSR order), posterior col_idx[e]
 struct RowQC {
     // The row table in LDS is followed by at least kColSpare readable words
-    // (the block-row order, the column table and its spare words), so col(k)
-    // may be read for any k < kColSpare past a row's blocks: the value is
-    // then some index, which the caller discards.
+    // (the block-row order, the column table and its spare words), so
+    // offsets(k) may be read for any k < kColSpare past a row's blocks: the
+    // offsets are then some values, which the caller discards.
     static constexpr bool kReadPast = true;
-    int32_t first_block, r, Z;
-    const int32_t *pack;  // LDS: (j * Z) | (shift << 16) per block
-    __device__ int32_t ridx(int k) const { return (first_block + k) * Z + r; }
-    __device__ int32_t col(int k) const
+    uint32_t r_t;          // tsize * r
+    uint32_t z_t;          // tsize * Z
+    uint32_t base;         // r0 + tsize * Z * (first block of this half)
+    const uint32_t *pack;  // LDS, from this half's first block: (tsize * j * Z) | (tsize * s) << 16
+    __device__ __forceinline__ void offsets(int k, uint32_t &ri, uint32_t &ci) const
     {
-        const uint32_t w = static_cast<uint32_t>(pack[first_block + k]);
-        const uint32_t c = static_cast<uint32_t>(r) + (w >> 16);  // in [0, 2Z): min picks c or c - Z
-        return static_cast<int32_t>((w & 0xffffu) + __builtin_elementwise_min(c, c - static_cast<uint32_t>(Z)));
+        const uint32_t w = pack[k];
+        const uint32_t c = r_t + (w >> 16);                             // in [0, 2 z_t): min picks c or c - z_t
+        const uint32_t cm = __builtin_elementwise_min(c, c - z_t);
+        ci = (w & 0xffffu) + cm;
+        ri = base + static_cast<uint32_t>(k) * z_t + cm;
     }
 };
 
+template <int TS>
 struct RowCSR {
     static constexpr bool kReadPast = false;  // col_idx ends with the last row
-    int32_t e0;
-    const int32_t *col_idx;
-    __device__ int32_t ridx(int k) const { return e0 + k; }
-    __device__ int32_t col(int k) const { return col_idx[e0 + k]; }
+    uint32_t base;        // r0 + TS * (e0 + k0)
+    const int32_t *cols;  // global: col_idx + e0 + k0
+    __device__ __forceinline__ void offsets(int k, uint32_t &ri, uint32_t &ci) const
+    {
+        ri = base + static_cast<uint32_t>(k * TS);
+        ci = static_cast<uint32_t>(cols[k] * TS);
+    }
 };
 
-// Column index of slot k of a half row, or `dummy` for a slot past its real
-// edges.  Where the row view allows it the table is read unconditionally, so
-// the load needs no exec-mask branch.
-template <int D, class Row>
-__device__ __forceinline__ int32_t slot_col(const Row &row, int k, bool real, int32_t dummy)
+// Offsets of slot k of a half row: the real edge's, or, for a slot past its
+// edges (a dummy), this thread's dummy slot and the +inf word.  Where the row
+// view allows it the table is read unconditionally, so the load needs no
+// exec-mask branch.
+template <class Row>
+__device__ __forceinline__ void slot_offsets(const Row &row, int k, bool real, uint32_t dslot, uint32_t inf_off,
+                                             uint32_t &ri, uint32_t &ci)
 {
     if constexpr (Row::kReadPast) {
-        static_assert(D <= kColSpare, "half row longer than the readable words past the row table");
-        const int32_t c = row.col(k);
-        return real ? c : dummy;
+        static_assert(kColSpare >= 16, "half rows up to 16 slots read past the row table");
+        uint32_t a, b;
+        row.offsets(k, a, b);
+        ri = real ? a : dslot;
+        ci = real ? b : inf_off;
     } else {
-        return real ? row.col(k) : dummy;
+        if (real) {
+            row.offsets(k, ri, ci);
+        } else {
+            ri = dslot;
+            ci = inf_off;
+        }
     }
 }
+
+// Per-thread places every half row of a frame shares: this thread's dummy
+// slot and the +inf word (byte offsets).
+struct Slots {
+    uint32_t dslot, inf_off;
+};
 
 // Value of the partner lane (lane ^ 32): the other half of the same row.
 // Rows are laid out so that lanes 0..31 of a wavefront hold the first halves
-// of 32 consecutive rows and lanes 32..63 their second halves; each half
-// wavefront then touches 32 consecutive LDS words (no bank conflicts).
+// of 32 consecutive rows and lanes 32..63 their second halves.
 __device__ __forceinline__ uint32_t pair_swap(uint32_t v)
 {
     return static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), 32));
@@ -153,39 +217,35 @@ __device__ __forceinline__ ArithF32::Acc pair_swap(const ArithF32::Acc &v)
 }
 
 // One half of a check row, run-time length dh <= D, as the straight-line
-// body of length D: this lane owns edges k0 .. k0+dh-1 of the row (the first
-// half, or the second), its partner lane the other half.  Edges j >= dh are
+// body of length D: this lane owns dh edges of the row (the first half, or
+// the second), its partner lane the other half.  Slots j >= dh are
 // dummies: they enter as q = +inf, whose terms are the exact identity of the
 // combination (t = 1, u = 0 in FP32; phi = 0 in FP64) with a + sign; they
 // read the +inf posterior word and this thread's dummy slot, and write only
-// to the dummy slot.  All of the half row's indices
-// and loads are issued before its arithmetic.  The forward pass parks (part
-// of) a_k in the edge's own r slot (free once q_k is formed, owned by this
-// lane alone) instead of a register array; after the partner's half
-// combination and sign are exchanged, the backward pass reads a_k back and
-// overwrites the slot with the new message.
+// to the dummy slot.  All of the half row's offsets and loads are issued
+// before its arithmetic.  The forward pass parks (part of) a_k in the edge's
+// own r slot (free once q_k is formed, owned by this lane alone) instead of
+// a register array; after the partner's half combination and sign are
+// exchanged, the backward pass reads a_k back and overwrites the slot with
+// the new message.
 template <class A, int D, class Row>
-__device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, typename A::T *__restrict__ sR,
-                                               const typename A::T *__restrict__ sL, bool first, uint32_t &parity)
+__device__ __forceinline__ void fused_half_row(const Row &row, int dh, unsigned char *__restrict__ s, Slots sl,
+                                               bool first, uint32_t &parity)
 {
     using T = typename A::T;
     typename A::Acc p[D];
     typename A::Keep kp[D];
     typename A::Acc acc = A::identity();
     uint32_t sign = 0, par = 0;
-    const int32_t dslot = static_cast<int32_t>(sL - sR) - kDummySlots + static_cast<int32_t>(threadIdx.x);
-    int32_t ri[D], ci[D];
+    uint32_t ri[D], ci[D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-        const bool real = j < dh;
-        ri[j] = real ? row.ridx(k0 + j) : dslot;
-        ci[j] = slot_col<D>(row, k0 + j, real, kInfSlot);
-    }
+    for (int j = 0; j < D; ++j)
+        slot_offsets(row, j, j < dh, sl.dslot, sl.inf_off, ri[j], ci[j]);
     T lv[D], rv[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        lv[j] = sL[ci[j]];
-        rv[j] = first ? T(0) : sR[ri[j]];
+        lv[j] = lds_ld<T>(s, ci[j]);
+        rv[j] = first ? T(0) : lds_ld<T>(s, ri[j]);
     }
     // A dummy edge reads l = +inf; its slot holds a finite value (a parked
     // term or a clamped message) written by this thread in an earlier
@@ -198,12 +258,12 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
         typename A::Term a_k;
         check_forward<A>(q, a_k, p[j], acc, sign);
         kp[j] = A::keep(a_k);
-        sR[ri[j]] = A::park(a_k);
+        lds_st<T>(s, ri[j], A::park(a_k));
     }
     const typename A::Acc s_other = pair_swap(acc);
     const uint32_t sign_total = sign ^ pair_swap(sign);
     parity |= par ^ pair_swap(par);  // a lane may hold several rows: any unsatisfied row counts
-    typename A::Acc s = A::seed(s_other);
+    typename A::Acc sx = A::seed(s_other);
     // The parked value is read for dummies too (their slot is valid; the
     // value, possibly a later dummy's message, is replaced), which spares an
     // exec-mask branch per slot.  FP32 bodies are held to 128 VGPRs, and the
@@ -214,14 +274,14 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
         const bool real = j < dh;
         T parked;
         if constexpr (kGuardParked) {
-            parked = real ? sR[ri[j]] : T(A::kDummyParked);
+            parked = real ? lds_ld<T>(s, ri[j]) : T(A::kDummyParked);
         } else {
-            const T v = sR[ri[j]];
+            const T v = lds_ld<T>(s, ri[j]);
             parked = real ? v : T(A::kDummyParked);
         }
         const typename A::Term a_k = A::unpark(parked, kp[j]);
-        const T r = check_backward<A>(a_k, p[j], s, sign_total);
-        sR[ri[j]] = r;
+        const T r = check_backward<A>(a_k, p[j], sx, sign_total);
+        lds_st<T>(s, ri[j], r);
     }
 }
 
@@ -229,20 +289,19 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int k0, int dh, t
 // FP32 circulant codes, the hot case; one padded body of length DB for FP64
 // and for CSR codes (fewer instantiations, same results).
 template <class A, int D, int DB, class Row>
-__device__ __forceinline__ void fused_row_dispatch(int hwave, const Row &row, int k0, int dh,
-                                                   typename A::T *__restrict__ sR, const typename A::T *__restrict__ sL,
-                                                   bool first, uint32_t &parity)
+__device__ __forceinline__ void fused_row_dispatch(int hwave, const Row &row, int dh, unsigned char *__restrict__ s,
+                                                   Slots sl, bool first, uint32_t &parity)
 {
     constexpr bool exact = std::is_same<A, ArithF32>::value && std::is_same<Row, RowQC>::value;
     if constexpr (!exact) {
-        fused_half_row<A, DB>(row, k0, dh, sR, sL, first, parity);
+        fused_half_row<A, DB>(row, dh, s, sl, first, parity);
     } else if constexpr (D < DB) {
         if (hwave == D)
-            fused_half_row<A, D>(row, k0, dh, sR, sL, first, parity);
+            fused_half_row<A, D>(row, dh, s, sl, first, parity);
         else
-            fused_row_dispatch<A, D + 1, DB>(hwave, row, k0, dh, sR, sL, first, parity);
+            fused_row_dispatch<A, D + 1, DB>(hwave, row, dh, s, sl, first, parity);
     } else {
-        fused_half_row<A, DB>(row, k0, dh, sR, sL, first, parity);
+        fused_half_row<A, DB>(row, dh, s, sl, first, parity);
     }
 }
 
@@ -255,27 +314,23 @@ __device__ __forceinline__ void fused_row_dispatch(int hwave, const Row &row, in
 // thread's dummy slot and their posterior in the +inf word, which their
 // writes (+inf, and +inf + r) leave unchanged; loads are issued first.
 template <class A, int D, class Row>
-__device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh, typename A::T *__restrict__ sR,
-                                                 typename A::T *__restrict__ sL, bool first)
+__device__ __forceinline__ void layered_half_row(const Row &row, int dh, unsigned char *__restrict__ s, Slots sl,
+                                                 bool first)
 {
     using T = typename A::T;
     typename A::Acc p[D];
     typename A::Keep kp[D];
     typename A::Acc acc = A::identity();
     uint32_t sign = 0;
-    const int32_t dslot = static_cast<int32_t>(sL - sR) - kDummySlots + static_cast<int32_t>(threadIdx.x);
-    int32_t ri[D], ci[D];
+    uint32_t ri[D], ci[D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-        const bool real = j < dh;
-        ri[j] = real ? row.ridx(k0 + j) : dslot;
-        ci[j] = slot_col<D>(row, k0 + j, real, kInfSlot);
-    }
+    for (int j = 0; j < D; ++j)
+        slot_offsets(row, j, j < dh, sl.dslot, sl.inf_off, ri[j], ci[j]);
     T lv[D], rv[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        lv[j] = sL[ci[j]];
-        rv[j] = first ? T(0) : sR[ri[j]];
+        lv[j] = lds_ld<T>(s, ci[j]);
+        rv[j] = first ? T(0) : lds_ld<T>(s, ri[j]);
     }
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -283,51 +338,50 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int k0, int dh,
         typename A::Term a_k;
         check_forward<A>(q, a_k, p[j], acc, sign);
         kp[j] = A::keep(a_k);
-        sR[ri[j]] = A::park(a_k);
-        sL[ci[j]] = q;
+        lds_st<T>(s, ri[j], A::park(a_k));
+        lds_st<T>(s, ci[j], q);
     }
     const typename A::Acc s_other = pair_swap(acc);
     const uint32_t sign_total = sign ^ pair_swap(sign);
-    typename A::Acc s = A::seed(s_other);
+    typename A::Acc sx = A::seed(s_other);
 #pragma unroll
     for (int j = D - 1; j >= 0; --j) {
         const bool real = j < dh;
-        const T parked = sR[ri[j]];  // a dummy's slot is valid; its value may be a later dummy's message
+        const T parked = lds_ld<T>(s, ri[j]);  // a dummy's slot is valid; its value may be a later dummy's message
         const typename A::Term a_k = A::unpark(real ? parked : T(A::kDummyParked), kp[j]);
-        const T r = check_backward<A>(a_k, p[j], s, sign_total);
-        const T q = sL[ci[j]];
-        sR[ri[j]] = r;
-        sL[ci[j]] = q + r;
+        const T r = check_backward<A>(a_k, p[j], sx, sign_total);
+        const T q = lds_ld<T>(s, ci[j]);
+        lds_st<T>(s, ri[j], r);
+        lds_st<T>(s, ci[j], q + r);
     }
 }
 
 template <class A, int D, int DB, class Row>
-__device__ __forceinline__ void layered_row_dispatch(int hwave, const Row &row, int k0, int dh,
-                                                     typename A::T *__restrict__ sR, typename A::T *__restrict__ sL,
-                                                     bool first)
+__device__ __forceinline__ void layered_row_dispatch(int hwave, const Row &row, int dh, unsigned char *__restrict__ s,
+                                                     Slots sl, bool first)
 {
     constexpr bool exact = std::is_same<A, ArithF32>::value && std::is_same<Row, RowQC>::value;
     if constexpr (!exact) {
-        layered_half_row<A, DB>(row, k0, dh, sR, sL, first);
+        layered_half_row<A, DB>(row, dh, s, sl, first);
     } else if constexpr (D < DB) {
         if (hwave == D)
-            layered_half_row<A, D>(row, k0, dh, sR, sL, first);
+            layered_half_row<A, D>(row, dh, s, sl, first);
         else
-            layered_row_dispatch<A, D + 1, DB>(hwave, row, k0, dh, sR, sL, first);
+            layered_row_dispatch<A, D + 1, DB>(hwave, row, dh, s, sl, first);
     } else {
-        layered_half_row<A, DB>(row, k0, dh, sR, sL, first);
+        layered_half_row<A, DB>(row, dh, s, sl, first);
     }
 }
 
 // One half of a check row under the min-sum rule, flooding or (LAYERED)
 // layered, padded body of length D: each lane keeps the running minimum
 // state of its half, the partner lanes merge theirs, and every real edge gets
-// one select.  Flooding folds the parity of the previous decision into
-// `parity` (as fused_half_row); layered writes L = q + r at once.
+// one select.  k0 is the half's first position in the row (positions identify
+// the smallest message).  Flooding folds the parity of the previous decision
+// into `parity` (as fused_half_row); layered writes L = q + r at once.
 template <class A, int D, bool LAYERED, class Row>
-__device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, typename A::T *__restrict__ sR,
-                                            typename A::T *__restrict__ sL, bool first, uint32_t &parity,
-                                            typename A::T scale, typename A::T offset)
+__device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, unsigned char *__restrict__ s, Slots sl,
+                                            bool first, uint32_t &parity, typename A::T scale, typename A::T offset)
 {
     using T = typename A::T;
     T q[D];
@@ -335,23 +389,19 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, type
     min_init(st);
     uint32_t par = 0;
     // dummy edges enter as q = +inf, which leaves the minimum state
-    // unchanged, and store their messages in this thread's dummy slot
-    const int32_t dslot = static_cast<int32_t>(sL - sR) - kDummySlots + static_cast<int32_t>(threadIdx.x);
-    int32_t ri[D], ci[D];
+    // unchanged, and store their messages in this thread's dummy slot; they
+    // read (and, layered, write back) the +inf posterior word, as in
+    // fused_half_row: a min-sum message is clamped too, so the dummy slot
+    // always holds a finite value
+    uint32_t ri[D], ci[D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-        const bool real = j < dh;
-        ri[j] = real ? row.ridx(k0 + j) : dslot;
-        // dummies read (and, layered, write back) the +inf posterior word, as
-        // in fused_half_row: a min-sum message is clamped too, so the dummy
-        // slot always holds a finite value
-        ci[j] = slot_col<D>(row, k0 + j, real, kInfSlot);
-    }
+    for (int j = 0; j < D; ++j)
+        slot_offsets(row, j, j < dh, sl.dslot, sl.inf_off, ri[j], ci[j]);
     T lv[D], rv[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        lv[j] = sL[ci[j]];
-        rv[j] = first ? T(0) : sR[ri[j]];
+        lv[j] = lds_ld<T>(s, ci[j]);
+        rv[j] = first ? T(0) : lds_ld<T>(s, ri[j]);
     }
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -369,28 +419,28 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, type
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         const T r = min_message<A>(st, q[j], k0 + j, scale, offset);
-        sR[ri[j]] = r;
+        lds_st<T>(s, ri[j], r);
         if (LAYERED)
-            sL[ci[j]] = q[j] + r;
+            lds_st<T>(s, ci[j], q[j] + r);
     }
 }
 
 // Column sum L = Lch + sum of r in ascending row order, run-time degree dv <= D
-// (dummy edges read a valid slot and are not added).  SAFE0: every table
+// (dummy edges read a valid word and are not added).  SAFE0: every table
 // slot up to D - 1 past the column's start is readable and decodes to a valid
-// message index (the circulant tables in LDS end with kColSpare zero words),
-// so all D slots are read unconditionally at constant offsets; otherwise
-// dummies read message slot 0.
+// offset (the circulant tables in LDS end with kColSpare zero words), so all
+// D slots are read unconditionally at constant offsets; otherwise dummies
+// read offset 0.  edge(k) is the byte offset of the column's k-th message.
 template <class A, int D, bool SAFE0, class Edge>
 __device__ __forceinline__ typename A::T fused_col(const Edge &edge, int dv, typename A::T acc,
-                                                   const typename A::T *__restrict__ sR)
+                                                   const unsigned char *__restrict__ s)
 {
     using T = typename A::T;
     static_assert(!SAFE0 || D <= kColSpare, "column body longer than the spare words cover");
     T rv[D > 0 ? D : 1];
 #pragma unroll
     for (int k = 0; k < D; ++k)
-        rv[k] = SAFE0 ? sR[edge(k)] : sR[k < dv ? edge(k) : 0];
+        rv[k] = SAFE0 ? lds_ld<T>(s, edge(k)) : lds_ld<T>(s, k < dv ? edge(k) : 0u);
 #pragma unroll
     for (int k = 0; k < D; ++k)
         acc = k < dv ? acc + rv[k] : acc;
@@ -399,38 +449,53 @@ __device__ __forceinline__ typename A::T fused_col(const Edge &edge, int dv, typ
 
 template <class A, int D, bool SAFE0, class Edge>
 __device__ __forceinline__ typename A::T fused_col_dispatch(int dwave, const Edge &edge, int dv, typename A::T acc,
-                                                            const typename A::T *__restrict__ sR)
+                                                            const unsigned char *__restrict__ s)
 {
+    using T = typename A::T;
     if constexpr (!std::is_same<A, ArithF32>::value) {
         for (int k = 0; k < dv; ++k)
-            acc += sR[edge(k)];
+            acc += lds_ld<T>(s, edge(k));
         return acc;
     } else if constexpr (D <= kColSpare) {
         if (dwave == D)
-            return fused_col<A, D, SAFE0>(edge, dv, acc, sR);
-        return fused_col_dispatch<A, D + 1, SAFE0>(dwave, edge, dv, acc, sR);
+            return fused_col<A, D, SAFE0>(edge, dv, acc, s);
+        return fused_col_dispatch<A, D + 1, SAFE0>(dwave, edge, dv, acc, s);
     } else {
         for (int k = 0; k < dv; ++k)
-            acc += sR[edge(k)];
+            acc += lds_ld<T>(s, edge(k));
         return acc;
     }
 }
 
+// Places of one frame's data in LDS, for the launch.
+struct FrameView {
+    unsigned char *s;      // the frame's LDS (posteriors at offset 0)
+    uint32_t r0;           // byte offset of the messages
+    const int32_t *tab;    // the code's tables (raw QC tables, then the views below)
+    Slots slots;
+};
+
+// QC table views in LDS (raw tables of `words` words first):
+//   [words, +nblocks)             row view: pack word of block b
+//   [.., +mb)                     brow_order
+//   [.., +nblocks)                column view: r0 + tsize * Z * b for block-column slot w
+//   [.., +kColSpare)              zero words
 template <class A, int DB>
-__device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int64_t f, typename A::T *__restrict__ sR,
-                             typename A::T *__restrict__ sL, const int32_t *__restrict__ sTab)
+__device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int64_t f, const FrameView &fv)
 {
     using T = typename A::T;
+    constexpr uint32_t TS = sizeof(T);
     const int tid = static_cast<int>(threadIdx.x), NT = static_cast<int>(blockDim.x);
     const int32_t m = c.m, n = c.n, Z = c.Z;
     const T *llr = static_cast<const T *>(job.llr) + f * n;
-    // QC tables in LDS: [row_blk_start mb+1][blk_col][blk_shift][col_blk_start nb+1][col_blk][pack][brow_order]
-    //                   [column pack]
-    const int32_t *rbs = sTab;
-    const int32_t *cbs = sTab + (c.mb + 1) + 2 * c.nblocks;
-    const int32_t *pack = sTab + c.words;
-    const int32_t *border = pack + c.nblocks;
-    const int32_t *cpack = border + c.mb;  // per block-column slot: (block * Z) | (shift << 16)
+    unsigned char *s = fv.s;
+    T *sL = reinterpret_cast<T *>(s);
+    const int32_t *rbs = fv.tab;
+    const int32_t *cbs = fv.tab + (c.mb + 1) + 2 * c.nblocks;
+    const uint32_t *pack = reinterpret_cast<const uint32_t *>(fv.tab + c.words);
+    const int32_t *border = fv.tab + c.words + c.nblocks;
+    const uint32_t *cpack = reinterpret_cast<const uint32_t *>(border + c.mb);
+    const uint32_t z_t = TS * static_cast<uint32_t>(Z);
 
     for (int j = tid; j < n; j += NT)
         sL[j] = llr[j] * T(A::kIn);
@@ -448,35 +513,30 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
         const int lane = tid & 63, half = lane >> 5;
         for (int rb = (tid >> 6) * 32; rb < m; rb += (NT >> 6) * 32) {
             const int dwave = c.row_gmax[__builtin_amdgcn_readfirstlane(rb) >> 5];
-            const int s = rb + (lane & 31);
-            if (dwave == 0 || s >= m)
+            const int sr = rb + (lane & 31);
+            if (dwave == 0 || sr >= m)
                 continue;
             const int hwave = (dwave + 1) >> 1;
-            int32_t d;
             if (c.qc) {
-                const int32_t si = s / Z;
-                const int32_t r = s - si * Z;
+                const int32_t si = div_z(sr, c.zmagic);
+                const int32_t r = sr - si * Z;
                 const int32_t i = border[si];
-                d = rbs[i + 1] - rbs[i];
-                const int32_t h = (d + 1) >> 1;
-                const RowQC row{rbs[i], r, Z, pack};
+                const int32_t b0 = rbs[i], d = rbs[i + 1] - b0, h = (d + 1) >> 1;
+                const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
+                const RowQC row{TS * static_cast<uint32_t>(r), z_t, fv.r0 + z_t * static_cast<uint32_t>(b0 + k0),
+                                pack + b0 + k0};
                 if (ms)
-                    ms_half_row<A, DB / 2, false>(row, half ? h : 0, half ? d - h : h, sR, sL, first, parity, ms_scale,
-                                                  ms_offset);
+                    ms_half_row<A, DB / 2, false>(row, k0, dh, s, fv.slots, first, parity, ms_scale, ms_offset);
                 else
-                    fused_row_dispatch<A, 1, DB / 2>(hwave, row, half ? h : 0, half ? d - h : h, sR, sL, first,
-                                                     parity);
+                    fused_row_dispatch<A, 1, DB / 2>(hwave, row, dh, s, fv.slots, first, parity);
             } else {
-                const int32_t e0 = c.row_ptr[s];
-                d = c.row_ptr[s + 1] - e0;
-                const int32_t h = (d + 1) >> 1;
-                const RowCSR row{e0, c.col_idx};
+                const int32_t e0 = c.row_ptr[sr], d = c.row_ptr[sr + 1] - e0, h = (d + 1) >> 1;
+                const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
+                const RowCSR<TS> row{fv.r0 + TS * static_cast<uint32_t>(e0 + k0), c.col_idx + e0 + k0};
                 if (ms)
-                    ms_half_row<A, DB / 2, false>(row, half ? h : 0, half ? d - h : h, sR, sL, first, parity, ms_scale,
-                                                  ms_offset);
+                    ms_half_row<A, DB / 2, false>(row, k0, dh, s, fv.slots, first, parity, ms_scale, ms_offset);
                 else
-                    fused_row_dispatch<A, 1, DB / 2>(hwave, row, half ? h : 0, half ? d - h : h, sR, sL, first,
-                                                     parity);
+                    fused_row_dispatch<A, 1, DB / 2>(hwave, row, dh, s, fv.slots, first, parity);
             }
         }
         const int unsat = __syncthreads_or(static_cast<int>(parity));
@@ -489,21 +549,15 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
             const T acc = llr[j] * T(A::kIn);
             T v;
             if (c.qc) {
-                const int32_t bj = j / Z;
-                const int32_t cc = j - bj * Z;
+                const int32_t bj = div_z(j, c.zmagic);
+                const uint32_t cc_t = TS * static_cast<uint32_t>(j - bj * Z);
                 const int32_t k0 = cbs[bj];
-                auto edge = [&](int k) {
-                    const uint32_t w = static_cast<uint32_t>(cpack[k0 + k]);
-                    // cc - shift in (-Z, Z); as unsigned, min picks it or it + Z
-                    const uint32_t r = static_cast<uint32_t>(cc) - (w >> 16);
-                    return static_cast<int32_t>((w & 0xffffu) +
-                                                __builtin_elementwise_min(r, r + static_cast<uint32_t>(Z)));
-                };
-                v = fused_col_dispatch<A, 0, true>(dwave, edge, cbs[bj + 1] - k0, acc, sR);
+                auto edge = [&](int k) { return cpack[k0 + k] + cc_t; };
+                v = fused_col_dispatch<A, 0, true>(dwave, edge, cbs[bj + 1] - k0, acc, s);
             } else {
                 const int32_t k0 = c.col_ptr[j];
-                auto edge = [&](int k) { return c.col_edge[k0 + k]; };
-                v = fused_col_dispatch<A, 0, false>(dwave, edge, c.col_ptr[j + 1] - k0, acc, sR);
+                auto edge = [&](int k) { return fv.r0 + TS * static_cast<uint32_t>(c.col_edge[k0 + k]); };
+                v = fused_col_dispatch<A, 0, false>(dwave, edge, c.col_ptr[j + 1] - k0, acc, s);
             }
             sL[j] = v;
         }
@@ -528,39 +582,53 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
 // of [L < 0] is tested before the first pass and after every pass but the
 // last.  Each row's arithmetic is the plain layered path's, bit for bit.
 template <class A, int DB>
-__device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &job, int64_t f,
-                                                     typename A::T *__restrict__ sR, typename A::T *__restrict__ sL,
-                                                     const int32_t *__restrict__ sTab)
+__device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &job, int64_t f, const FrameView &fv)
 {
     using T = typename A::T;
+    constexpr uint32_t TS = sizeof(T);
     const int tid = static_cast<int>(threadIdx.x), NT = static_cast<int>(blockDim.x);
     const int lane = tid & 63, half = lane >> 5, wave = tid >> 6, nwaves = NT >> 6;
     const int32_t m = c.m, n = c.n, Z = c.Z;
     const T *llr = static_cast<const T *>(job.llr) + f * n;
-    const int32_t *rbs = sTab;
-    const int32_t *pack = sTab + c.words;
+    unsigned char *s = fv.s;
+    T *sL = reinterpret_cast<T *>(s);
+    const int32_t *rbs = fv.tab;
+    const uint32_t *pack = reinterpret_cast<const uint32_t *>(fv.tab + c.words);
+    const uint32_t z_t = TS * static_cast<uint32_t>(Z);
 
     for (int j = tid; j < n; j += NT)
         sL[j] = llr[j] * T(A::kIn);
     __syncthreads();
+
+    // View of one half of row sr (natural order).
+    auto qc_half = [&](int32_t i, int32_t r, int32_t &d, int32_t &k0, int32_t &dh) {
+        const int32_t b0 = rbs[i];
+        d = rbs[i + 1] - b0;
+        const int32_t h = (d + 1) >> 1;
+        k0 = half ? h : 0;
+        dh = half ? d - h : h;
+        return RowQC{TS * static_cast<uint32_t>(r), z_t, fv.r0 + z_t * static_cast<uint32_t>(b0 + k0), pack + b0 + k0};
+    };
 
     // 1 if some row is unsatisfied by [sL < 0]: each lane takes one half of a
     // row, partner lanes combine their parities.
     auto unsatisfied = [&]() -> int {
         uint32_t bad = 0;
         for (int rb = wave * 32; rb < m; rb += nwaves * 32) {
-            const int s = rb + (lane & 31);
+            const int sr = rb + (lane & 31);
             uint32_t par = 0;
-            if (s < m) {
+            if (sr < m) {
                 if (c.qc) {
-                    const int32_t si = s / Z;
-                    const int32_t b0 = rbs[si], d = rbs[si + 1] - b0, h = (d + 1) >> 1;
-                    const RowQC row{b0, s - si * Z, Z, pack};
-                    const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
-                    for (int32_t k = 0; k < dh; ++k)
-                        par ^= static_cast<uint32_t>(sL[row.col(k0 + k)] < T(0));
+                    const int32_t si = div_z(sr, c.zmagic);
+                    int32_t d, k0, dh;
+                    const RowQC row = qc_half(si, sr - si * Z, d, k0, dh);
+                    for (int32_t k = 0; k < dh; ++k) {
+                        uint32_t ri, ci;
+                        row.offsets(k, ri, ci);
+                        par ^= static_cast<uint32_t>(lds_ld<T>(s, ci) < T(0));
+                    }
                 } else {
-                    const int32_t e0 = c.row_ptr[s], d = c.row_ptr[s + 1] - e0, h = (d + 1) >> 1;
+                    const int32_t e0 = c.row_ptr[sr], d = c.row_ptr[sr + 1] - e0, h = (d + 1) >> 1;
                     const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
                     for (int32_t k = 0; k < dh; ++k)
                         par ^= static_cast<uint32_t>(sL[c.col_idx[e0 + k0 + k]] < T(0));
@@ -583,18 +651,20 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
             const bool first = (t == 1);
             if (c.qc) {
                 for (int32_t i = 0; i < c.mb; ++i) {
-                    const int32_t b0 = rbs[i], d = rbs[i + 1] - b0, h = (d + 1) >> 1;
                     for (int rb = wave * 32; rb < Z; rb += nwaves * 32) {
                         const int r = rb + (lane & 31);
-                        if (d == 0 || r >= Z)
+                        if (r >= Z)
                             continue;
-                        const RowQC row{b0, r, Z, pack};
+                        int32_t d, k0, dh;
+                        const RowQC row = qc_half(i, r, d, k0, dh);
+                        if (d == 0)
+                            continue;
+                        const int32_t h = (d + 1) >> 1;
                         if (ms)
-                            ms_half_row<A, DB / 2, true>(row, half ? h : 0, half ? d - h : h, sR, sL, first,
-                                                         no_parity, ms_scale, ms_offset);
+                            ms_half_row<A, DB / 2, true>(row, k0, dh, s, fv.slots, first, no_parity, ms_scale,
+                                                         ms_offset);
                         else
-                            layered_row_dispatch<A, 1, DB / 2>(h, row, half ? h : 0, half ? d - h : h, sR, sL,
-                                                               first);
+                            layered_row_dispatch<A, 1, DB / 2>(h, row, dh, s, fv.slots, first);
                     }
                     __syncthreads();
                 }
@@ -609,13 +679,13 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
                         if (d == 0)
                             continue;
                         const int32_t h = (d + 1) >> 1;
-                        const RowCSR row{e0, c.col_idx};
+                        const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
+                        const RowCSR<TS> row{fv.r0 + TS * static_cast<uint32_t>(e0 + k0), c.col_idx + e0 + k0};
                         if (ms)
-                            ms_half_row<A, DB / 2, true>(row, half ? h : 0, half ? d - h : h, sR, sL, first,
-                                                         no_parity, ms_scale, ms_offset);
+                            ms_half_row<A, DB / 2, true>(row, k0, dh, s, fv.slots, first, no_parity, ms_scale,
+                                                         ms_offset);
                         else
-                            layered_row_dispatch<A, 1, DB / 2>(h, row, half ? h : 0, half ? d - h : h, sR, sL,
-                                                               first);
+                            layered_row_dispatch<A, 1, DB / 2>(h, row, dh, s, fv.slots, first);
                     }
                     __syncthreads();
                 }
@@ -648,15 +718,16 @@ template <class A, int DB>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWavesPerEU<A>))) void k_fused(const Batch *__restrict__ batch, unsigned long long *counter)
 {
     using T = typename A::T;
+    constexpr uint32_t TS = sizeof(T);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ long long s_item;
     const Batch &b = *batch;
-    T *sR = reinterpret_cast<T *>(smem);
-    T *sL = sR + b.emax + 1 + kDummySlots;
-    int32_t *sTab = reinterpret_cast<int32_t *>(
-        smem + (static_cast<size_t>(b.emax + 1 + kDummySlots + b.nmax) * sizeof(T) + 15) / 16 * 16);
+    const FrameLayout lay = frame_layout(b.emax, b.nmax, 0, 0, 0, TS);
+    int32_t *sTab = reinterpret_cast<int32_t *>(smem + lay.t0);
+    const uint32_t nmax = static_cast<uint32_t>(b.nmax);
+    const FrameView fv{smem, lay.r0, sTab, Slots{TS * (nmax + 1 + threadIdx.x), TS * nmax}};
     if (threadIdx.x == 0)  // published by the first barrier of the item loop
-        sL[kInfSlot] = T(__builtin_huge_val());
+        reinterpret_cast<T *>(smem)[nmax] = T(__builtin_huge_val());
     int cur_code = -1;
     for (;;) {
         if (threadIdx.x == 0)
@@ -676,25 +747,28 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWaves
             for (int w = threadIdx.x; w < c.words; w += blockDim.x)
                 sTab[w] = c.tab[w];
             if (c.qc) {
+                const uint32_t Z = static_cast<uint32_t>(c.Z);
                 const int32_t *bcol = c.tab + (c.mb + 1);
                 const int32_t *bsh = bcol + c.nblocks;
                 for (int w = threadIdx.x; w < c.nblocks; w += blockDim.x)
-                    sTab[c.words + w] = (bcol[w] * c.Z) | (bsh[w] << 16);
+                    sTab[c.words + w] = static_cast<int32_t>((TS * static_cast<uint32_t>(bcol[w]) * Z) |
+                                                             ((TS * static_cast<uint32_t>(bsh[w])) << 16));
                 for (int w = threadIdx.x; w < c.mb; w += blockDim.x)
                     sTab[c.words + c.nblocks + w] = c.brow_order[w];
                 // the column phase's view: block-column slot w holds block cb[w]
                 const int32_t *cb = bsh + c.nblocks + (c.nb + 1);
                 for (int w = threadIdx.x; w < c.nblocks; w += blockDim.x)
-                    sTab[c.words + c.nblocks + c.mb + w] = (cb[w] * c.Z) | (bsh[cb[w]] << 16);
+                    sTab[c.words + c.nblocks + c.mb + w] =
+                        static_cast<int32_t>(lay.r0 + TS * Z * static_cast<uint32_t>(cb[w]));
                 if (threadIdx.x < kColSpare)  // readable words past the column table's end
                     sTab[c.words + 2 * c.nblocks + c.mb + threadIdx.x] = 0;
             }
             __syncthreads();
         }
         if (job.flags & LDPC_LAYERED)
-            decode_frame_layered<A, DB>(c, job, item - job.item_begin, sR, sL, sTab);
+            decode_frame_layered<A, DB>(c, job, item - job.item_begin, fv);
         else
-            decode_frame<A, DB>(c, job, item - job.item_begin, sR, sL, sTab);
+            decode_frame<A, DB>(c, job, item - job.item_begin, fv);
         __syncthreads();
     }
 }
