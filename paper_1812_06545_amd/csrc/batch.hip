@@ -233,6 +233,7 @@ fused::Code code_entry(const ldpc_code_s *c, size_t tsize)
     fused::Code e{};
     e.m = c->m;
     e.n = c->n;
+    e.E = static_cast<int32_t>(c->E);
     e.Z = qc ? c->Z : 1;
     e.nblocks = qc ? c->nblocks : 0;
     e.mb = qc ? c->mb : 0;
@@ -311,6 +312,9 @@ ldpc_status launch_group(const ldpc_job *jobs, const Group &g, char *ws, int thr
 }
 
 }  // namespace
+
+size_t fused_group_bytes() { return kGroupBytes; }
+
 }  // namespace ldpc
 
 // Scratch memory of ldpc_decode_batch_noalloc: the batch tables and work

@@ -51,7 +51,7 @@ constexpr int kMaxJobs = 24;
 
 // Kernel-argument copy of a code's device layout.
 struct Code {
-    int32_t m, n, Z, nblocks;
+    int32_t m, n, E, Z, nblocks;
     int32_t mb, nb, qc, words;  // qc: use the circulant view (words: QC table words, 0 otherwise)
     uint32_t zmagic;            // ceil(2^32 / Z): x / Z = mulhi(x, zmagic) for x * Z < 2^32 (qc only, Z >= 2)
     const int32_t *tab, *row_ptr, *col_idx, *col_ptr, *col_edge, *brow_order, *row_gmax, *col_gmax;
@@ -230,7 +230,7 @@ __device__ __forceinline__ ArithF32::Acc pair_swap(const ArithF32::Acc &v)
 // the new message.
 template <class A, int D, class Row>
 __device__ __forceinline__ void fused_half_row(const Row &row, int dh, unsigned char *__restrict__ s, Slots sl,
-                                               bool first, uint32_t &parity)
+                                               uint32_t &parity)
 {
     using T = typename A::T;
     typename A::Acc p[D];
@@ -245,7 +245,7 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int dh, unsigned 
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         lv[j] = lds_ld<T>(s, ci[j]);
-        rv[j] = first ? T(0) : lds_ld<T>(s, ri[j]);
+        rv[j] = lds_ld<T>(s, ri[j]);
     }
     // A dummy edge reads l = +inf; its slot holds a finite value (a parked
     // term or a clamped message) written by this thread in an earlier
@@ -254,7 +254,7 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int dh, unsigned 
     for (int j = 0; j < D; ++j) {
         const T l = lv[j];
         par ^= static_cast<uint32_t>(l < T(0));
-        const T q = first ? l : l - rv[j];
+        const T q = l - rv[j];
         typename A::Term a_k;
         check_forward<A>(q, a_k, p[j], acc, sign);
         kp[j] = A::keep(a_k);
@@ -290,18 +290,18 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int dh, unsigned 
 // and for CSR codes (fewer instantiations, same results).
 template <class A, int D, int DB, class Row>
 __device__ __forceinline__ void fused_row_dispatch(int hwave, const Row &row, int dh, unsigned char *__restrict__ s,
-                                                   Slots sl, bool first, uint32_t &parity)
+                                                   Slots sl, uint32_t &parity)
 {
     constexpr bool exact = std::is_same<A, ArithF32>::value && std::is_same<Row, RowQC>::value;
     if constexpr (!exact) {
-        fused_half_row<A, DB>(row, dh, s, sl, first, parity);
+        fused_half_row<A, DB>(row, dh, s, sl, parity);
     } else if constexpr (D < DB) {
         if (hwave == D)
-            fused_half_row<A, D>(row, dh, s, sl, first, parity);
+            fused_half_row<A, D>(row, dh, s, sl, parity);
         else
-            fused_row_dispatch<A, D + 1, DB>(hwave, row, dh, s, sl, first, parity);
+            fused_row_dispatch<A, D + 1, DB>(hwave, row, dh, s, sl, parity);
     } else {
-        fused_half_row<A, DB>(row, dh, s, sl, first, parity);
+        fused_half_row<A, DB>(row, dh, s, sl, parity);
     }
 }
 
@@ -314,8 +314,7 @@ __device__ __forceinline__ void fused_row_dispatch(int hwave, const Row &row, in
 // thread's dummy slot and their posterior in the +inf word, which their
 // writes (+inf, and +inf + r) leave unchanged; loads are issued first.
 template <class A, int D, class Row>
-__device__ __forceinline__ void layered_half_row(const Row &row, int dh, unsigned char *__restrict__ s, Slots sl,
-                                                 bool first)
+__device__ __forceinline__ void layered_half_row(const Row &row, int dh, unsigned char *__restrict__ s, Slots sl)
 {
     using T = typename A::T;
     typename A::Acc p[D];
@@ -330,11 +329,11 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int dh, unsigne
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         lv[j] = lds_ld<T>(s, ci[j]);
-        rv[j] = first ? T(0) : lds_ld<T>(s, ri[j]);
+        rv[j] = lds_ld<T>(s, ri[j]);
     }
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        const T q = first ? lv[j] : lv[j] - rv[j];  // +inf for a dummy
+        const T q = lv[j] - rv[j];  // +inf for a dummy
         typename A::Term a_k;
         check_forward<A>(q, a_k, p[j], acc, sign);
         kp[j] = A::keep(a_k);
@@ -358,18 +357,18 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int dh, unsigne
 
 template <class A, int D, int DB, class Row>
 __device__ __forceinline__ void layered_row_dispatch(int hwave, const Row &row, int dh, unsigned char *__restrict__ s,
-                                                     Slots sl, bool first)
+                                                     Slots sl)
 {
     constexpr bool exact = std::is_same<A, ArithF32>::value && std::is_same<Row, RowQC>::value;
     if constexpr (!exact) {
-        layered_half_row<A, DB>(row, dh, s, sl, first);
+        layered_half_row<A, DB>(row, dh, s, sl);
     } else if constexpr (D < DB) {
         if (hwave == D)
-            layered_half_row<A, D>(row, dh, s, sl, first);
+            layered_half_row<A, D>(row, dh, s, sl);
         else
-            layered_row_dispatch<A, D + 1, DB>(hwave, row, dh, s, sl, first);
+            layered_row_dispatch<A, D + 1, DB>(hwave, row, dh, s, sl);
     } else {
-        layered_half_row<A, DB>(row, dh, s, sl, first);
+        layered_half_row<A, DB>(row, dh, s, sl);
     }
 }
 
@@ -381,7 +380,7 @@ __device__ __forceinline__ void layered_row_dispatch(int hwave, const Row &row, 
 // into `parity` (as fused_half_row); layered writes L = q + r at once.
 template <class A, int D, bool LAYERED, class Row>
 __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, unsigned char *__restrict__ s, Slots sl,
-                                            bool first, uint32_t &parity, typename A::T scale, typename A::T offset)
+                                            uint32_t &parity, typename A::T scale, typename A::T offset)
 {
     using T = typename A::T;
     T q[D];
@@ -401,13 +400,13 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, unsi
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         lv[j] = lds_ld<T>(s, ci[j]);
-        rv[j] = first ? T(0) : lds_ld<T>(s, ri[j]);
+        rv[j] = lds_ld<T>(s, ri[j]);
     }
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         if (!LAYERED)
             par ^= static_cast<uint32_t>(lv[j] < T(0));
-        q[j] = first ? lv[j] : lv[j] - rv[j];
+        q[j] = lv[j] - rv[j];
         min_add(st, q[j], k0 + j);
     }
     const T o_m1 = pair_swap(st.m1), o_m2 = pair_swap(st.m2);
@@ -475,6 +474,19 @@ struct FrameView {
     Slots slots;
 };
 
+// Messages r start at 0 (before the first iteration, or pass, there are
+// none), and so does this thread's dummy slot: the first iteration then
+// forms q = L - 0 = L exactly, as the streaming kernels' first iteration,
+// with the same code as every later one.
+template <class T>
+__device__ __forceinline__ void start_messages(const Code &c, const FrameView &fv)
+{
+    T *sR = reinterpret_cast<T *>(fv.s + fv.r0);
+    for (int e = static_cast<int>(threadIdx.x); e < c.E; e += static_cast<int>(blockDim.x))
+        sR[e] = T(0);
+    lds_st<T>(fv.s, fv.slots.dslot, T(0));
+}
+
 // QC table views in LDS (raw tables of `words` words first):
 //   [words, +nblocks)             row view: pack word of block b
 //   [.., +mb)                     brow_order
@@ -499,6 +511,7 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
 
     for (int j = tid; j < n; j += NT)
         sL[j] = llr[j] * T(A::kIn);
+    start_messages<T>(c, fv);
     __syncthreads();
 
     const bool es = (job.flags & LDPC_EARLY_STOP) != 0;
@@ -506,7 +519,6 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
     const T ms_scale = static_cast<T>(job.ms_scale), ms_offset = static_cast<T>(job.ms_offset * A::kIn);
     int32_t it = job.max_iter;
     for (int32_t t = 1; t <= job.max_iter; ++t) {
-        const bool first = (t == 1);
         uint32_t parity = 0;
         // two lanes per check row: in each wavefront, lane l < 32 takes the
         // first half of slot rb + l and lane l + 32 its second half
@@ -526,17 +538,17 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
                 const RowQC row{TS * static_cast<uint32_t>(r), z_t, fv.r0 + z_t * static_cast<uint32_t>(b0 + k0),
                                 pack + b0 + k0};
                 if (ms)
-                    ms_half_row<A, DB / 2, false>(row, k0, dh, s, fv.slots, first, parity, ms_scale, ms_offset);
+                    ms_half_row<A, DB / 2, false>(row, k0, dh, s, fv.slots, parity, ms_scale, ms_offset);
                 else
-                    fused_row_dispatch<A, 1, DB / 2>(hwave, row, dh, s, fv.slots, first, parity);
+                    fused_row_dispatch<A, 1, DB / 2>(hwave, row, dh, s, fv.slots, parity);
             } else {
                 const int32_t e0 = c.row_ptr[sr], d = c.row_ptr[sr + 1] - e0, h = (d + 1) >> 1;
                 const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
                 const RowCSR<TS> row{fv.r0 + TS * static_cast<uint32_t>(e0 + k0), c.col_idx + e0 + k0};
                 if (ms)
-                    ms_half_row<A, DB / 2, false>(row, k0, dh, s, fv.slots, first, parity, ms_scale, ms_offset);
+                    ms_half_row<A, DB / 2, false>(row, k0, dh, s, fv.slots, parity, ms_scale, ms_offset);
                 else
-                    fused_row_dispatch<A, 1, DB / 2>(hwave, row, dh, s, fv.slots, first, parity);
+                    fused_row_dispatch<A, 1, DB / 2>(hwave, row, dh, s, fv.slots, parity);
             }
         }
         const int unsat = __syncthreads_or(static_cast<int>(parity));
@@ -598,6 +610,7 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
 
     for (int j = tid; j < n; j += NT)
         sL[j] = llr[j] * T(A::kIn);
+    start_messages<T>(c, fv);
     __syncthreads();
 
     // View of one half of row sr (natural order).
@@ -648,8 +661,7 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
         it = 0;
     } else {
         for (int32_t t = 1; t <= job.max_iter; ++t) {
-            const bool first = (t == 1);
-            if (c.qc) {
+                if (c.qc) {
                 for (int32_t i = 0; i < c.mb; ++i) {
                     for (int rb = wave * 32; rb < Z; rb += nwaves * 32) {
                         const int r = rb + (lane & 31);
@@ -661,10 +673,9 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
                             continue;
                         const int32_t h = (d + 1) >> 1;
                         if (ms)
-                            ms_half_row<A, DB / 2, true>(row, k0, dh, s, fv.slots, first, no_parity, ms_scale,
-                                                         ms_offset);
+                            ms_half_row<A, DB / 2, true>(row, k0, dh, s, fv.slots, no_parity, ms_scale, ms_offset);
                         else
-                            layered_row_dispatch<A, 1, DB / 2>(h, row, dh, s, fv.slots, first);
+                            layered_row_dispatch<A, 1, DB / 2>(h, row, dh, s, fv.slots);
                     }
                     __syncthreads();
                 }
@@ -682,10 +693,9 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
                         const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
                         const RowCSR<TS> row{fv.r0 + TS * static_cast<uint32_t>(e0 + k0), c.col_idx + e0 + k0};
                         if (ms)
-                            ms_half_row<A, DB / 2, true>(row, k0, dh, s, fv.slots, first, no_parity, ms_scale,
-                                                         ms_offset);
+                            ms_half_row<A, DB / 2, true>(row, k0, dh, s, fv.slots, no_parity, ms_scale, ms_offset);
                         else
-                            layered_row_dispatch<A, 1, DB / 2>(h, row, dh, s, fv.slots, first);
+                            layered_row_dispatch<A, 1, DB / 2>(h, row, dh, s, fv.slots);
                     }
                     __syncthreads();
                 }
