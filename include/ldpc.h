@@ -278,7 +278,9 @@ typedef struct {
     size_t mem_budget_bytes;   /* arena for in-flight requests: about budget/10 coded bits (frames x n) at once,
                                   each 4 bytes of device memory (LLR) and 9 of pinned host memory */
     int32_t max_inflight;      /* concurrent launch groups (streams), 1 .. 8 */
-    int32_t max_group_frames;  /* cap on frames per launch group (bounds latency), >= 1 */
+    int32_t max_group_frames;  /* cap on frames per launch group (bounds latency), >= 1; each launch slot
+                                  also reserves about 4.4 KiB of device memory per frame of this cap for
+                                  the launch tables of the group's fused launches */
     int32_t max_queue;         /* queued requests beyond which submit returns LDPC_EBUSY, >= 1 */
 } ldpc_server_cfg;
 

@@ -140,6 +140,10 @@ ldpc_status launch_copy16(void *dst, const void *src, size_t bytes, hipStream_t 
 // for copies that cross the host link while other kernels run.
 ldpc_status launch_link_copy16(void *dst, const void *src, size_t bytes, int32_t max_blocks, hipStream_t stream);
 
+// Workspace bytes of one fused launch of ldpc_decode_batch (its job table
+// and work counter).  A batch of J jobs needs at most J such launches.
+size_t fused_group_bytes();
+
 // Streaming (per-iteration) path.
 size_t stream_workspace_bytes(const ldpc_code_s *c, ldpc_dtype dt, int32_t frames, int32_t max_iter);
 // ms_scale / ms_offset: the min-sum magnitude correction (used with

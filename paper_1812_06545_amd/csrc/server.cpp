@@ -600,7 +600,12 @@ try {
     sv->elems = RangeAlloc(elems_cap);
     sv->frames = RangeAlloc(frames_cap);
     sv->slots.resize(cfg->max_inflight);
-    const size_t ws_bytes = (static_cast<size_t>(cfg->max_group_frames) / 24 + 2) * 8192;
+    // A group's requests become at most one job each (alike neighbours
+    // merge), and its jobs at most one fused launch each (codes that do not
+    // fit one launch's LDS together split it), so max_group_frames launch
+    // tables always suffice, whatever the mix of codes, iteration limits
+    // and flags.
+    const size_t ws_bytes = static_cast<size_t>(cfg->max_group_frames) * ldpc::fused_group_bytes();
     for (Slot &s : sv->slots) {
         s.ws_bytes = ws_bytes;
         if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
