@@ -99,7 +99,8 @@ typedef enum { LDPC_F32 = 0, LDPC_F64 = 1 } ldpc_dtype;
 
 typedef struct ldpc_code_s *ldpc_code;
 
-/* Human-readable name of a status code (static storage). */
+/* Human-readable name of a status code (static storage).  Not an operation of
+ * the paper: the error convention of this library. */
 const char *ldpc_status_str(ldpc_status status);
 
 /*
@@ -129,7 +130,8 @@ ldpc_status ldpc_code_from_csr(int32_t m, int32_t n, const int32_t *row_ptr, con
  */
 ldpc_status ldpc_code_from_qc(int32_t mb, int32_t nb, int32_t Z, const int32_t *shifts, ldpc_code *out);
 
-/* Sizes of a code: m, n and the number of edges (ones of H).  Any output may be NULL. */
+/* Sizes of a code (Section II: m check nodes, n variable nodes, one Tanner
+ * graph edge per 1 of H): m, n and the number of edges.  Any output may be NULL. */
 ldpc_status ldpc_code_info(ldpc_code code, int32_t *m, int32_t *n, int64_t *edges);
 
 /* Layers of the layered schedule (Section II, Algorithm 2): the rows in
@@ -139,13 +141,16 @@ ldpc_status ldpc_code_info(ldpc_code code, int32_t *m, int32_t *n, int64_t *edge
  * output may be NULL. */
 ldpc_status ldpc_code_layers(ldpc_code code, int32_t *nlayers, int32_t *min_rows, int32_t *max_rows);
 
-/* Release a code.  The caller must ensure no enqueued work still uses it.  NULL is ignored. */
+/* Release a code (library bookkeeping, no paper passage).  The caller must
+ * ensure no enqueued work still uses it.  NULL is ignored. */
 void ldpc_code_destroy(ldpc_code code);
 
 /*
  * Workspace needed by ldpc_decode for `frames` frames of `code` in `dtype`
  * with at most `max_iter` iterations.  Frames are padded to a multiple of 64;
- * the messages are stored edge-major with frames innermost.
+ * the messages are stored edge-major with frames innermost (the interleaved
+ * frame layout of Section III-B: the same node of consecutive frames side by
+ * side).
  */
 ldpc_status ldpc_workspace_bytes(ldpc_code code, ldpc_dtype dtype, int32_t frames, int32_t max_iter,
                                  size_t *bytes);
@@ -153,9 +158,11 @@ ldpc_status ldpc_workspace_bytes(ldpc_code code, ldpc_dtype dtype, int32_t frame
 /*
  * Decode `frames` frames with per-iteration kernel launches (the plain
  * path, messages streamed through device memory): flooding runs one
- * check-node and one variable-node kernel per iteration; layered
- * (LDPC_LAYERED) one kernel per layer, plus a syndrome kernel per iteration
- * with early stop.
+ * check-node and one variable-node kernel per iteration (Section II,
+ * Algorithm 1: Loop 2, then Loops 3 and 4; the launch boundary is the
+ * two-phase barrier); layered (LDPC_LAYERED; Algorithm 2) one kernel per
+ * layer, plus a syndrome kernel per iteration with early stop.  The frames
+ * are interleaved on the device as in Section III-B.
  *   dtype      LDPC_F32 (llr/posterior are float) or LDPC_F64 (double)
  *   max_iter   >= 0; 0 returns the hard decision of llr, iters 0, posterior = llr
  *   flags      any of LDPC_EARLY_STOP, LDPC_LAYERED, LDPC_MIN_SUM (or 0)
@@ -171,7 +178,8 @@ ldpc_status ldpc_decode(ldpc_code code, ldpc_dtype dtype, int32_t frames, int32_
                         size_t workspace_bytes, void *stream);
 
 /*
- * ldpc_decode with the min-sum magnitude correction given: with LDPC_MIN_SUM
+ * ldpc_decode with the min-sum magnitude correction given (Section II: the
+ * min-sum rule Algorithm 1 is named after): with LDPC_MIN_SUM
  * in flags, |r| = max(ms_scale * min - ms_offset, 0) before the clamp
  * (ms_offset in natural LLR units).  EINVAL unless ms_scale is finite and
  * > 0 and ms_offset finite and >= 0 (checked whatever the flags).
@@ -180,7 +188,8 @@ ldpc_status ldpc_decode_minsum(ldpc_code code, ldpc_dtype dtype, int32_t frames,
                                float ms_scale, float ms_offset, const void *llr, uint8_t *bits, int32_t *iters,
                                void *posterior, void *workspace, size_t workspace_bytes, void *stream);
 
-/* One decoding job of a batch: same meaning as the ldpc_decode arguments. */
+/* One decoding job of a batch (Section III-A: one code's frames, decoded
+ * alike): same meaning as the ldpc_decode arguments. */
 typedef struct {
     ldpc_code code;
     int32_t frames;
@@ -195,12 +204,17 @@ typedef struct {
 } ldpc_job;
 
 /*
- * Workspace for ldpc_decode_batch over these jobs (all of one dtype).
+ * Workspace for ldpc_decode_batch over these jobs (all of one dtype): the job
+ * tables of its persistent launches (Section III-A), and the streaming
+ * workspace of the largest job that takes the plain path.
  */
 ldpc_status ldpc_batch_workspace_bytes(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, size_t *bytes);
 
 /*
- * Decode a batch of jobs of possibly different codes, lengths and rates.
+ * Decode a batch of jobs of possibly different codes, lengths and rates
+ * (Section III-A: frame-level parallelism, the same decoding carried out
+ * for many frames at once, a workgroup per frame here; Section III-C: work
+ * from several sources kept in flight together, here in one launch).
  * Jobs whose code fits the fused frame-resident kernel (messages of one
  * frame held in LDS) run together in ONE persistent launch whose workgroups
  * pull (job, frame) items from a device-side queue; each workgroup runs every
@@ -239,7 +253,9 @@ ldpc_status ldpc_decode_batch_noalloc(const ldpc_job *jobs, int32_t njobs, ldpc_
 
 /*
  * Plans: the launch sequence of ldpc_decode_batch for these jobs, captured
- * once in a HIP graph (kernel nodes only) and replayed by ldpc_plan_launch.
+ * once in a HIP graph (kernel nodes only) and replayed by ldpc_plan_launch
+ * (Section III-C: the paper's streams re-issue the same per-batch kernel
+ * sequence for every batch; a plan records it once and replays it).
  * The job buffers and the workspace are fixed at creation and must outlive
  * the plan; each launch decodes whatever the LLR buffers hold when it runs,
  * with results identical to ldpc_decode_batch on the same inputs.  Creation
@@ -254,7 +270,9 @@ void ldpc_plan_destroy(ldpc_plan plan);
 
 /*
  * Serving: continuous batching of decode requests (one request = 1 or more
- * frames of one code).  A scheduler thread owned by the server admits queued
+ * frames of one code), the concurrency of Section III-C (several host
+ * threads keeping their own frames in flight on the GPU) re-designed: requests
+ * of any thread join the next launch group as memory and slots free up.  A scheduler thread owned by the server admits queued
  * requests, first come first served, whenever arena memory (fixed at
  * creation, sized by mem_budget_bytes) and one of max_inflight launch slots
  * are free; each admitted group's LLRs are packed contiguously in pinned host
@@ -292,7 +310,8 @@ typedef struct {
     int64_t max_queue_depth;
 } ldpc_server_stats;
 
-/* Create a server on the current device.  Before returning it decodes one
+/* Create a server on the current device (Section III-C, as above).  Before
+ * returning it decodes one
  * frame of every code on every launch stream (synchronously), so that stream
  * set-up and kernel loading, which happen on first use, are not charged to
  * the first requests.  EINVAL for bad sizes or NULL arguments, EUNSUPPORTED
@@ -301,7 +320,8 @@ typedef struct {
 ldpc_status ldpc_server_create(const ldpc_server_cfg *cfg, ldpc_server *out);
 
 /*
- * Queue a request: `frames` frames of codes[code_id], LLRs llr[frames][n]
+ * Queue a request (Section III-C: a host thread handing its frames to the
+ * GPU): `frames` frames of codes[code_id], LLRs llr[frames][n]
  * (host memory, float), decoded with max_iter / flags as in ldpc_decode
  * (flags 0 or LDPC_EARLY_STOP: the server runs the flooding schedule only).
  * Outputs go to host memory bits[frames][n], iters[frames] and, if non-NULL,
@@ -321,24 +341,31 @@ ldpc_status ldpc_server_submit(ldpc_server server, int32_t code_id, int32_t fram
                                const float *llr, uint8_t *bits, int32_t *iters, float *posterior, int64_t arrival_ns,
                                uint64_t *ticket);
 
-/* *done = 1 when the request's outputs are complete (0 otherwise).  EINVAL for an unknown ticket. */
+/* *done = 1 when the request's outputs are complete (0 otherwise).  EINVAL for
+ * an unknown ticket.  (Section III-C: a worker learning that its frames are
+ * decoded.) */
 ldpc_status ldpc_server_poll(ldpc_server server, uint64_t ticket, int32_t *done);
 
-/* Block until the request is done or timeout_ms elapses (LDPC_EBUSY on timeout). */
+/* Block until the request is done or timeout_ms elapses (LDPC_EBUSY on
+ * timeout); the blocking wait of Section III-C's workers. */
 ldpc_status ldpc_server_wait(ldpc_server server, uint64_t ticket, double timeout_ms);
 
-/* Remove a request that is still queued (LDPC_OK); LDPC_EBUSY if it is already on the device or done. */
+/* Remove a request that is still queued (LDPC_OK); LDPC_EBUSY if it is
+ * already on the device or done.  (Serving bookkeeping; no paper passage.) */
 ldpc_status ldpc_server_cancel(ldpc_server server, uint64_t ticket);
 
-/* Counters and latency percentiles since creation or the last reset. */
+/* Counters and latency percentiles since creation or the last reset
+ * (throughput and latency, the quantities of Section IV's measurements). */
 ldpc_status ldpc_server_stats_get(ldpc_server server, ldpc_server_stats *out, int reset);
 
-/* Finish every admitted and queued request, stop the scheduler, free everything. */
+/* Finish every admitted and queued request, stop the scheduler, free
+ * everything.  (Serving bookkeeping; no paper passage.) */
 void ldpc_server_destroy(ldpc_server server);
 
 /*
  * Workgroup size (a multiple of 64, at most 512) of the fused frame-resident
- * kernel used by ldpc_decode_batch; default 512.  EINVAL for other values.  Process-wide setting (the
+ * kernel used by ldpc_decode_batch (Section III-A: the threads that decode
+ * one frame); default 512.  EINVAL for other values.  Process-wide setting (the
  * autotuner writes it); affects speed only, never results.
  */
 ldpc_status ldpc_batch_set_threads(int32_t threads);
@@ -360,7 +387,7 @@ ldpc_status ldpc_autotune_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype 
 
 /*
  * Whether frames of `code` in `dtype` can run in the fused frame-resident
- * kernel on the current device (row degree <= 32, n < 65536 and one frame's
+ * kernel (Section III-A: one frame per workgroup) on the current device (row degree <= 32, n < 65536 and one frame's
  * messages within one workgroup's LDS).  LDPC_OK if so, LDPC_EUNSUPPORTED if
  * ldpc_decode_batch would route the code through the plain path; *lds_bytes
  * (may be NULL) receives the LDS one frame needs.
@@ -368,7 +395,8 @@ ldpc_status ldpc_autotune_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype 
 ldpc_status ldpc_batch_fits_fused(ldpc_code code, ldpc_dtype dtype, size_t *lds_bytes);
 
 /*
- * Per-kernel device timing, a measurement aid (not part of decoding).  While
+ * Per-kernel device timing, a measurement aid (not part of decoding; the
+ * per-stage timing breakdown of Section IV, kernel by kernel).  While
  * enabled, every kernel the library launches outside a stream capture is
  * bracketed by a pair of HIP events on its own stream.  ldpc_profile_collect
  * waits for the recorded events, writes for each kernel kind k the summed
@@ -421,7 +449,9 @@ ldpc_status ldpc_mstream_run(ldpc_code code, int32_t workers, int32_t frames_per
 /*
  * Streaming copy of `bytes` (a multiple of 16; both pointers 16-byte aligned,
  * device memory) on `stream`: a yardstick for achievable HBM bandwidth and
- * for scaling hardware byte counters.  Not part of decoding.
+ * for scaling hardware byte counters (Section III: the decoder is bound by
+ * its memory accesses, so their achievable rate is the reference).  Not part
+ * of decoding.
  */
 ldpc_status ldpc_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
 
