@@ -79,16 +79,21 @@ __global__ __launch_bounds__(256) void k_ingest(const typename A::T *__restrict_
     }
 }
 
+// done[f] = -1 (running) for every frame, done[Fp + c] = 64 running frames
+// per chunk, unsat = 0.
 __global__ __launch_bounds__(256) void k_frames_init(int64_t Fp, int32_t *__restrict__ done,
                                                      int32_t *__restrict__ unsat, int64_t unsat_words)
 {
+    const int64_t nchunk = Fp / kChunk;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < Fp + unsat_words;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < Fp + nchunk + unsat_words;
          i += stride) {
         if (i < Fp)
             done[i] = -1;
+        else if (i < Fp + nchunk)
+            done[i] = kChunk;
         else
-            unsat[i - Fp] = 0;
+            unsat[i - Fp - nchunk] = 0;
     }
 }
 
@@ -146,6 +151,8 @@ __global__ __launch_bounds__(256) void k_syndrome(const int32_t *__restrict__ ro
     const int row = group * kWaves + wave;
     if (row >= m)
         return;
+    if (chunk_active(done, nchunk, chunk) == 0)
+        return;
     const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
     if (done[f] >= 0)
         return;
@@ -161,13 +168,16 @@ __global__ __launch_bounds__(256) void k_syndrome(const int32_t *__restrict__ ro
         unsat[f] = 1;
 }
 
-// A frame still running whose decision x^t satisfies every row stops at t.
+// A frame still running whose decision x^t satisfies every row stops at t
+// (and leaves its chunk's count of running frames).
 __global__ __launch_bounds__(256) void k_retire(int64_t Fp, int32_t *__restrict__ done,
                                                 const int32_t *__restrict__ unsat, int32_t t)
 {
     const int64_t f = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (f < Fp && done[f] < 0 && unsat[f] == 0)
+    if (f < Fp && done[f] < 0 && unsat[f] == 0) {
         done[f] = t;
+        atomicSub(&done[Fp + f / kChunk], 1);
+    }
 }
 
 struct Carve {
@@ -188,7 +198,7 @@ size_t ws_bytes(const ldpc_code_s *c, int64_t Fp, int32_t max_iter)
     size_t b = 0;
     b += align_up(static_cast<size_t>(c->E) * Fp * sizeof(T), 256);
     b += 2 * align_up(static_cast<size_t>(c->n) * Fp * sizeof(T), 256);
-    b += align_up(static_cast<size_t>(Fp) * sizeof(int32_t), 256);
+    b += align_up(static_cast<size_t>(Fp + Fp / kChunk) * sizeof(int32_t), 256);  // done, chunk counts
     b += align_up(static_cast<size_t>(std::max(max_iter, 1)) * Fp * sizeof(int32_t), 256);
     return b;
 }
@@ -294,11 +304,11 @@ ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, 
     T *R = cv.take<T>(static_cast<size_t>(c->E) * Fp);
     T *L = cv.take<T>(static_cast<size_t>(c->n) * Fp);
     T *Lch = cv.take<T>(static_cast<size_t>(c->n) * Fp);
-    int32_t *done = cv.take<int32_t>(Fp);
+    int32_t *done = cv.take<int32_t>(Fp + nchunk);  // per frame, then per chunk (flood_kernels.h)
     int32_t *unsat = cv.take<int32_t>(static_cast<size_t>(std::max(max_iter, 1)) * Fp);
 
     const int64_t unsat_words = es ? static_cast<int64_t>(max_iter) * Fp : 0;
-    const int init_blocks = static_cast<int>(std::min<int64_t>((Fp + unsat_words + 255) / 256, 4096));
+    const int init_blocks = static_cast<int>(std::min<int64_t>((Fp + nchunk + unsat_words + 255) / 256, 4096));
     {
         ProfScope ps(LDPC_KERNEL_OTHER, s);
         LDPC_LAUNCH(ps, k_frames_init, dim3(init_blocks), dim3(256), 0, s, Fp, done, unsat, unsat_words);

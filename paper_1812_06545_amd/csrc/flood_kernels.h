@@ -12,6 +12,16 @@ namespace flood {
 
 constexpr int kWaves = 4;  // wavefronts (rows or columns) per 256-thread block
 
+// Frame state with early stop: done[f] (f < frames padded to whole chunks)
+// is the iteration at which frame f stopped, -1 while it runs; done[Fp + c]
+// counts the frames of chunk c still running (written by the variable
+// kernel, or by the retire kernel of the layered schedule), so that work on
+// a chunk whose frames have all stopped is skipped with one wave-uniform load.
+__device__ __forceinline__ int32_t chunk_active(const int32_t *__restrict__ done, int32_t nchunk, int chunk)
+{
+    return done[nchunk * kChunk + chunk];
+}
+
 // Block -> (group of kWaves rows, frame chunk).  Workgroups are dispatched to
 // the 8 XCDs round-robin; when the chunk count allows it, XCD x gets chunks
 // x, x+8, ... and sweeps every row of one chunk before the next, so that the
@@ -197,9 +207,14 @@ __global__ __launch_bounds__(256) void k_check(const int32_t *__restrict__ row_p
     const int row = group * kWaves + wave;
     if (row >= m)
         return;
-    const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
-    if (ES && done[f] >= 0)
+    // A chunk whose frames have all stopped is skipped whole (one wave-uniform
+    // load).  Otherwise every lane is computed: a stopped frame's posterior is
+    // frozen (the variable kernel leaves it) and its messages are never read
+    // again, and computing its lane costs no extra traffic, since the chunk's
+    // 256-byte segments are read anyway.
+    if (ES && chunk_active(done, nchunk, chunk) == 0)
         return;
+    const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
     const uint32_t off = static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(T));
     const int32_t e0 = row_ptr[row];
     const int32_t d = __builtin_amdgcn_readfirstlane(row_ptr[row + 1] - e0);
@@ -266,22 +281,35 @@ __global__ __launch_bounds__(256) void k_variable(const int32_t *__restrict__ co
     const int col = group * kWaves + wave;
     if (col >= n)
         return;
+    if (ES && chunk_active(done, nchunk, chunk) == 0)
+        return;
     const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
-    if (ES) {
-        if (done[f] >= 0)
-            return;
-        if (unsat[f] == 0) {  // x^(t-1) is a codeword: the frame stops at t-1
-            done[f] = t_prev;
-            return;
-        }
-    }
     const uint32_t off = static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(T));
     const int32_t k0 = col_ptr[col];
     const int32_t dv = __builtin_amdgcn_readfirstlane(col_ptr[col + 1] - k0);
     const int64_t vo = (static_cast<int64_t>(chunk) * n + col) * kChunk;
     const T *Rc = R + static_cast<int64_t>(chunk) * E * kChunk;
     const T acc = ld_lane(Lch + vo, off);
-    st_lane(L + vo, off, column_sum_exact<A, 0>(dv, acc, col_edge + k0, Rc, off));
+    // the column's loads are issued before the frame's stop test, so that
+    // test's loads add no round trip in front of them
+    const T v = column_sum_exact<A, 0>(dv, acc, col_edge + k0, Rc, off);
+    if (ES) {
+        // A frame runs iteration t unless it stopped earlier or its decision
+        // x^(t-1) satisfies every row (it stops at t-1).  The column-0 wave of
+        // each chunk records the stops and the chunk's count of running frames.
+        const int32_t dn = done[f];
+        const bool running = dn < 0 && unsat[f] != 0;
+        if (col == 0) {
+            if (dn < 0 && !running)
+                done[f] = t_prev;
+            const uint64_t live = __ballot(running);
+            if (lane == 0)
+                done[nchunk * kChunk + chunk] = __popcll(live);
+        }
+        if (!running)
+            return;
+    }
+    st_lane(L + vo, off, v);
 }
 
 }  // namespace flood

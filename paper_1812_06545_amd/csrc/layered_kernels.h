@@ -150,6 +150,8 @@ __global__ __launch_bounds__(256) void k_layer(const int32_t *__restrict__ row_p
     if (slot >= rows)
         return;
     const int row = row0 + slot;
+    if (ES && flood::chunk_active(done, nchunk, chunk) == 0)
+        return;
     const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
     if (ES && done[f] >= 0)
         return;

@@ -140,9 +140,9 @@ __global__ __launch_bounds__(256) void k_check_ms(const int32_t *__restrict__ ro
     const int row = group * kWaves + wave;
     if (row >= m)
         return;
-    const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
-    if (ES && done[f] >= 0)
+    if (ES && flood::chunk_active(done, nchunk, chunk) == 0)  // as k_check: stopped chunks skipped, stopped lanes harmless
         return;
+    const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
     const uint32_t off = static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(T));
     const int32_t e0 = row_ptr[row];
     const int32_t d = __builtin_amdgcn_readfirstlane(row_ptr[row + 1] - e0);
@@ -173,8 +173,10 @@ __global__ __launch_bounds__(256) void k_layer_ms(const int32_t *__restrict__ ro
     if (slot >= rows)
         return;
     const int row = row0 + slot;
+    if (ES && flood::chunk_active(done, nchunk, chunk) == 0)
+        return;
     const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
-    if (ES && done[f] >= 0)
+    if (ES && done[f] >= 0)  // the layer updates L in place: a stopped frame is left untouched
         return;
     const uint32_t off = static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(T));
     const int32_t e0 = row_ptr[row];
