@@ -210,6 +210,8 @@ def main():
         roofline["valu"] = {"achieved": insts / (avg_ms * 1e-3) / 1e9, "peak": VALU_ISSUE_PEAK / 1e9,
                             "unit": "G wavefront instructions/s", "frac": insts / (avg_ms * 1e-3) / VALU_ISSUE_PEAK,
                             "insts_per_launch": insts, "profile": CHECK_VALU["profile"]}
+    # the whole step against its algorithmic floor (every frame runs T iterations)
+    roofline["step_floor"] = floor_frac(E, n, 4, F * T, ms_per_step)
     kernels = {k: {"ms_total": v[0], "launches": v[1]} for k, v in prof.items() if v[1]}
 
     other_path = None
@@ -264,6 +266,17 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def floor_frac(E, n, tsize, frame_iters, ms):
+    """Fraction of HBM peak that the whole step's algorithmic floor traffic
+    would need: per frame-iteration one stored message per edge read and
+    written once (2 tsize E) and one posterior per variable (tsize n),
+    summed over the iterations each frame actually ran, divided by the
+    measured time."""
+    floor_bytes = frame_iters * (2 * tsize * E + tsize * n)
+    gbs = floor_bytes / (ms * 1e-3) / 1e9
+    return {"floor_bytes": floor_bytes, "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+
 def _time_ms(fn, reps):
     import torch
     fn()
@@ -295,22 +308,27 @@ def batch_path_run(h, llrs, bits, iters, post, F, n, T, steps):
         k[0] += 1
     ms = _time_ms(step, steps)
     return {"entry": "ldpc_decode_batch (fused frame-resident persistent kernel)", "ms_per_step": ms,
-            "mbps": F * n / (ms * 1e-3) / 1e6}
+            "mbps": F * n / (ms * 1e-3) / 1e6, "step_floor": floor_frac(h.edges, n, 4, F * T, ms)}
 
 
 def extra_workloads():
     """The other seeded workloads, each timed with HIP events on the device:
     - gallager504 (FP64, 1000 frames, 20 iterations, early stop): plain and batch;
     - qc_mix (12 codes, 16384 frames, 10 iterations, early stop): one batched
-      launch vs twelve plain per-code launches (identical outputs);
-    - stair64800 (256 frames, 50 iterations, early stop): plain path."""
+      launch vs twelve plain per-code launches (identical outputs), the batch
+      with the default launch shape, after ldpc_autotune_batch, and replayed
+      from a HIP-graph plan;
+    - stair64800 (256 frames, 50 iterations, early stop): plain path and
+      ldpc_decode_batch (which takes the plain kernels for this code).
+    Each carries the whole step's algorithmic-floor fraction (floor_frac)
+    over the iterations its frames actually ran."""
     import torch
 
     import paper_1812_06545_amd as L
     from workloads import configs
     out = {}
 
-    def plain_and_batch(batches, dtype, reps):
+    def plain_and_batch(batches, dtype, reps, tune=False):
         hs = [L.Code.from_workload(b.code) for b in batches]
         jobs = [L.Job(hh, torch.from_numpy(b.llr).cuda(), b.max_iter, early_stop=b.early_stop)
                 for hh, b in zip(hs, batches)]
@@ -329,23 +347,35 @@ def extra_workloads():
                 raise RuntimeError("ldpc_decode_batch failed")
         bits = sum(b.llr.shape[0] * b.code.n for b in batches)
         tp, tb = _time_ms(plain, reps), _time_ms(batched, reps)
-        mean_it = float(sum(j.iters.float().sum().item() for j in jobs) / sum(b.llr.shape[0] for b in batches))
-        return {"plain_ms": tp, "plain_mbps": bits / (tp * 1e-3) / 1e6, "batch_ms": tb,
-                "batch_mbps": bits / (tb * 1e-3) / 1e6, "mean_iters": mean_it}
+        frames = sum(b.llr.shape[0] for b in batches)
+        frame_iters = [float(j.iters.float().sum().item()) for j in jobs]
+        mean_it = sum(frame_iters) / frames
+        tsize = 8 if dtype == torch.float64 else 4
+        # floor bytes summed over the jobs' codes
+        fb = sum(fi * (2 * tsize * b.code.edges + tsize * b.code.n) for fi, b in zip(frame_iters, batches))
+
+        def frac(ms):
+            return {"floor_bytes": fb, "achieved_gbs": fb / (ms * 1e-3) / 1e9,
+                    "frac": fb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        res = {"plain_ms": tp, "plain_mbps": bits / (tp * 1e-3) / 1e6, "batch_ms": tb,
+               "batch_mbps": bits / (tb * 1e-3) / 1e6, "mean_iters": mean_it,
+               "plain_floor": frac(tp), "batch_floor": frac(tb)}
+        if tune:
+            threads, _ = L.ldpc_autotune_batch(cj, dtype, bws, bw)
+            tt = _time_ms(batched, reps)
+            plan = L.Plan(jobs)
+            tg = _time_ms(plan.launch, reps)
+            plan.close()
+            res.update({"batch_tuned_ms": tt, "batch_tuned_mbps": bits / (tt * 1e-3) / 1e6,
+                        "tuned_threads": threads, "plan_replay_ms": tg, "plan_replay_mbps": bits / (tg * 1e-3) / 1e6,
+                        "batch_tuned_floor": frac(tt)})
+        return res
 
     out["gallager504_f64"] = plain_and_batch([configs.gallager504()], torch.float64, 5)
-    out["qc_mix_16384"] = plain_and_batch(configs.qc_mix(), torch.float32, 5)
-    st = configs.stair64800()
-    hs = L.Code.from_workload(st.code)
-    llr = torch.from_numpy(st.llr).cuda()
-    ws = torch.empty(L.ldpc_workspace_bytes(hs, torch.float32, 256, 50), dtype=torch.uint8, device="cuda")
-    res = {}
-
-    def run():
-        res["out"] = L.decode(hs, llr, 50, early_stop=True, workspace=ws)
-    ms = _time_ms(run, 3)
-    out["stair64800"] = {"plain_ms": ms, "plain_mbps": 256 * st.code.n / (ms * 1e-3) / 1e6,
-                         "mean_iters": float(res["out"][1].float().mean().item())}
+    out["qc_mix_16384"] = plain_and_batch(configs.qc_mix(), torch.float32, 5, tune=True)
+    st = plain_and_batch([configs.stair64800()], torch.float32, 3)
+    st["batch_entry"] = "ldpc_decode_batch routes this code to the plain kernels (too large for one workgroup's LDS)"
+    out["stair64800"] = st
     return out
 
 

@@ -371,19 +371,57 @@ void ldpc_server_destroy(ldpc_server server);
 ldpc_status ldpc_batch_set_threads(int32_t threads);
 
 /*
- * Autotuner of the batch path.  Decodes the given batch (its output buffers
- * are overwritten, inputs untouched) once per candidate workgroup size of
- * the fused kernel (64, 128, 192, 256, 384, 512), checks that every
- * candidate gives bit-identical outputs, times each (HIP events, 3 runs
- * after a warm-up) and
- * records the fastest for this batch shape (codes, frame counts rounded up
- * to a power of two, iteration caps, flags, dtype); later ldpc_decode_batch
- * calls of the same shape use it.  Blocks until done.  *best_threads and
- * *best_ms (may be NULL) receive the choice and its time.  LDPC_EDEVICE if
+ * Frames per workgroup of the fused kernel used by ldpc_decode_batch for FP32
+ * flooding sum-product jobs whose code fits two frames in one workgroup's LDS:
+ * 1 (default) or 2.  With 2, every thread runs its rows and columns for two
+ * frames of a job at once (Section III-A: frames decoded side by side),
+ * sharing the offsets and table reads of each edge slot; other jobs keep 1.
+ * Process-wide default (tuned shapes override it); affects speed only, never
+ * results.  EINVAL for other values.
+ */
+ldpc_status ldpc_batch_set_frames_per_group(int32_t frames);
+
+/*
+ * The launch configuration ldpc_decode_batch would use for these jobs: the
+ * tuned one if ldpc_autotune_batch (or ldpc_tuning_load) recorded this batch
+ * shape, else the process-wide defaults.  Any output may be NULL; *tuned is 1
+ * for a tuned shape.  Errors as ldpc_decode_batch's argument checks.
+ */
+ldpc_status ldpc_batch_launch_config(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, int32_t *threads,
+                                     int32_t *frames_per_group, int32_t *tuned);
+
+/*
+ * Autotuner of the batch path (Section III-A: the mapping of frames onto the
+ * GPU, chosen per batch shape).  Decodes the given batch (its output buffers
+ * are overwritten, inputs untouched) once per candidate launch
+ * configuration: workgroup sizes 64, 128, 192, 256, 384, 512 of the fused
+ * kernel, each with one frame per workgroup and, where some job can use it,
+ * two (ldpc_batch_set_frames_per_group); checks that every candidate gives
+ * bit-identical outputs, times each (HIP events, 3 runs after a warm-up) and
+ * records the fastest for this batch shape (device architecture, code shapes
+ * by sizes and degree profiles, frame counts rounded up to a power of two,
+ * iteration caps, flags, dtype); later ldpc_decode_batch calls of the same
+ * shape use it.  Blocks until done.  *best_threads and *best_ms (may be NULL)
+ * receive the choice's workgroup size and time (ldpc_batch_launch_config
+ * gives the whole choice).  The workspace must hold
+ * ldpc_batch_workspace_bytes (which covers every candidate).  LDPC_EDEVICE if
  * candidates disagree (then nothing is recorded).
  */
 ldpc_status ldpc_autotune_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, void *workspace,
                                 size_t workspace_bytes, void *stream, int32_t *best_threads, double *best_ms);
+
+/*
+ * The tuning table on disk (library bookkeeping of the autotuner above): save
+ * writes every recorded choice, one text line each ("<arch> <key> <threads>
+ * <frames per workgroup> <ms>", the key being the hash of the batch shape,
+ * device architecture included); load merges a saved table into the
+ * process's (*entries, may be NULL, receives the number of lines read), so a
+ * later process skips tuning for shapes already tuned on that architecture.
+ * EINVAL if the file cannot be opened or a line is malformed (load keeps the
+ * lines read before it).
+ */
+ldpc_status ldpc_tuning_save(const char *path);
+ldpc_status ldpc_tuning_load(const char *path, int32_t *entries);
 
 /*
  * Whether frames of `code` in `dtype` can run in the fused frame-resident

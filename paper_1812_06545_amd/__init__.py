@@ -92,6 +92,11 @@ _sig("ldpc_plan_create", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c
 _sig("ldpc_plan_launch", ctypes.c_int, [_P, _P])
 _sig("ldpc_plan_destroy", None, [_P])
 _sig("ldpc_batch_set_threads", ctypes.c_int, [_I32])
+_sig("ldpc_batch_set_frames_per_group", ctypes.c_int, [_I32])
+_sig("ldpc_batch_launch_config", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, ctypes.POINTER(_I32),
+                                                ctypes.POINTER(_I32), ctypes.POINTER(_I32)])
+_sig("ldpc_tuning_save", ctypes.c_int, [ctypes.c_char_p])
+_sig("ldpc_tuning_load", ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_I32)])
 _sig("ldpc_autotune_batch", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, _P, ctypes.c_size_t, _P,
                                            ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double)])
 _sig("ldpc_batch_fits_fused", ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)])
@@ -305,6 +310,30 @@ def autotune_batch(jobs, stream=None):
 
 def ldpc_batch_set_threads(threads: int) -> int:
     return _lib.ldpc_batch_set_threads(int(threads))
+
+
+def ldpc_batch_set_frames_per_group(frames: int) -> int:
+    return _lib.ldpc_batch_set_frames_per_group(int(frames))
+
+
+def ldpc_batch_launch_config(jobs, dtype):
+    """-> {"threads", "frames_per_group", "tuned"} that ldpc_decode_batch would use for these jobs."""
+    arr = _jobs_array(jobs)
+    t, f, tu = _I32(), _I32(), _I32()
+    _check(_lib.ldpc_batch_launch_config(arr, len(jobs), _dtype_code(dtype), ctypes.byref(t), ctypes.byref(f),
+                                         ctypes.byref(tu)), "ldpc_batch_launch_config")
+    return {"threads": t.value, "frames_per_group": f.value, "tuned": bool(tu.value)}
+
+
+def ldpc_tuning_save(path) -> int:
+    return _lib.ldpc_tuning_save(os.fsencode(path))
+
+
+def ldpc_tuning_load(path):
+    """-> (status, entries read)."""
+    n = _I32()
+    st = _lib.ldpc_tuning_load(os.fsencode(path), ctypes.byref(n))
+    return st, n.value
 
 
 def ldpc_batch_fits_fused(handle, dtype):

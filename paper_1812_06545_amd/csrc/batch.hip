@@ -8,6 +8,7 @@
 // written on the device by a tiny kernel that receives it by value.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -18,46 +19,89 @@
 namespace ldpc {
 namespace {
 
-std::mutex g_mu;
-int g_threads = 512;                 // workgroup size of the fused kernel (set by ldpc_batch_set_threads)
-std::map<uint64_t, int> g_tuned;     // batch shape key -> workgroup size chosen by ldpc_autotune_batch
+// Launch configuration of the fused kernel: workgroup size and frames per
+// workgroup (1, or 2 for FP32 flooding sum-product jobs).
+struct LaunchCfg {
+    int threads = 512;
+    int fpw = 1;
+};
 
-// Shape of a batch for the tuning table: a hash of the dtype and, per job,
-// the code's shape (sizes and degree histograms, not its address), frames
-// rounded up to a power of two, the iteration cap and the flags.  Computed
-// without allocating.
-uint64_t shape_key(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt)
+std::mutex g_mu;
+LaunchCfg g_cfg;                        // default (ldpc_batch_set_threads / ldpc_batch_set_frames_per_group)
+struct Tuned {
+    LaunchCfg cfg;
+    double ms = 0.0;
+};
+std::map<uint64_t, Tuned> g_tuned;      // batch shape key -> configuration chosen by ldpc_autotune_batch
+
+constexpr int kMaxArchDevices = 64;
+uint64_t g_arch_hash[kMaxArchDevices];  // per device: hash of its architecture name, 0 until looked up
+char g_arch_name[kMaxArchDevices][64];
+
+uint64_t fnv(uint64_t x, uint64_t v)
 {
-    uint64_t x = 1469598103934665603ull;
-    auto mix = [&x](uint64_t v) {
-        for (int b = 0; b < 8; ++b) {
-            x ^= (v >> (8 * b)) & 0xffu;
-            x *= 1099511628211ull;
-        }
-    };
-    mix(static_cast<uint64_t>(dt));
-    mix(static_cast<uint64_t>(njobs));
-    for (int32_t i = 0; i < njobs; ++i) {
-        uint64_t f = 1;
-        while (f < static_cast<uint64_t>(jobs[i].frames))
-            f <<= 1;
-        mix(jobs[i].code->shape_hash);
-        mix(f);
-        mix(static_cast<uint64_t>(jobs[i].max_iter));
-        mix(jobs[i].flags);
+    for (int b = 0; b < 8; ++b) {
+        x ^= (v >> (8 * b)) & 0xffu;
+        x *= 1099511628211ull;
     }
     return x;
 }
 
-int threads_for(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt)
+// The current device's architecture name (e.g. "gfx950:sramecc+:xnack-")
+// and its hash, looked up once per device.  Caller holds g_mu.
+const char *arch_of_current(uint64_t *hash)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxArchDevices) {
+        *hash = 1;
+        return "";
+    }
+    if (g_arch_hash[dev] == 0) {
+        hipDeviceProp_t prop;
+        uint64_t x = 1469598103934665603ull;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            std::snprintf(g_arch_name[dev], sizeof(g_arch_name[dev]), "%s", prop.gcnArchName);
+            for (const char *c = g_arch_name[dev]; *c; ++c)
+                x = fnv(x, static_cast<unsigned char>(*c));
+        }
+        g_arch_hash[dev] = x | 1;
+    }
+    *hash = g_arch_hash[dev];
+    return g_arch_name[dev];
+}
+
+// Shape of a batch for the tuning table: a hash of the device architecture,
+// the dtype and, per job, the code's shape (sizes and degree histograms, not
+// its address), frames rounded up to a power of two, the iteration cap and
+// the flags.  Computed without allocating.  Caller holds g_mu.
+uint64_t shape_key(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt)
+{
+    uint64_t arch = 0;
+    arch_of_current(&arch);
+    uint64_t x = fnv(1469598103934665603ull, arch);
+    x = fnv(x, static_cast<uint64_t>(dt));
+    x = fnv(x, static_cast<uint64_t>(njobs));
+    for (int32_t i = 0; i < njobs; ++i) {
+        uint64_t f = 1;
+        while (f < static_cast<uint64_t>(jobs[i].frames))
+            f <<= 1;
+        x = fnv(x, jobs[i].code->shape_hash);
+        x = fnv(x, f);
+        x = fnv(x, static_cast<uint64_t>(jobs[i].max_iter));
+        x = fnv(x, jobs[i].flags);
+    }
+    return x;
+}
+
+LaunchCfg cfg_for(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_tuned.empty()) {
         auto it = g_tuned.find(shape_key(jobs, njobs, dt));
         if (it != g_tuned.end())
-            return it->second;
+            return it->second.cfg;
     }
-    return g_threads;
+    return g_cfg;
 }
 
 size_t lds_limit()
@@ -108,6 +152,7 @@ FusedFit fused_fit(const ldpc_code_s *c, ldpc_dtype dt, size_t limit)
 // One fused launch: up to kMaxJobs jobs over up to kMaxCodes codes (fixed
 // storage, so planning needs no heap).
 struct Group {
+    int fpw = 1;  // frames per workgroup of this launch
     int32_t njobs = 0, ncodes = 0;
     int32_t jobs[fused::kMaxJobs];
     const ldpc_code_s *codes[fused::kMaxCodes];
@@ -116,7 +161,7 @@ struct Group {
     int64_t emax = 0;
     int32_t nmax = 0, words = 0, nblocks = 0, mb = 0;
     size_t tsize = 4;
-    size_t lds() const { return fused::frame_lds_bytes(emax, nmax, words, nblocks, mb, tsize); }
+    size_t lds() const { return fused::frame_lds_bytes(emax, nmax, words, nblocks, mb, tsize, fpw); }
     int code_index(const ldpc_code_s *c) const
     {
         for (int32_t k = 0; k < ncodes; ++k)
@@ -139,12 +184,27 @@ struct Group {
 constexpr int kPlanNotFused = -1;  // a job's code does not fit the fused kernel and no plain list was given
 constexpr int kPlanTooMany = -2;   // more than max_groups launch groups would be needed
 
+// Frames per workgroup a job runs with when fpw_pref frames are preferred:
+// 2 only for FP32 flooding sum-product jobs whose code fits two frames in
+// one workgroup's LDS.
+int job_fpw(const ldpc_job &j, ldpc_dtype dt, int fpw_pref, size_t limit)
+{
+    if (fpw_pref != 2 || dt != LDPC_F32 || (j.flags & (LDPC_LAYERED | LDPC_MIN_SUM)) != 0)
+        return 1;
+    const ldpc_code_s *c = j.code;
+    const bool qc = fused_qc_view(c, sizeof(float));
+    const size_t two = fused::frame_lds_bytes(c->E, c->n, qc ? c->qc_words : 0, qc ? c->nblocks : 0,
+                                              qc ? c->mb : 0, sizeof(float), 2);
+    return two <= limit ? 2 : 1;
+}
+
 // Greedy packing of the fusable jobs, in order, into launch groups (at most
-// max_groups).  Jobs whose code does not fit go to plain[] (*nplain of them),
-// or, with plain == nullptr, make the plan fail.  Returns the group count or
-// kPlanNotFused / kPlanTooMany.
-int plan(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, Group *groups, int max_groups, int32_t *plain,
-         int32_t *nplain)
+// max_groups); consecutive jobs share a group while they run with the same
+// frames per workgroup (job_fpw of fpw_pref).  Jobs whose code does not fit
+// go to plain[] (*nplain of them), or, with plain == nullptr, make the plan
+// fail.  Returns the group count or kPlanNotFused / kPlanTooMany.
+int plan(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, int fpw_pref, Group *groups, int max_groups,
+         int32_t *plain, int32_t *nplain)
 {
     const size_t limit = lds_limit();
     const size_t tsize = dt == LDPC_F64 ? sizeof(double) : sizeof(float);
@@ -161,7 +221,8 @@ int plan(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, Group *groups, int 
             plain[(*nplain)++] = i;
             continue;
         }
-        bool need_new = ng == 0 || groups[ng - 1].njobs == fused::kMaxJobs;
+        const int fpw = job_fpw(jobs[i], dt, fpw_pref, limit);
+        bool need_new = ng == 0 || groups[ng - 1].njobs == fused::kMaxJobs || groups[ng - 1].fpw != fpw;
         if (!need_new && groups[ng - 1].code_index(jobs[i].code) < 0) {
             Group trial = groups[ng - 1];
             trial.add_code(jobs[i].code);
@@ -172,6 +233,7 @@ int plan(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, Group *groups, int 
                 return kPlanTooMany;
             groups[ng++] = Group{};
             groups[ng - 1].tsize = tsize;
+            groups[ng - 1].fpw = fpw;
         }
         Group &g = groups[ng - 1];
         g.jobs[g.njobs++] = i;
@@ -275,6 +337,7 @@ ldpc_status launch_group(const ldpc_job *jobs, const Group &g, char *ws, int thr
         nblocks_max = std::max(nblocks_max, b.codes[k].nblocks);
     }
     int64_t items = 0;
+    const int fpw = g.fpw;
     for (int32_t k = 0; k < g.njobs; ++k) {
         const ldpc_job &j = jobs[g.jobs[k]];
         fused::Job &e = b.jobs[k];
@@ -289,11 +352,11 @@ ldpc_status launch_group(const ldpc_job *jobs, const Group &g, char *ws, int thr
         e.bits = j.bits;
         e.iters = j.iters;
         e.post = j.posterior;
-        items += j.frames;
+        items += (j.frames + fpw - 1) / fpw;  // one item per frame, or per pair of frames
     }
     b.nitems = items;
     const size_t lds = fused::frame_lds_bytes(b.emax, b.nmax, b.words_max, nblocks_max, b.mb_max,
-                                              sizeof(typename A::T));
+                                              sizeof(typename A::T), fpw);
     auto *d_batch = reinterpret_cast<fused::Batch *>(ws);
     auto *counter = reinterpret_cast<unsigned long long *>(ws + kGroupBytes - 256);
     {
@@ -301,13 +364,13 @@ ldpc_status launch_group(const ldpc_job *jobs, const Group &g, char *ws, int thr
         LDPC_LAUNCH(ps, k_store_batch, dim3(1), dim3(256), 0, s, b, d_batch, counter);
     }
     switch (g.bucket) {
-    case 8: return launch_fused_bucket<A, 8>(b, d_batch, counter, lds, threads, s, profile);
-    case 16: return launch_fused_bucket<A, 16>(b, d_batch, counter, lds, threads, s, profile);
+    case 8: return launch_fused_bucket<A, 8>(b, d_batch, counter, lds, threads, fpw, s, profile);
+    case 16: return launch_fused_bucket<A, 16>(b, d_batch, counter, lds, threads, fpw, s, profile);
     case 24:
         if constexpr (std::is_same<A, ArithF32>::value)
-            return launch_fused_bucket<A, 24>(b, d_batch, counter, lds, threads, s, profile);
-        return launch_fused_bucket<A, 32>(b, d_batch, counter, lds, threads, s, profile);
-    default: return launch_fused_bucket<A, 32>(b, d_batch, counter, lds, threads, s, profile);
+            return launch_fused_bucket<A, 24>(b, d_batch, counter, lds, threads, fpw, s, profile);
+        return launch_fused_bucket<A, 32>(b, d_batch, counter, lds, threads, fpw, s, profile);
+    default: return launch_fused_bucket<A, 32>(b, d_batch, counter, lds, threads, fpw, s, profile);
     }
 }
 
@@ -366,13 +429,27 @@ struct FullPlan {
     std::vector<int32_t> plain;
     int ngroups = 0;
     int32_t nplain = 0;
-    void make(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype)
+    void make(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, int fpw)
     {
         groups.resize(std::max(njobs, 1));
         plain.resize(std::max(njobs, 1));
-        ngroups = plan(jobs, njobs, dtype, groups.data(), static_cast<int>(groups.size()), plain.data(), &nplain);
+        ngroups = plan(jobs, njobs, dtype, fpw, groups.data(), static_cast<int>(groups.size()), plain.data(),
+                       &nplain);
     }
 };
+
+// Workspace of a batch under either frames-per-workgroup choice (the
+// autotuner tries both in the caller's workspace).
+size_t batch_bytes_any(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype)
+{
+    size_t need = 0;
+    for (int fpw : {1, 2}) {
+        FullPlan p;
+        p.make(jobs, njobs, dtype, fpw);
+        need = std::max(need, batch_bytes(jobs, p.ngroups, p.plain.data(), p.nplain, dtype));
+    }
+    return need;
+}
 
 }  // namespace
 
@@ -384,9 +461,7 @@ try {
     const ldpc_status st = validate_jobs(jobs, njobs, dtype);
     if (st != LDPC_OK)
         return st;
-    FullPlan p;
-    p.make(jobs, njobs, dtype);
-    *bytes = batch_bytes(jobs, p.ngroups, p.plain.data(), p.nplain, dtype);
+    *bytes = batch_bytes_any(jobs, njobs, dtype);
     return LDPC_OK;
 } catch (...) {
     return ldpc::status_of_exception();
@@ -398,20 +473,20 @@ try {
     const ldpc_status st = validate_jobs(jobs, njobs, dtype);
     if (st != LDPC_OK)
         return st;
+    const LaunchCfg cfg = cfg_for(jobs, njobs, dtype);
     FullPlan p;
-    p.make(jobs, njobs, dtype);
+    p.make(jobs, njobs, dtype, cfg.fpw);
     const size_t need = batch_bytes(jobs, p.ngroups, p.plain.data(), p.nplain, dtype);
     if (need == 0)
         return LDPC_OK;
     if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return LDPC_EINVAL;
-    const int threads = threads_for(jobs, njobs, dtype);
     const hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
     for (int gi = 0; gi < p.ngroups; ++gi) {
         const Group &g = p.groups[gi];
-        const ldpc_status r = dtype == LDPC_F64 ? launch_group<ArithF64>(jobs, g, ws, threads, s, true)
-                                                : launch_group<ArithF32>(jobs, g, ws, threads, s, true);
+        const ldpc_status r = dtype == LDPC_F64 ? launch_group<ArithF64>(jobs, g, ws, cfg.threads, s, true)
+                                                : launch_group<ArithF32>(jobs, g, ws, cfg.threads, s, true);
         if (r != LDPC_OK)
             return r;
         ws += kGroupBytes;
@@ -434,8 +509,9 @@ try {
     const ldpc_status st = validate_jobs(jobs, njobs, dtype);
     if (st != LDPC_OK)
         return st;
+    const LaunchCfg cfg = cfg_for(jobs, njobs, dtype);
     Group groups[LDPC_NOALLOC_MAX_GROUPS];
-    const int ng = plan(jobs, njobs, dtype, groups, LDPC_NOALLOC_MAX_GROUPS, nullptr, nullptr);
+    const int ng = plan(jobs, njobs, dtype, cfg.fpw, groups, LDPC_NOALLOC_MAX_GROUPS, nullptr, nullptr);
     if (ng < 0)
         return LDPC_EUNSUPPORTED;  // a code too large for the fused kernel, or more groups than the scratch holds
     if (ng == 0)
@@ -444,11 +520,10 @@ try {
     const ldpc_status sc = noalloc_scratch(&ws);
     if (sc != LDPC_OK)
         return sc;
-    const int threads = threads_for(jobs, njobs, dtype);
     const hipStream_t s = static_cast<hipStream_t>(stream);
     for (int gi = 0; gi < ng; ++gi) {
-        const ldpc_status r = dtype == LDPC_F64 ? launch_group<ArithF64>(jobs, groups[gi], ws, threads, s, false)
-                                                : launch_group<ArithF32>(jobs, groups[gi], ws, threads, s, false);
+        const ldpc_status r = dtype == LDPC_F64 ? launch_group<ArithF64>(jobs, groups[gi], ws, cfg.threads, s, false)
+                                                : launch_group<ArithF32>(jobs, groups[gi], ws, cfg.threads, s, false);
         if (r != LDPC_OK)
             return r;
         ws += kGroupBytes;
@@ -463,8 +538,99 @@ try {
     if (threads < 64 || threads > 512 || threads % 64 != 0)
         return LDPC_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_threads = threads;
+    g_cfg.threads = threads;
     return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
+}
+
+extern "C" ldpc_status ldpc_batch_set_frames_per_group(int32_t frames)
+try {
+    if (frames != 1 && frames != 2)
+        return LDPC_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cfg.fpw = frames;
+    return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
+}
+
+extern "C" ldpc_status ldpc_batch_launch_config(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype,
+                                                int32_t *threads, int32_t *frames_per_group, int32_t *tuned)
+try {
+    const ldpc_status st = validate_jobs(jobs, njobs, dtype);
+    if (st != LDPC_OK)
+        return st;
+    std::lock_guard<std::mutex> lk(g_mu);
+    LaunchCfg cfg = g_cfg;
+    auto it = g_tuned.find(shape_key(jobs, njobs, dtype));
+    if (it != g_tuned.end())
+        cfg = it->second.cfg;
+    if (threads)
+        *threads = cfg.threads;
+    if (frames_per_group)
+        *frames_per_group = cfg.fpw;
+    if (tuned)
+        *tuned = it != g_tuned.end();
+    return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
+}
+
+// Tuning file: one line per entry, "<arch> <key> <threads> <frames per
+// workgroup> <ms>", key in hex.  Entries of another architecture keep their
+// line but, their key including the architecture, never match here.
+extern "C" ldpc_status ldpc_tuning_save(const char *path)
+try {
+    if (!path)
+        return LDPC_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint64_t arch = 0;
+    const char *name = arch_of_current(&arch);
+    FILE *f = std::fopen(path, "w");
+    if (!f)
+        return LDPC_EINVAL;
+    for (const auto &e : g_tuned)
+        std::fprintf(f, "%s %016llx %d %d %.6f\n", name[0] ? name : "unknown",
+                     static_cast<unsigned long long>(e.first), e.second.cfg.threads, e.second.cfg.fpw, e.second.ms);
+    return std::fclose(f) == 0 ? LDPC_OK : LDPC_EINVAL;
+} catch (...) {
+    return ldpc::status_of_exception();
+}
+
+extern "C" ldpc_status ldpc_tuning_load(const char *path, int32_t *entries)
+try {
+    if (!path)
+        return LDPC_EINVAL;
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return LDPC_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    char arch[128];
+    unsigned long long key = 0;
+    int threads = 0, fpw = 0;
+    double ms = 0.0;
+    int32_t count = 0;
+    ldpc_status rc = LDPC_OK;
+    for (;;) {
+        const int got = std::fscanf(f, "%127s %llx %d %d %lf", arch, &key, &threads, &fpw, &ms);
+        if (got == EOF)
+            break;
+        if (got != 5 || threads < 64 || threads > 512 || threads % 64 != 0 || (fpw != 1 && fpw != 2)) {
+            rc = LDPC_EINVAL;  // malformed: the entries read so far are kept
+            break;
+        }
+        Tuned t;
+        t.cfg.threads = threads;
+        t.cfg.fpw = fpw;
+        t.ms = ms;
+        g_tuned[static_cast<uint64_t>(key)] = t;
+        ++count;
+    }
+    std::fclose(f);
+    if (entries)
+        *entries = count;
+    return rc;
 } catch (...) {
     return ldpc::status_of_exception();
 }
@@ -516,58 +682,76 @@ try {
     if (st != LDPC_OK)
         return st;
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    static const int kCandidates[] = {64, 128, 192, 256, 384, 512};
-    const uint64_t key = shape_key(jobs, njobs, dtype);
+    static const int kThreads[] = {64, 128, 192, 256, 384, 512};
+    uint64_t key = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        key = shape_key(jobs, njobs, dtype);
+    }
+    // frames per workgroup: 2 only where some job would run with it
+    int fpw_max = 1;
+    const size_t limit = lds_limit();
+    for (int32_t i = 0; i < njobs; ++i)
+        if (jobs[i].frames > 0 && fused_fit(jobs[i].code, dtype, limit).ok && job_fpw(jobs[i], dtype, 2, limit) == 2)
+            fpw_max = 2;
     std::vector<char> ref, cur;
-    int best = 0;
+    LaunchCfg best;
     double best_t = 0.0;
+    bool have = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return LDPC_EDEVICE;
     ldpc_status rc = LDPC_OK;
-    for (int threads : kCandidates) {
-        {
-            std::lock_guard<std::mutex> lk(g_mu);
-            g_tuned[key] = threads;
-        }
-        rc = ldpc_decode_batch(jobs, njobs, dtype, workspace, workspace_bytes, stream);  // warm-up
-        if (rc != LDPC_OK)
-            break;
-        rc = snapshot(jobs, njobs, dtype, s, cur);
-        if (rc != LDPC_OK)
-            break;
-        if (ref.empty())
-            ref = cur;
-        else if (ref.size() != cur.size() || std::memcmp(ref.data(), cur.data(), ref.size()) != 0) {
-            rc = LDPC_EDEVICE;  // a schedule changed the results: never expected, refuse to tune
-            break;
-        }
-        constexpr int kReps = 3;
-        (void)hipEventRecord(e0, s);
-        for (int r = 0; r < kReps && rc == LDPC_OK; ++r)
-            rc = ldpc_decode_batch(jobs, njobs, dtype, workspace, workspace_bytes, stream);
-        (void)hipEventRecord(e1, s);
-        float ms = 0.f;
-        if (rc != LDPC_OK || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            rc = rc == LDPC_OK ? LDPC_EDEVICE : rc;
-            break;
-        }
-        const double t = ms / kReps;
-        if (best == 0 || t < best_t) {
-            best = threads;
-            best_t = t;
+    for (int fpw = 1; fpw <= fpw_max && rc == LDPC_OK; ++fpw) {
+        for (int threads : kThreads) {
+            LaunchCfg cand;
+            cand.threads = threads;
+            cand.fpw = fpw;
+            {
+                std::lock_guard<std::mutex> lk(g_mu);
+                g_tuned[key] = Tuned{cand, 0.0};
+            }
+            rc = ldpc_decode_batch(jobs, njobs, dtype, workspace, workspace_bytes, stream);  // warm-up
+            if (rc != LDPC_OK)
+                break;
+            rc = snapshot(jobs, njobs, dtype, s, cur);
+            if (rc != LDPC_OK)
+                break;
+            if (ref.empty())
+                ref = cur;
+            else if (ref.size() != cur.size() || std::memcmp(ref.data(), cur.data(), ref.size()) != 0) {
+                rc = LDPC_EDEVICE;  // a launch shape changed the results: never expected, refuse to tune
+                break;
+            }
+            constexpr int kReps = 3;
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < kReps && rc == LDPC_OK; ++r)
+                rc = ldpc_decode_batch(jobs, njobs, dtype, workspace, workspace_bytes, stream);
+            (void)hipEventRecord(e1, s);
+            float ms = 0.f;
+            if (rc != LDPC_OK || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = rc == LDPC_OK ? LDPC_EDEVICE : rc;
+                break;
+            }
+            const double t = ms / kReps;
+            if (!have || t < best_t) {
+                best = cand;
+                best_t = t;
+                have = true;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     std::lock_guard<std::mutex> lk(g_mu);
-    if (rc != LDPC_OK || best == 0) {
+    if (rc != LDPC_OK || !have) {
         g_tuned.erase(key);
         return rc != LDPC_OK ? rc : LDPC_EDEVICE;
     }
-    g_tuned[key] = best;
+    g_tuned[key] = Tuned{best, best_t};
     if (best_threads)
-        *best_threads = best;
+        *best_threads = best.threads;
     if (best_ms)
         *best_ms = best_t;
     return LDPC_OK;

@@ -91,31 +91,34 @@ constexpr int kColSpare = 16;
 
 __host__ __device__ inline uint32_t align16(size_t x) { return static_cast<uint32_t>((x + 15) / 16 * 16); }
 
-// Byte layout of one frame in LDS, for the launch's largest n and E:
+// Byte layout of a workgroup's LDS for `frames` frames (1, or 2 for the
+// pair kernel) of the launch's largest n and E.  Frame k's region starts at
+// k * span; inside it (offsets from its start):
 //   [0, n)              posteriors L (message-sized words)
 //   n                   +inf: dummy edges read their posterior there
 //   n + 1 + t           dummy slot of thread t
 //   r0 ..               messages r, one word per edge
-//   t0 ..               the code's tables (int32 words)
+// and the code's tables (int32 words) follow the last frame, at t0.
 struct FrameLayout {
-    uint32_t r0, t0;
+    uint32_t r0, span, t0;
     size_t bytes;
 };
 __host__ __device__ inline FrameLayout frame_layout(int64_t E, int32_t n, int32_t words, int32_t nblocks, int32_t mb,
-                                                    size_t tsize)
+                                                    size_t tsize, int frames = 1)
 {
     FrameLayout f;
     f.r0 = align16((static_cast<size_t>(n) + 1 + kDummySlots) * tsize);
-    f.t0 = align16(f.r0 + static_cast<size_t>(E) * tsize);
+    f.span = align16(f.r0 + static_cast<size_t>(E) * tsize);
+    f.t0 = f.span * static_cast<uint32_t>(frames);
     f.bytes = f.t0 + static_cast<size_t>(words + 2 * nblocks + mb + kColSpare) * sizeof(int32_t);
     return f;
 }
 
-// LDS bytes a workgroup needs for one frame of this code.
+// LDS bytes a workgroup needs for `frames` frames of this code.
 __host__ __device__ inline size_t frame_lds_bytes(int64_t E, int32_t n, int32_t words, int32_t nblocks, int32_t mb,
-                                                  size_t tsize)
+                                                  size_t tsize, int frames = 1)
 {
-    return frame_layout(E, n, words, nblocks, mb, tsize).bytes;
+    return frame_layout(E, n, words, nblocks, mb, tsize, frames).bytes;
 }
 
 // Loads and stores of LDS words by byte offset from the frame's base.
@@ -264,21 +267,16 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int dh, unsigned 
     const uint32_t sign_total = sign ^ pair_swap(sign);
     parity |= par ^ pair_swap(par);  // a lane may hold several rows: any unsatisfied row counts
     typename A::Acc sx = A::seed(s_other);
-    // The parked value is read for dummies too (their slot is valid; the
-    // value, possibly a later dummy's message, is replaced), which spares an
-    // exec-mask branch per slot.  FP32 bodies are held to 128 VGPRs, and the
-    // long ones (D > 8) spill when they do, so there the load stays guarded.
-    constexpr bool kGuardParked = std::is_same<A, ArithF32>::value && D > 8;
+    // Every parked value is read before the first message is stored: a
+    // dummy's slot then still holds the parked dummy term (kDummyParked,
+    // written by the forward pass), which needs no per-slot select.
+    T pv[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+        pv[j] = lds_ld<T>(s, ri[j]);
 #pragma unroll
     for (int j = D - 1; j >= 0; --j) {
-        const bool real = j < dh;
-        T parked;
-        if constexpr (kGuardParked) {
-            parked = real ? lds_ld<T>(s, ri[j]) : T(A::kDummyParked);
-        } else {
-            const T v = lds_ld<T>(s, ri[j]);
-            parked = real ? v : T(A::kDummyParked);
-        }
+        const T parked = pv[j];
         const typename A::Term a_k = A::unpark(parked, kp[j]);
         const T r = check_backward<A>(a_k, p[j], sx, sign_total);
         lds_st<T>(s, ri[j], r);
@@ -718,6 +716,320 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
         job.iters[f] = it;
 }
 
+// The code's tables in LDS (see decode_frame): the raw QC tables, then the
+// row view (pack words), the block-row order, the column view (message
+// offsets from a frame's base) and the spare zero words.  Ends with a
+// workgroup barrier.
+template <uint32_t TS>
+__device__ __forceinline__ void load_tables(const Code &c, int32_t *__restrict__ sTab, uint32_t r0)
+{
+    for (int w = threadIdx.x; w < c.words; w += blockDim.x)
+        sTab[w] = c.tab[w];
+    if (c.qc) {
+        const uint32_t Z = static_cast<uint32_t>(c.Z);
+        const int32_t *bcol = c.tab + (c.mb + 1);
+        const int32_t *bsh = bcol + c.nblocks;
+        for (int w = threadIdx.x; w < c.nblocks; w += blockDim.x)
+            sTab[c.words + w] = static_cast<int32_t>((TS * static_cast<uint32_t>(bcol[w]) * Z) |
+                                                     ((TS * static_cast<uint32_t>(bsh[w])) << 16));
+        for (int w = threadIdx.x; w < c.mb; w += blockDim.x)
+            sTab[c.words + c.nblocks + w] = c.brow_order[w];
+        // the column phase's view: block-column slot w holds block cb[w]
+        const int32_t *cb = bsh + c.nblocks + (c.nb + 1);
+        for (int w = threadIdx.x; w < c.nblocks; w += blockDim.x)
+            sTab[c.words + c.nblocks + c.mb + w] = static_cast<int32_t>(r0 + TS * Z * static_cast<uint32_t>(cb[w]));
+        if (threadIdx.x < kColSpare)  // readable words past the column table's end
+            sTab[c.words + 2 * c.nblocks + c.mb + threadIdx.x] = 0;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Two frames per workgroup (flooding, sum-product): every lane runs its half
+// rows and columns for two frames of one job at once, so the offsets, table
+// reads, dummy handling and loop bookkeeping of a slot serve both frames.
+// Each frame's arithmetic, in its own LDS region, is exactly the one-frame
+// kernel's (and so the plain path's), bit for bit.
+
+// fused_half_row for frames at s0 and s1 (see there).
+template <class A, int D, class Row>
+__device__ __forceinline__ void fused_half_row2(const Row &row, int dh, unsigned char *__restrict__ s0,
+                                                unsigned char *__restrict__ s1, Slots sl, uint32_t &parity0,
+                                                uint32_t &parity1)
+{
+    using T = typename A::T;
+    typename A::Acc p0[D], p1[D];
+    typename A::Keep kp0[D], kp1[D];
+    typename A::Acc acc0 = A::identity(), acc1 = A::identity();
+    uint32_t sign0 = 0, sign1 = 0, par0 = 0, par1 = 0;
+    uint32_t ri[D], ci[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+        slot_offsets(row, j, j < dh, sl.dslot, sl.inf_off, ri[j], ci[j]);
+    T lv0[D], rv0[D], lv1[D], rv1[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        lv0[j] = lds_ld<T>(s0, ci[j]);
+        rv0[j] = lds_ld<T>(s0, ri[j]);
+        lv1[j] = lds_ld<T>(s1, ci[j]);
+        rv1[j] = lds_ld<T>(s1, ri[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        par0 ^= static_cast<uint32_t>(lv0[j] < T(0));
+        par1 ^= static_cast<uint32_t>(lv1[j] < T(0));
+        typename A::Term a0, a1;
+        check_forward<A>(lv0[j] - rv0[j], a0, p0[j], acc0, sign0);
+        check_forward<A>(lv1[j] - rv1[j], a1, p1[j], acc1, sign1);
+        kp0[j] = A::keep(a0);
+        kp1[j] = A::keep(a1);
+        lds_st<T>(s0, ri[j], A::park(a0));
+        lds_st<T>(s1, ri[j], A::park(a1));
+    }
+    const typename A::Acc o0 = pair_swap(acc0), o1 = pair_swap(acc1);
+    const uint32_t st0 = sign0 ^ pair_swap(sign0), st1 = sign1 ^ pair_swap(sign1);
+    parity0 |= par0 ^ pair_swap(par0);
+    parity1 |= par1 ^ pair_swap(par1);
+    typename A::Acc x0 = A::seed(o0), x1 = A::seed(o1);
+    // Every parked value is read before the first message is stored: a
+    // dummy's slot then still holds the parked dummy term (kDummyParked,
+    // written by the forward pass), which needs no per-slot select.
+    T v0[D], v1[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        v0[j] = lds_ld<T>(s0, ri[j]);
+        v1[j] = lds_ld<T>(s1, ri[j]);
+    }
+#pragma unroll
+    for (int j = D - 1; j >= 0; --j) {
+        const typename A::Term a0 = A::unpark(v0[j], kp0[j]);
+        const typename A::Term a1 = A::unpark(v1[j], kp1[j]);
+        const T r0 = check_backward<A>(a0, p0[j], x0, st0);
+        const T r1 = check_backward<A>(a1, p1[j], x1, st1);
+        lds_st<T>(s0, ri[j], r0);
+        lds_st<T>(s1, ri[j], r1);
+    }
+}
+
+template <class A, int D, int DB, class Row>
+__device__ __forceinline__ void fused_row_dispatch2(int hwave, const Row &row, int dh, unsigned char *__restrict__ s0,
+                                                    unsigned char *__restrict__ s1, Slots sl, uint32_t &parity0,
+                                                    uint32_t &parity1)
+{
+    constexpr bool exact = std::is_same<Row, RowQC>::value;
+    if constexpr (!exact) {
+        fused_half_row2<A, DB>(row, dh, s0, s1, sl, parity0, parity1);
+    } else if constexpr (D < DB) {
+        if (hwave == D)
+            fused_half_row2<A, D>(row, dh, s0, s1, sl, parity0, parity1);
+        else
+            fused_row_dispatch2<A, D + 1, DB>(hwave, row, dh, s0, s1, sl, parity0, parity1);
+    } else {
+        fused_half_row2<A, DB>(row, dh, s0, s1, sl, parity0, parity1);
+    }
+}
+
+// fused_col for frames at s0 and s1.
+template <class A, int D, bool SAFE0, class Edge>
+__device__ __forceinline__ void fused_col2(const Edge &edge, int dv, typename A::T &acc0, typename A::T &acc1,
+                                           const unsigned char *__restrict__ s0, const unsigned char *__restrict__ s1)
+{
+    using T = typename A::T;
+    static_assert(!SAFE0 || D <= kColSpare, "column body longer than the spare words cover");
+    T rv0[D > 0 ? D : 1], rv1[D > 0 ? D : 1];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const uint32_t o = SAFE0 ? edge(k) : (k < dv ? edge(k) : 0u);
+        rv0[k] = lds_ld<T>(s0, o);
+        rv1[k] = lds_ld<T>(s1, o);
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        acc0 = k < dv ? acc0 + rv0[k] : acc0;
+        acc1 = k < dv ? acc1 + rv1[k] : acc1;
+    }
+}
+
+template <class A, int D, bool SAFE0, class Edge>
+__device__ __forceinline__ void fused_col_dispatch2(int dwave, const Edge &edge, int dv, typename A::T &acc0,
+                                                    typename A::T &acc1, const unsigned char *__restrict__ s0,
+                                                    const unsigned char *__restrict__ s1)
+{
+    using T = typename A::T;
+    if constexpr (SAFE0 && D <= kColSpare) {
+        if (dwave == D)
+            return fused_col2<A, D, SAFE0>(edge, dv, acc0, acc1, s0, s1);
+        return fused_col_dispatch2<A, D + 1, SAFE0>(dwave, edge, dv, acc0, acc1, s0, s1);
+    } else {
+        for (int k = 0; k < dv; ++k) {
+            const uint32_t o = edge(k);
+            acc0 += lds_ld<T>(s0, o);
+            acc1 += lds_ld<T>(s1, o);
+        }
+    }
+}
+
+// Frames f0 and f0 + 1 of a flooding sum-product job (with has1 false only
+// frame f0: the second region then decodes a copy of it, whose results are
+// not written).  Early stop is per frame: a frame whose decision is a
+// codeword keeps its posteriors from then on (its column updates are
+// skipped) and leaves the loop's work to the other frame.
+template <class A, int DB>
+__device__ __forceinline__ void decode_frame_pair(const Code &c, const Job &job, int64_t f0, bool has1,
+                                                  const FrameView &fv0, const FrameView &fv1)
+{
+    using T = typename A::T;
+    constexpr uint32_t TS = sizeof(T);
+    const int tid = static_cast<int>(threadIdx.x), NT = static_cast<int>(blockDim.x);
+    const int32_t m = c.m, n = c.n, Z = c.Z;
+    const T *llr0 = static_cast<const T *>(job.llr) + f0 * n;
+    const T *llr1 = has1 ? llr0 + n : llr0;
+    unsigned char *s0 = fv0.s, *s1 = fv1.s;
+    T *sL0 = reinterpret_cast<T *>(s0), *sL1 = reinterpret_cast<T *>(s1);
+    const int32_t *rbs = fv0.tab;
+    const int32_t *cbs = fv0.tab + (c.mb + 1) + 2 * c.nblocks;
+    const uint32_t *pack = reinterpret_cast<const uint32_t *>(fv0.tab + c.words);
+    const int32_t *border = fv0.tab + c.words + c.nblocks;
+    const uint32_t *cpack = reinterpret_cast<const uint32_t *>(border + c.mb);
+    const uint32_t z_t = TS * static_cast<uint32_t>(Z);
+
+    for (int j = tid; j < n; j += NT) {
+        sL0[j] = llr0[j] * T(A::kIn);
+        sL1[j] = llr1[j] * T(A::kIn);
+    }
+    start_messages<T>(c, fv0);
+    start_messages<T>(c, fv1);
+    __syncthreads();
+
+    const bool es = (job.flags & LDPC_EARLY_STOP) != 0;
+    int32_t it0 = job.max_iter, it1 = job.max_iter;
+    bool run0 = true, run1 = true;
+    for (int32_t t = 1; t <= job.max_iter; ++t) {
+        uint32_t parity0 = 0, parity1 = 0;
+        const int lane = tid & 63, half = lane >> 5;
+        for (int rb = (tid >> 6) * 32; rb < m; rb += (NT >> 6) * 32) {
+            const int dwave = c.row_gmax[__builtin_amdgcn_readfirstlane(rb) >> 5];
+            const int sr = rb + (lane & 31);
+            if (dwave == 0 || sr >= m)
+                continue;
+            const int hwave = (dwave + 1) >> 1;
+            if (c.qc) {
+                const int32_t si = div_z(sr, c.zmagic);
+                const int32_t r = sr - si * Z;
+                const int32_t i = border[si];
+                const int32_t b0 = rbs[i], d = rbs[i + 1] - b0, h = (d + 1) >> 1;
+                const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
+                const RowQC row{TS * static_cast<uint32_t>(r), z_t, fv0.r0 + z_t * static_cast<uint32_t>(b0 + k0),
+                                pack + b0 + k0};
+                fused_row_dispatch2<A, 1, DB / 2>(hwave, row, dh, s0, s1, fv0.slots, parity0, parity1);
+            } else {
+                const int32_t e0 = c.row_ptr[sr], d = c.row_ptr[sr + 1] - e0, h = (d + 1) >> 1;
+                const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
+                const RowCSR<TS> row{fv0.r0 + TS * static_cast<uint32_t>(e0 + k0), c.col_idx + e0 + k0};
+                fused_row_dispatch2<A, 1, DB / 2>(hwave, row, dh, s0, s1, fv0.slots, parity0, parity1);
+            }
+        }
+        const int unsat0 = __syncthreads_or(static_cast<int>(parity0));
+        const int unsat1 = __syncthreads_or(static_cast<int>(parity1));
+        if (es) {  // as decode_frame, per frame: x^(t-1) a codeword -> stop at t-1, keep L^(t-1)
+            if (run0 && !unsat0) {
+                it0 = t - 1;
+                run0 = false;
+            }
+            if (run1 && !unsat1) {
+                it1 = t - 1;
+                run1 = false;
+            }
+            if (!run0 && !run1)
+                break;
+        }
+        for (int j = tid; j < n; j += NT) {
+            const int dwave = c.col_gmax[__builtin_amdgcn_readfirstlane(j) >> 6];
+            T v0 = llr0[j] * T(A::kIn), v1 = llr1[j] * T(A::kIn);
+            if (c.qc) {
+                const int32_t bj = div_z(j, c.zmagic);
+                const uint32_t cc_t = TS * static_cast<uint32_t>(j - bj * Z);
+                const int32_t k0 = cbs[bj];
+                auto edge = [&](int k) { return cpack[k0 + k] + cc_t; };
+                fused_col_dispatch2<A, 0, true>(dwave, edge, cbs[bj + 1] - k0, v0, v1, s0, s1);
+            } else {
+                const int32_t k0 = c.col_ptr[j];
+                auto edge = [&](int k) { return fv0.r0 + TS * static_cast<uint32_t>(c.col_edge[k0 + k]); };
+                fused_col_dispatch2<A, 0, false>(dwave, edge, c.col_ptr[j + 1] - k0, v0, v1, s0, s1);
+            }
+            if (run0)
+                sL0[j] = v0;
+            if (run1)
+                sL1[j] = v1;
+        }
+        __syncthreads();
+    }
+    uint8_t *bits = job.bits + f0 * n;
+    T *post = job.post ? static_cast<T *>(job.post) + f0 * n : nullptr;
+    for (int j = tid; j < n; j += NT) {
+        const T v = sL0[j];
+        bits[j] = static_cast<uint8_t>(v < T(0));
+        if (post)
+            post[j] = it0 == 0 ? llr0[j] : v * T(A::kOut);
+        if (has1) {
+            const T w = sL1[j];
+            bits[n + j] = static_cast<uint8_t>(w < T(0));
+            if (post)
+                post[n + j] = it1 == 0 ? llr1[j] : w * T(A::kOut);
+        }
+    }
+    if (tid == 0) {
+        job.iters[f0] = it0;
+        if (has1)
+            job.iters[f0 + 1] = it1;
+    }
+}
+
+// Persistent batch kernel over frame pairs: flooding sum-product jobs only,
+// item i of a job being its frames 2i and 2i + 1.  Two frames' LDS (qc1944:
+// 152 KB) allow one 512-thread workgroup per CU, so the bodies may use 256
+// VGPRs (2 waves per SIMD).
+template <class A, int DB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_pair(const Batch *__restrict__ batch, unsigned long long *counter)
+{
+    using T = typename A::T;
+    constexpr uint32_t TS = sizeof(T);
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ long long s_item;
+    const Batch &b = *batch;
+    const FrameLayout lay = frame_layout(b.emax, b.nmax, 0, 0, 0, TS, 2);
+    int32_t *sTab = reinterpret_cast<int32_t *>(smem + lay.t0);
+    const uint32_t nmax = static_cast<uint32_t>(b.nmax);
+    const Slots slots{TS * (nmax + 1 + threadIdx.x), TS * nmax};
+    const FrameView fv0{smem, lay.r0, sTab, slots}, fv1{smem + lay.span, lay.r0, sTab, slots};
+    if (threadIdx.x == 0) {  // published by the first barrier of the item loop
+        reinterpret_cast<T *>(fv0.s)[nmax] = T(__builtin_huge_val());
+        reinterpret_cast<T *>(fv1.s)[nmax] = T(__builtin_huge_val());
+    }
+    int cur_code = -1;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = static_cast<long long>(atomicAdd(counter, 1ull));
+        __syncthreads();
+        const int64_t item = s_item;
+        __syncthreads();
+        if (item >= b.nitems)
+            break;
+        int j = 0;
+        while (j + 1 < b.njobs && b.jobs[j + 1].item_begin <= item)
+            ++j;
+        const Job &job = b.jobs[j];
+        const Code &c = b.codes[job.code];
+        if (job.code != cur_code) {
+            cur_code = job.code;
+            load_tables<TS>(c, sTab, lay.r0);
+        }
+        const int64_t f0 = 2 * (item - job.item_begin);
+        decode_frame_pair<A, DB>(c, job, f0, f0 + 1 < job.frames, fv0, fv1);
+        __syncthreads();
+    }
+}
+
 // Persistent batch kernel: workgroups take (job, frame) items from *counter.
 // 512-thread workgroups, two per CU for n = 1944 (LDS bound): FP32 bodies are
 // held to 128 VGPRs so both fit (4 waves per SIMD); FP64 bodies get 256.
@@ -754,26 +1066,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWaves
         const Code &c = b.codes[job.code];
         if (job.code != cur_code) {
             cur_code = job.code;
-            for (int w = threadIdx.x; w < c.words; w += blockDim.x)
-                sTab[w] = c.tab[w];
-            if (c.qc) {
-                const uint32_t Z = static_cast<uint32_t>(c.Z);
-                const int32_t *bcol = c.tab + (c.mb + 1);
-                const int32_t *bsh = bcol + c.nblocks;
-                for (int w = threadIdx.x; w < c.nblocks; w += blockDim.x)
-                    sTab[c.words + w] = static_cast<int32_t>((TS * static_cast<uint32_t>(bcol[w]) * Z) |
-                                                             ((TS * static_cast<uint32_t>(bsh[w])) << 16));
-                for (int w = threadIdx.x; w < c.mb; w += blockDim.x)
-                    sTab[c.words + c.nblocks + w] = c.brow_order[w];
-                // the column phase's view: block-column slot w holds block cb[w]
-                const int32_t *cb = bsh + c.nblocks + (c.nb + 1);
-                for (int w = threadIdx.x; w < c.nblocks; w += blockDim.x)
-                    sTab[c.words + c.nblocks + c.mb + w] =
-                        static_cast<int32_t>(lay.r0 + TS * Z * static_cast<uint32_t>(cb[w]));
-                if (threadIdx.x < kColSpare)  // readable words past the column table's end
-                    sTab[c.words + 2 * c.nblocks + c.mb + threadIdx.x] = 0;
-            }
-            __syncthreads();
+            load_tables<TS>(c, sTab, lay.r0);
         }
         if (job.flags & LDPC_LAYERED)
             decode_frame_layered<A, DB>(c, job, item - job.item_begin, fv);
@@ -852,29 +1145,45 @@ inline ldpc_status launch_shape(const void *fn, size_t lds, int threads, int &pe
 // Launcher of the fused kernel for codes of row degree <= DB (one
 // translation unit per dtype and bucket).
 // The caller has already written the batch table to d_batch and reset *counter.
+// fpw: frames per workgroup, 1 (k_fused) or 2 (k_fused_pair, FP32 flooding
+// sum-product jobs only; the batch's items are then frame pairs).
 // profile = false keeps the launch out of ldpc_profile_* timing (whose event
 // pool may create events).
 template <class A, int DB>
 ldpc_status launch_fused_bucket(const fused::Batch &batch, fused::Batch *d_batch, unsigned long long *counter,
-                                size_t lds_bytes, int threads, hipStream_t s, bool profile);
+                                size_t lds_bytes, int threads, int fpw, hipStream_t s, bool profile);
+
+template <class K>
+ldpc_status launch_fused_kernel(K kern, const fused::Batch &batch, fused::Batch *d_batch, unsigned long long *counter,
+                                size_t lds_bytes, int threads, hipStream_t s, bool profile)
+{
+    int per_cu = 0, cus = 0;
+    const ldpc_status shape_rc =
+        fused::launch_shape(reinterpret_cast<const void *>(kern), lds_bytes, threads, per_cu, cus);
+    if (shape_rc != LDPC_OK)
+        return shape_rc;
+    const int64_t grid = std::min<int64_t>(batch.nitems, static_cast<int64_t>(per_cu) * cus);
+    ProfScope ps(LDPC_KERNEL_FUSED, s, profile);
+    LDPC_LAUNCH(ps, kern, dim3(static_cast<unsigned>(grid)), dim3(threads), static_cast<uint32_t>(lds_bytes), s,
+                d_batch, counter);
+    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EDEVICE;
+}
 
 #define LDPC_DEFINE_FUSED_BUCKET(A_, DB_)                                                                        \
     template <>                                                                                                  \
     ldpc_status launch_fused_bucket<A_, DB_>(const fused::Batch &batch, fused::Batch *d_batch,                  \
                                              unsigned long long *counter, size_t lds_bytes, int threads,        \
-                                             hipStream_t s, bool profile)                                        \
+                                             int fpw, hipStream_t s, bool profile)                               \
     {                                                                                                            \
-        auto kern = fused::k_fused<A_, DB_>;                                                                     \
-        int per_cu = 0, cus = 0;                                                                                 \
-        const ldpc_status shape_rc =                                                                             \
-            fused::launch_shape(reinterpret_cast<const void *>(kern), lds_bytes, threads, per_cu, cus);          \
-        if (shape_rc != LDPC_OK)                                                                                 \
-            return shape_rc;                                                                                     \
-        const int64_t grid = std::min<int64_t>(batch.nitems, static_cast<int64_t>(per_cu) * cus);               \
-        ProfScope ps(LDPC_KERNEL_FUSED, s, profile);                                                             \
-        LDPC_LAUNCH(ps, kern, dim3(static_cast<unsigned>(grid)), dim3(threads), static_cast<uint32_t>(lds_bytes), \
-                    s, d_batch, counter);                                                                        \
-        return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EDEVICE;                                         \
+        if constexpr (std::is_same<A_, ArithF32>::value) {                                                       \
+            if (fpw == 2)                                                                                        \
+                return launch_fused_kernel(fused::k_fused_pair<A_, DB_>, batch, d_batch, counter, lds_bytes,    \
+                                           threads, s, profile);                                                 \
+        }                                                                                                        \
+        if (fpw != 1)                                                                                            \
+            return LDPC_EUNSUPPORTED;                                                                            \
+        return launch_fused_kernel(fused::k_fused<A_, DB_>, batch, d_batch, counter, lds_bytes, threads, s,     \
+                                   profile);                                                                     \
     }
 
 }  // namespace ldpc

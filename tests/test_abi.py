@@ -111,3 +111,24 @@ def test_noalloc_batch_argument_errors_without_device():
     assert lib.ldpc_decode_batch_noalloc(None, 0, 7, None) == L.LDPC_EINVAL
     job = L.ldpc_job(None, 4, 10, 0, None, None, None, None)
     assert lib.ldpc_decode_batch_noalloc(ctypes.byref(job), 1, 0, None) == L.LDPC_EINVAL
+
+
+def test_tuning_file_round_trip_without_device(tmp_path):
+    """The tuning table's file format: valid lines load (and count), a
+    malformed line is refused; saving writes one line per entry."""
+    lib = L.library()
+    good = tmp_path / "tune.txt"
+    good.write_text("gfx950 00000000000000ab 256 2 1.250000\ngfx950 00000000000000cd 512 1 0.500000\n")
+    n = ctypes.c_int32(-1)
+    assert lib.ldpc_tuning_load(str(good).encode(), ctypes.byref(n)) == L.LDPC_OK and n.value == 2
+    bad = tmp_path / "bad.txt"
+    bad.write_text("gfx950 00000000000000ef 100 1 1.0\n")  # 100 threads: not a multiple of 64
+    assert lib.ldpc_tuning_load(str(bad).encode(), ctypes.byref(n)) == L.LDPC_EINVAL
+    assert lib.ldpc_tuning_load(str(tmp_path / "missing.txt").encode(), None) == L.LDPC_EINVAL
+    out = tmp_path / "saved.txt"
+    assert lib.ldpc_tuning_save(str(out).encode()) == L.LDPC_OK
+    saved = out.read_text().splitlines()
+    assert len(saved) >= 2 and all(len(s.split()) == 5 for s in saved)
+    assert {s.split()[1] for s in saved} >= {"00000000000000ab", "00000000000000cd"}
+    assert lib.ldpc_batch_set_frames_per_group(3) == L.LDPC_EINVAL
+    assert lib.ldpc_batch_set_frames_per_group(1) == L.LDPC_OK
