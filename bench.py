@@ -361,13 +361,15 @@ def extra_workloads():
                "batch_mbps": bits / (tb * 1e-3) / 1e6, "mean_iters": mean_it,
                "plain_floor": frac(tp), "batch_floor": frac(tb)}
         if tune:
-            threads, _ = L.ldpc_autotune_batch(cj, dtype, bws, bw)
+            L.ldpc_autotune_batch(cj, dtype, bws, bw)
+            chosen = L.ldpc_batch_launch_config(cj, dtype)
             tt = _time_ms(batched, reps)
             plan = L.Plan(jobs)
             tg = _time_ms(plan.launch, reps)
             plan.close()
             res.update({"batch_tuned_ms": tt, "batch_tuned_mbps": bits / (tt * 1e-3) / 1e6,
-                        "tuned_threads": threads, "plan_replay_ms": tg, "plan_replay_mbps": bits / (tg * 1e-3) / 1e6,
+                        "tuned_threads": chosen["threads"], "tuned_frames_per_group": chosen["frames_per_group"],
+                        "plan_replay_ms": tg, "plan_replay_mbps": bits / (tg * 1e-3) / 1e6,
                         "batch_tuned_floor": frac(tt)})
         return res
 
@@ -669,7 +671,11 @@ def serve_run(seconds, rate, max_group_frames=1024, max_inflight=3, warmup_s=0.0
             "offered_req_per_s": rate, "duration_s": seconds, "warmup_s": warmup_s, "requests": s["completed"],
             "rejected": rejected,
             "failed": s["failed"], "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "p999_ms": s["p999_ms"],
-            "max_ms": s["max_ms"], "mbps": s["bits_completed"] / wall / 1e6, "launches": s["launches"],
+            "max_ms": s["max_ms"],
+            "max_ms_breakdown": {k: s["worst_" + k + "_ms"] for k in ("submit", "queue", "stage", "device", "copyout")},
+            "max_step_ms": s["max_step_ms"],
+            "max_host_ms": {k: s["max_" + k + "_ms"] for k in ("copy", "launch", "query")},
+            "mbps": s["bits_completed"] / wall / 1e6, "launches": s["launches"],
             "mean_group_frames": s["mean_group_frames"], "max_queue_depth": s["max_queue_depth"],
             "submit_lag_p99_ms": float(lag_ms[int(0.99 * (lag_ms.size - 1))]) if lag_ms.size else 0.0,
             "submit_lag_max_ms": float(lag_ms[-1]) if lag_ms.size else 0.0}

@@ -286,6 +286,12 @@ void ldpc_plan_destroy(ldpc_plan plan);
  * requester's LLRs are read when the group is admitted, so they must stay
  * valid until the request completes.  Every frame's result equals decoding it
  * alone.
+ * While groups are in flight the scheduler thread polls their completion by
+ * spinning (one host core busy), not by timed sleeps: waking a sleeping
+ * thread can take milliseconds, which every request in flight would wait out.
+ * With LDPC_SERVER_TRACE set to a file name, scheduler steps slower than
+ * 0.5 ms are appended to that file when the server is destroyed (where the
+ * step's time went, the thread's CPU time, its context switches).
  * Codes must fit the fused kernel (ldpc_batch_fits_fused), all FP32.
  */
 typedef struct ldpc_server_s *ldpc_server;
@@ -308,6 +314,18 @@ typedef struct {
     double p50_ms, p99_ms, p999_ms, max_ms;    /* latency: completion - arrival, over completed requests */
     double mean_group_frames;
     int64_t max_queue_depth;
+    /* where the slowest request (the one of max_ms) spent its time: */
+    double worst_submit_ms;   /* arrival -> submit call */
+    double worst_queue_ms;    /* submit -> its group admitted by the scheduler */
+    double worst_stage_ms;    /* admitted -> group launched (LLR staging copy and launch calls) */
+    double worst_device_ms;   /* launched -> completion seen by the scheduler (device time, including
+                                 any wait behind other groups on the device) */
+    double worst_copyout_ms;  /* completion seen -> results copied out, request done */
+    double max_step_ms;       /* longest scheduler step (completions reaped + groups admitted), and within
+                                 steps the longest: */
+    double max_copy_ms;       /* host copy of one group's LLRs in, or of its results out */
+    double max_launch_ms;     /* sequence of launch calls of one group */
+    double max_query_ms;      /* completion query of one group */
 } ldpc_server_stats;
 
 /* Create a server on the current device (Section III-C, as above).  Before

@@ -76,7 +76,11 @@ class ldpc_server_stats(ctypes.Structure):
                 ("failed", ctypes.c_int64), ("launches", ctypes.c_int64), ("frames_completed", ctypes.c_int64),
                 ("bits_completed", ctypes.c_int64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
                 ("p999_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("mean_group_frames", ctypes.c_double),
-                ("max_queue_depth", ctypes.c_int64)]
+                ("max_queue_depth", ctypes.c_int64), ("worst_submit_ms", ctypes.c_double),
+                ("worst_queue_ms", ctypes.c_double), ("worst_stage_ms", ctypes.c_double),
+                ("worst_device_ms", ctypes.c_double), ("worst_copyout_ms", ctypes.c_double),
+                ("max_step_ms", ctypes.c_double), ("max_copy_ms", ctypes.c_double),
+                ("max_launch_ms", ctypes.c_double), ("max_query_ms", ctypes.c_double)]
 
 
 _sig("ldpc_server_create", ctypes.c_int, [ctypes.POINTER(ldpc_server_cfg), ctypes.POINTER(_P)])

@@ -15,6 +15,7 @@
 // queue and the slots: the staging copies, launches and result copies run
 // without it, so a large group never holds up submitters.  Arithmetic is per
 // frame, so a request's result does not depend on what it was batched with.
+#include <sys/resource.h>
 #include <time.h>
 
 #include <algorithm>
@@ -22,10 +23,13 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -39,6 +43,24 @@ int64_t now_ns()
     clock_gettime(CLOCK_MONOTONIC, &ts);
     return static_cast<int64_t>(ts.tv_sec) * 1000000000LL + ts.tv_nsec;
 }
+
+int64_t thread_cpu_ns()
+{
+    timespec ts;
+    clock_gettime(CLOCK_THREAD_CPUTIME_ID, &ts);
+    return static_cast<int64_t>(ts.tv_sec) * 1000000000LL + ts.tv_nsec;
+}
+
+// Scheduler steps slower than kTraceStepNs are recorded when the environment
+// variable LDPC_SERVER_TRACE names a file (written when the server is
+// destroyed): where the step's time went, the thread's CPU time in it and
+// its context switches, to tell a blocked or preempted thread from work.
+constexpr int64_t kTraceStepNs = 500000;
+struct StepTrace {
+    int64_t start_ns, wall_ns, cpu_ns, sleep_ns;  // sleep_ns: the wait before this step
+    int64_t copy_ns, launch_ns, query_ns;         // longest of each inside the step
+    long nvcsw, nivcsw;                           // voluntary / involuntary context switches in the step
+};
 
 // First-fit allocator of contiguous ranges in [0, capacity).
 class RangeAlloc {
@@ -91,12 +113,16 @@ inline int64_t align4(int64_t e) { return (e + 3) & ~int64_t(3); }
 // slots keep their compute units while it runs.
 constexpr int32_t kLinkCopyBlocks = 64;
 
-// Host copies of one group (LLRs into staging, results out of it), split over
-// helper threads when the group is large: one thread copies about 10 GB/s,
-// and near capacity the next group's admission waits on these copies (the
-// tail latency grows several-fold without the helpers).  The calling (scheduler)
-// thread takes one share and each helper another; destinations are
-// disjoint, so the shares are independent.  Only the scheduler calls run().
+// Host copies of one group (LLRs into staging, results out of it), shared
+// with helper threads when the group is large: one thread copies about
+// 10 GB/s, and near capacity the next group's admission waits on these copies
+// (the tail latency grows several-fold without the helpers).  The copy is cut
+// into chunks that the calling (scheduler) thread and the helpers claim one at
+// a time, so the caller never waits for a helper that has not started: a
+// helper that wakes late (waking a sleeping thread has been seen to take
+// milliseconds) finds the chunks taken, and the caller waits only for chunks
+// already being copied.  Destinations are disjoint, so chunks are independent.
+// Only the scheduler calls run().
 class CopyPool {
   public:
     struct Item {
@@ -104,14 +130,14 @@ class CopyPool {
         const void *src;
         size_t bytes;
     };
-    static constexpr size_t kParallelBytes = 256 << 10;  // smaller groups are copied by the caller alone
+    static constexpr size_t kParallelBytes = 1 << 20;  // smaller groups are copied by the caller alone
+    static constexpr size_t kChunkBytes = 64 << 10;
 
     explicit CopyPool(int helpers)
     {
-        parts_.resize(static_cast<size_t>(helpers) + 1);
         try {
             for (int i = 0; i < helpers; ++i)
-                threads_.emplace_back([this, i] { loop(i + 1); });
+                threads_.emplace_back([this] { loop(); });
         } catch (...) {
             shut_down();  // helpers started so far must be joined before the members go
             throw;
@@ -130,37 +156,37 @@ class CopyPool {
                     std::memcpy(it.dst, it.src, it.bytes);
             return;
         }
-        // cut the items into parts of about total / parts bytes each
-        const size_t nparts = parts_.size(), share = (total + nparts - 1) / nparts;
-        for (auto &p : parts_)
-            p.clear();
-        size_t part = 0, room = nparts == 1 ? SIZE_MAX : share;
-        for (const Item &it : items) {
-            size_t off = 0;
-            while (off < it.bytes) {
-                const size_t take = std::min(room, it.bytes - off);
-                parts_[part].push_back({static_cast<char *>(it.dst) + off, static_cast<const char *>(it.src) + off, take});
-                off += take;
-                room -= take;
-                if (room == 0 && part + 1 < nparts) {
-                    ++part;
-                    room = part + 1 == nparts ? SIZE_MAX : share;  // the last part takes whatever is left
-                }
-            }
-        }
-        {
-            std::lock_guard<std::mutex> lk(mu_);
-            remaining_ = static_cast<int>(threads_.size());
-            ++gen_;
-        }
-        go_.notify_all();
-        for (const Item &it : parts_[0])
-            std::memcpy(it.dst, it.src, it.bytes);
+        // No helper reads chunks_ now: the previous run ended with every
+        // chunk claimed and copied.
+        chunks_.clear();
+        for (const Item &it : items)
+            for (size_t off = 0; off < it.bytes; off += kChunkBytes)
+                chunks_.push_back({static_cast<char *>(it.dst) + off, static_cast<const char *>(it.src) + off,
+                                   std::min(kChunkBytes, it.bytes - off)});
         std::unique_lock<std::mutex> lk(mu_);
-        done_.wait(lk, [&] { return remaining_ == 0; });
+        next_ = 0;
+        count_ = pending_ = chunks_.size();
+        lk.unlock();
+        go_.notify_all();
+        lk.lock();
+        copy_claimed(lk);
+        done_.wait(lk, [&] { return pending_ == 0; });  // chunks helpers are copying right now
     }
 
   private:
+    // Claims and copies chunks until none is left (called and returns with lk held).
+    void copy_claimed(std::unique_lock<std::mutex> &lk)
+    {
+        while (next_ < count_) {
+            const Item &c = chunks_[next_++];
+            lk.unlock();
+            std::memcpy(c.dst, c.src, c.bytes);
+            lk.lock();
+            if (--pending_ == 0)
+                done_.notify_one();
+        }
+    }
+
     void shut_down()
     {
         {
@@ -173,30 +199,22 @@ class CopyPool {
         threads_.clear();
     }
 
-    void loop(size_t me)
+    void loop()
     {
-        uint64_t seen = 0;
         std::unique_lock<std::mutex> lk(mu_);
         for (;;) {
-            go_.wait(lk, [&] { return stop_ || gen_ != seen; });
+            go_.wait(lk, [&] { return stop_ || next_ < count_; });
             if (stop_)
                 return;
-            seen = gen_;
-            lk.unlock();
-            for (const Item &it : parts_[me])
-                std::memcpy(it.dst, it.src, it.bytes);
-            lk.lock();
-            if (--remaining_ == 0)
-                done_.notify_one();
+            copy_claimed(lk);
         }
     }
 
     std::vector<std::thread> threads_;
-    std::vector<std::vector<Item>> parts_;
+    std::vector<Item> chunks_;  // written by run() only while no chunk is claimable
     std::mutex mu_;
     std::condition_variable go_, done_;
-    uint64_t gen_ = 0;
-    int remaining_ = 0;
+    size_t next_ = 0, count_ = 0, pending_ = 0;  // next chunk to claim, chunks, chunks not yet copied
     bool stop_ = false;
 };
 
@@ -211,6 +229,8 @@ struct Request {
     int32_t *iters = nullptr;
     float *post = nullptr;
     int64_t arrival_ns = 0, done_ns = 0;
+    // scheduler milestones, for the slowest request's latency breakdown
+    int64_t submit_ns = 0, admit_ns = 0, launch_ns = 0, seen_ns = 0;
     int state = kQueued;
     int64_t elem_off = 0, frame_off = 0;  // offsets inside the group's ranges
 };
@@ -244,6 +264,7 @@ struct ldpc_server_s {
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
+    std::atomic<uint64_t> submits{0};  // requests queued so far (read by the polling scheduler without the lock)
     std::deque<Request *> queue;
     // request of ticket t at by_ticket[t - 1]: tickets are consecutive, and a
     // deque grows in fixed blocks (no rehash or bulk move under the lock)
@@ -264,6 +285,11 @@ struct ldpc_server_s {
     ldpc_server_stats st{};
     std::deque<double> lat_ms;  // grows in fixed blocks: no bulk move under the lock
     int64_t group_frames_sum = 0;
+    double worst_ms = -1.0;     // latency of the request behind st.worst_*
+    // slow-step trace (see StepTrace); the step_* maxima cover the current step
+    std::string trace_path;
+    std::vector<StepTrace> trace;
+    int64_t step_copy_ns = 0, step_launch_ns = 0, step_query_ns = 0, t_created = 0;
 
     void run();
     void schedule(std::unique_lock<std::mutex> &lk);
@@ -281,7 +307,14 @@ bool ldpc_server_s::reap(std::unique_lock<std::mutex> &lk)
         // slots belong to the scheduler thread: their events are queried and
         // their results copied out without holding the lock, so submitters
         // are never held up by a large group's copies
-        if (!s.busy || hipEventQuery(s.done) != hipSuccess)
+        if (!s.busy)
+            continue;
+        const int64_t q0 = now_ns();
+        const hipError_t q = hipEventQuery(s.done);
+        const int64_t seen = now_ns();
+        step_query_ns = std::max(step_query_ns, seen - q0);
+        st.max_query_ms = std::max(st.max_query_ms, static_cast<double>(seen - q0) * 1e-6);
+        if (q != hipSuccess)
             continue;
         lk.unlock();
         copy_items.clear();
@@ -296,10 +329,22 @@ bool ldpc_server_s::reap(std::unique_lock<std::mutex> &lk)
         copies->run(copy_items);
         const int64_t t = now_ns();
         lk.lock();
+        step_copy_ns = std::max(step_copy_ns, t - seen);
+        st.max_copy_ms = std::max(st.max_copy_ms, static_cast<double>(t - seen) * 1e-6);
         for (Request *r : s.reqs) {
+            r->seen_ns = seen;
             r->done_ns = t;
             r->state = kDone;
-            lat_ms.push_back(static_cast<double>(t - r->arrival_ns) * 1e-6);
+            const double lat = static_cast<double>(t - r->arrival_ns) * 1e-6;
+            lat_ms.push_back(lat);
+            if (lat > worst_ms) {
+                worst_ms = lat;
+                st.worst_submit_ms = static_cast<double>(r->submit_ns - r->arrival_ns) * 1e-6;
+                st.worst_queue_ms = static_cast<double>(r->admit_ns - r->submit_ns) * 1e-6;
+                st.worst_stage_ms = static_cast<double>(r->launch_ns - r->admit_ns) * 1e-6;
+                st.worst_device_ms = static_cast<double>(r->seen_ns - r->launch_ns) * 1e-6;
+                st.worst_copyout_ms = static_cast<double>(r->done_ns - r->seen_ns) * 1e-6;
+            }
             st.completed += 1;
             st.frames_completed += r->frames;
             st.bits_completed += r->frames * code_n[r->code_id];
@@ -353,8 +398,11 @@ bool ldpc_server_s::admit(std::unique_lock<std::mutex> &lk)
         s.frame_begin = fb;
         s.frame_len = f;
         s.want_post = false;
-        for (Request *r : s.reqs)
+        const int64_t admitted = now_ns();
+        for (Request *r : s.reqs) {
             r->state = kInFlight;  // from here on cancel() refuses these requests
+            r->admit_ns = admitted;
+        }
         // staging copies and launches run without the lock
         lk.unlock();
         // The group's requests are laid out in the arena by code (and by
@@ -401,6 +449,7 @@ bool ldpc_server_s::admit(std::unique_lock<std::mutex> &lk)
             fo += r->frames;
         }
         copies->run(copy_items);
+        const int64_t copied = now_ns();
         // The copy kernel moves the staged LLRs into the device arena (the
         // decode kernel reads them every iteration); the decode kernel writes
         // bits, iteration counts and posteriors straight into pinned host
@@ -432,7 +481,14 @@ bool ldpc_server_s::admit(std::unique_lock<std::mutex> &lk)
             continue;
         }
         (void)hipEventRecord(s.done, s.stream);
+        const int64_t launched = now_ns();
+        for (Request *r : s.reqs)
+            r->launch_ns = launched;
         lk.lock();
+        step_copy_ns = std::max(step_copy_ns, copied - admitted);
+        step_launch_ns = std::max(step_launch_ns, launched - copied);
+        st.max_copy_ms = std::max(st.max_copy_ms, static_cast<double>(copied - admitted) * 1e-6);
+        st.max_launch_ms = std::max(st.max_launch_ms, static_cast<double>(launched - copied) * 1e-6);
         s.busy = true;
         st.launches += 1;
         group_frames_sum += f;
@@ -443,16 +499,48 @@ bool ldpc_server_s::admit(std::unique_lock<std::mutex> &lk)
 
 void ldpc_server_s::schedule(std::unique_lock<std::mutex> &lk)
 {
+    const bool tracing = !trace_path.empty();
+    int64_t slept = 0;
+    bool waited_busy = false;  // the last wait was a 20 us poll (with groups in flight)
     for (;;) {
+        const int64_t t0 = now_ns();
+        int64_t c0 = 0;
+        rusage u0{};
+        if (tracing) {
+            c0 = thread_cpu_ns();
+            getrusage(RUSAGE_THREAD, &u0);
+            step_copy_ns = step_launch_ns = step_query_ns = 0;
+        }
         reap(lk);
         admit(lk);
+        const int64_t t1 = now_ns();
+        st.max_step_ms = std::max(st.max_step_ms, static_cast<double>(t1 - t0) * 1e-6);
+        if (tracing && (t1 - t0 > kTraceStepNs || (waited_busy && slept > kTraceStepNs))) {
+            rusage u1{};
+            getrusage(RUSAGE_THREAD, &u1);
+            trace.push_back(StepTrace{t0 - t_created, t1 - t0, thread_cpu_ns() - c0, slept, step_copy_ns,
+                                      step_launch_ns, step_query_ns, u1.ru_nvcsw - u0.ru_nvcsw,
+                                      u1.ru_nivcsw - u0.ru_nivcsw});
+        }
         const bool busy = std::any_of(slots.begin(), slots.end(), [](const Slot &s) { return s.busy; });
         if (stop && queue.empty() && !busy)
             break;
-        if (busy)
-            cv_work.wait_for(lk, std::chrono::microseconds(20));
-        else
+        waited_busy = busy;
+        if (busy) {
+            // Groups in flight: poll again within 20 us, or sooner once a
+            // request arrives.  The thread spins rather than sleeps: waking a
+            // sleeping thread has been seen to take milliseconds here, which
+            // every request in flight would wait out.
+            const uint64_t seen = submits.load(std::memory_order_relaxed);
+            lk.unlock();
+            const int64_t until = t1 + 20000;
+            while (submits.load(std::memory_order_relaxed) == seen && now_ns() < until)
+                __builtin_ia32_pause();
+            lk.lock();
+        } else {
             cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+        }
+        slept = now_ns() - t1;
     }
 }
 
@@ -645,6 +733,11 @@ try {
     }
     const unsigned hw = std::thread::hardware_concurrency();
     sv->copies.reset(new CopyPool(static_cast<int>(std::min(3u, hw > 4 ? hw / 4 : 0u))));
+    if (const char *tp = std::getenv("LDPC_SERVER_TRACE")) {
+        sv->trace_path = tp;
+        sv->trace.reserve(4096);
+    }
+    sv->t_created = now_ns();
     ldpc_server_s *raw = sv.get();
     sv->sched = std::thread([raw] { raw->run(); });
     *out = sv.release();
@@ -673,7 +766,8 @@ try {
     r->bits = bits;
     r->iters = iters;
     r->post = posterior;
-    r->arrival_ns = arrival_ns > 0 ? arrival_ns : now_ns();
+    r->submit_ns = now_ns();
+    r->arrival_ns = arrival_ns > 0 ? arrival_ns : r->submit_ns;
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         if (sv->broken)
@@ -694,6 +788,7 @@ try {
         sv->st.max_queue_depth = std::max<int64_t>(sv->st.max_queue_depth, static_cast<int64_t>(sv->queue.size()));
         *ticket = r->ticket;
     }
+    sv->submits.fetch_add(1, std::memory_order_relaxed);
     sv->cv_work.notify_one();
     return LDPC_OK;
 } catch (...) {
@@ -769,6 +864,7 @@ try {
             v.swap(sv->lat_ms);
             sv->st = ldpc_server_stats{};
             sv->group_frames_sum = 0;
+            sv->worst_ms = -1.0;
         } else {
             v = sv->lat_ms;
         }
@@ -802,6 +898,16 @@ try {
     sv->cv_work.notify_all();
     if (sv->sched.joinable())
         sv->sched.join();
+    if (!sv->trace_path.empty()) {
+        if (FILE *f = std::fopen(sv->trace_path.c_str(), "a")) {
+            std::fprintf(f, "# start_ms wall_ms cpu_ms sleep_before_ms copy_ms launch_ms query_ms nvcsw nivcsw\n");
+            for (const StepTrace &t : sv->trace)
+                std::fprintf(f, "%.3f %.3f %.3f %.3f %.3f %.3f %.3f %ld %ld\n", t.start_ns * 1e-6, t.wall_ns * 1e-6,
+                             t.cpu_ns * 1e-6, t.sleep_ns * 1e-6, t.copy_ns * 1e-6, t.launch_ns * 1e-6,
+                             t.query_ns * 1e-6, t.nvcsw, t.nivcsw);
+            std::fclose(f);
+        }
+    }
     sv->free_all();
     delete sv;
 } catch (...) {

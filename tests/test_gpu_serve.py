@@ -75,6 +75,10 @@ def test_server_isolation_and_oracle(L, pool):
         _log(f"[gpu] serve stats: {stats}")
         assert stats["completed"] == len(reqs) and stats["failed"] == 0
         assert stats["launches"] >= 2
+        # the slowest request's stages add up to its latency, and none is negative
+        parts = [stats["worst_" + k + "_ms"] for k in ("queue", "stage", "device", "copyout")]
+        assert min(parts) >= 0.0 and stats["max_step_ms"] > 0.0
+        assert abs(sum(parts) + stats["worst_submit_ms"] - stats["max_ms"]) < 1e-3
     finally:
         L.ldpc_server_destroy(srv)
     for k, r in enumerate(reqs):
