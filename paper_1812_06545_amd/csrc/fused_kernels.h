@@ -231,7 +231,7 @@ __device__ __forceinline__ ArithF32::Acc pair_swap(const ArithF32::Acc &v)
 // a register array; after the partner's half combination and sign are
 // exchanged, the backward pass reads a_k back and overwrites the slot with
 // the new message.
-template <class A, int D, class Row>
+template <class A, int D, bool PAR, class Row>
 __device__ __forceinline__ void fused_half_row(const Row &row, int dh, unsigned char *__restrict__ s, Slots sl,
                                                uint32_t &parity)
 {
@@ -256,7 +256,8 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int dh, unsigned 
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         const T l = lv[j];
-        par ^= static_cast<uint32_t>(l < T(0));
+        if constexpr (PAR)
+            par ^= static_cast<uint32_t>(l < T(0));
         const T q = l - rv[j];
         typename A::Term a_k;
         check_forward<A>(q, a_k, p[j], acc, sign);
@@ -265,7 +266,8 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int dh, unsigned 
     }
     const typename A::Acc s_other = pair_swap(acc);
     const uint32_t sign_total = sign ^ pair_swap(sign);
-    parity |= par ^ pair_swap(par);  // a lane may hold several rows: any unsatisfied row counts
+    if constexpr (PAR)
+        parity |= par ^ pair_swap(par);  // a lane may hold several rows: any unsatisfied row counts
     typename A::Acc sx = A::seed(s_other);
     // Every parked value is read before the first message is stored: a
     // dummy's slot then still holds the parked dummy term (kDummyParked,
@@ -286,20 +288,20 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int dh, unsigned 
 // Body selection by the wave's largest half length: exact-length bodies for
 // FP32 circulant codes, the hot case; one padded body of length DB for FP64
 // and for CSR codes (fewer instantiations, same results).
-template <class A, int D, int DB, class Row>
+template <class A, int D, int DB, bool PAR, class Row>
 __device__ __forceinline__ void fused_row_dispatch(int hwave, const Row &row, int dh, unsigned char *__restrict__ s,
                                                    Slots sl, uint32_t &parity)
 {
     constexpr bool exact = std::is_same<A, ArithF32>::value && std::is_same<Row, RowQC>::value;
     if constexpr (!exact) {
-        fused_half_row<A, DB>(row, dh, s, sl, parity);
+        fused_half_row<A, DB, PAR>(row, dh, s, sl, parity);
     } else if constexpr (D < DB) {
         if (hwave == D)
-            fused_half_row<A, D>(row, dh, s, sl, parity);
+            fused_half_row<A, D, PAR>(row, dh, s, sl, parity);
         else
-            fused_row_dispatch<A, D + 1, DB>(hwave, row, dh, s, sl, parity);
+            fused_row_dispatch<A, D + 1, DB, PAR>(hwave, row, dh, s, sl, parity);
     } else {
-        fused_half_row<A, DB>(row, dh, s, sl, parity);
+        fused_half_row<A, DB, PAR>(row, dh, s, sl, parity);
     }
 }
 
@@ -428,7 +430,7 @@ __device__ __forceinline__ void ms_half_row(const Row &row, int k0, int dh, unsi
 // offset (the circulant tables in LDS end with kColSpare zero words), so all
 // D slots are read unconditionally at constant offsets; otherwise dummies
 // read offset 0.  edge(k) is the byte offset of the column's k-th message.
-template <class A, int D, bool SAFE0, class Edge>
+template <class A, int D, bool SAFE0, bool FULL, class Edge>
 __device__ __forceinline__ typename A::T fused_col(const Edge &edge, int dv, typename A::T acc,
                                                    const unsigned char *__restrict__ s)
 {
@@ -437,10 +439,10 @@ __device__ __forceinline__ typename A::T fused_col(const Edge &edge, int dv, typ
     T rv[D > 0 ? D : 1];
 #pragma unroll
     for (int k = 0; k < D; ++k)
-        rv[k] = SAFE0 ? lds_ld<T>(s, edge(k)) : lds_ld<T>(s, k < dv ? edge(k) : 0u);
+        rv[k] = SAFE0 || FULL ? lds_ld<T>(s, edge(k)) : lds_ld<T>(s, k < dv ? edge(k) : 0u);
 #pragma unroll
     for (int k = 0; k < D; ++k)
-        acc = k < dv ? acc + rv[k] : acc;
+        acc = FULL || k < dv ? acc + rv[k] : acc;
     return acc;
 }
 
@@ -454,8 +456,12 @@ __device__ __forceinline__ typename A::T fused_col_dispatch(int dwave, const Edg
             acc += lds_ld<T>(s, edge(k));
         return acc;
     } else if constexpr (D <= kColSpare) {
-        if (dwave == D)
-            return fused_col<A, D, SAFE0>(edge, dv, acc, s);
+        if (dwave == D) {
+            // FULL: every column of the wave has degree D (no slot to skip)
+            if (__all(dv == D))
+                return fused_col<A, D, SAFE0, true>(edge, dv, acc, s);
+            return fused_col<A, D, SAFE0, false>(edge, dv, acc, s);
+        }
         return fused_col_dispatch<A, D + 1, SAFE0>(dwave, edge, dv, acc, s);
     } else {
         for (int k = 0; k < dv; ++k)
@@ -537,22 +543,31 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
                                 pack + b0 + k0};
                 if (ms)
                     ms_half_row<A, DB / 2, false>(row, k0, dh, s, fv.slots, parity, ms_scale, ms_offset);
+                else if (es)
+                    fused_row_dispatch<A, 1, DB / 2, true>(hwave, row, dh, s, fv.slots, parity);
                 else
-                    fused_row_dispatch<A, 1, DB / 2>(hwave, row, dh, s, fv.slots, parity);
+                    fused_row_dispatch<A, 1, DB / 2, false>(hwave, row, dh, s, fv.slots, parity);
             } else {
                 const int32_t e0 = c.row_ptr[sr], d = c.row_ptr[sr + 1] - e0, h = (d + 1) >> 1;
                 const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
                 const RowCSR<TS> row{fv.r0 + TS * static_cast<uint32_t>(e0 + k0), c.col_idx + e0 + k0};
                 if (ms)
                     ms_half_row<A, DB / 2, false>(row, k0, dh, s, fv.slots, parity, ms_scale, ms_offset);
+                else if (es)
+                    fused_row_dispatch<A, 1, DB / 2, true>(hwave, row, dh, s, fv.slots, parity);
                 else
-                    fused_row_dispatch<A, 1, DB / 2>(hwave, row, dh, s, fv.slots, parity);
+                    fused_row_dispatch<A, 1, DB / 2, false>(hwave, row, dh, s, fv.slots, parity);
             }
         }
-        const int unsat = __syncthreads_or(static_cast<int>(parity));
-        if (es && !unsat) {  // x^(t-1) is a codeword: stop at t-1, keep L^(t-1)
-            it = t - 1;
-            break;
+        // The syndrome of x^(t-1) is formed only under early stop (min-sum
+        // rows form it always, unused without).
+        if (es) {
+            if (!__syncthreads_or(static_cast<int>(parity))) {  // a codeword: stop at t-1, keep L^(t-1)
+                it = t - 1;
+                break;
+            }
+        } else {
+            __syncthreads();
         }
         for (int j = tid; j < n; j += NT) {
             const int dwave = c.col_gmax[__builtin_amdgcn_readfirstlane(j) >> 6];
