@@ -231,7 +231,9 @@ __device__ __forceinline__ ArithF32::Acc pair_swap(const ArithF32::Acc &v)
 // a register array; after the partner's half combination and sign are
 // exchanged, the backward pass reads a_k back and overwrites the slot with
 // the new message.
-template <class A, int D, bool PAR, class Row>
+// TAIL: the caller has checked that every lane of the wave has dh >= D - 1,
+// so only the last slot can be a dummy.
+template <class A, int D, bool PAR, bool TAIL, class Row>
 __device__ __forceinline__ void fused_half_row(const Row &row, int dh, unsigned char *__restrict__ s, Slots sl,
                                                uint32_t &parity)
 {
@@ -243,7 +245,7 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int dh, unsigned 
     uint32_t ri[D], ci[D];
 #pragma unroll
     for (int j = 0; j < D; ++j)
-        slot_offsets(row, j, j < dh, sl.dslot, sl.inf_off, ri[j], ci[j]);
+        slot_offsets(row, j, (TAIL && j < D - 1) || j < dh, sl.dslot, sl.inf_off, ri[j], ci[j]);
     T lv[D], rv[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -285,6 +287,24 @@ __device__ __forceinline__ void fused_half_row(const Row &row, int dh, unsigned 
     }
 }
 
+// An exact-length body.  For jobs without early stop (no syndrome), when the
+// wave's half rows are all D or D - 1 long (a wave within one block-row, or
+// across two of close degrees: the common case), one whose slots need no
+// dummy select but the last.  (With the syndrome the same body measured
+// slower on most codes, so early-stop jobs keep the general one.)
+template <class A, int D, bool PAR, class Row>
+__device__ __forceinline__ void fused_row_exact(const Row &row, int dh, unsigned char *__restrict__ s, Slots sl,
+                                                uint32_t &parity)
+{
+    if constexpr (!PAR && D > 1) {
+        if (__all(dh >= D - 1)) {
+            fused_half_row<A, D, PAR, true>(row, dh, s, sl, parity);
+            return;
+        }
+    }
+    fused_half_row<A, D, PAR, false>(row, dh, s, sl, parity);
+}
+
 // Body selection by the wave's largest half length: exact-length bodies for
 // FP32 circulant codes, the hot case; one padded body of length DB for FP64
 // and for CSR codes (fewer instantiations, same results).
@@ -294,14 +314,14 @@ __device__ __forceinline__ void fused_row_dispatch(int hwave, const Row &row, in
 {
     constexpr bool exact = std::is_same<A, ArithF32>::value && std::is_same<Row, RowQC>::value;
     if constexpr (!exact) {
-        fused_half_row<A, DB, PAR>(row, dh, s, sl, parity);
+        fused_half_row<A, DB, PAR, false>(row, dh, s, sl, parity);
     } else if constexpr (D < DB) {
         if (hwave == D)
-            fused_half_row<A, D, PAR>(row, dh, s, sl, parity);
+            fused_row_exact<A, D, PAR>(row, dh, s, sl, parity);
         else
             fused_row_dispatch<A, D + 1, DB, PAR>(hwave, row, dh, s, sl, parity);
     } else {
-        fused_half_row<A, DB, PAR>(row, dh, s, sl, parity);
+        fused_row_exact<A, DB, PAR>(row, dh, s, sl, parity);
     }
 }
 
