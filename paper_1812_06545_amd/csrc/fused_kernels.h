@@ -219,6 +219,18 @@ __device__ __forceinline__ ArithF32::Acc pair_swap(const ArithF32::Acc &v)
     return ArithF32::Acc{pair_swap(v.P), pair_swap(v.Q)};
 }
 
+// Value of lane ^ 16: the sibling quarter of a layered row, whose four
+// quarters sit in lanes l, l + 16, l + 32 and l + 48 (l < 16).
+__device__ __forceinline__ uint32_t quad_swap(uint32_t v)
+{
+    return static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), 16));
+}
+__device__ __forceinline__ double quad_swap(double v) { return __shfl_xor(v, 16); }
+__device__ __forceinline__ ArithF32::Acc quad_swap(const ArithF32::Acc &v)
+{
+    return ArithF32::Acc{__shfl_xor(v.P, 16), __shfl_xor(v.Q, 16)};
+}
+
 // One half of a check row, run-time length dh <= D, as the straight-line
 // body of length D: this lane owns dh edges of the row (the first half, or
 // the second), its partner lane the other half.  Slots j >= dh are
@@ -325,16 +337,14 @@ __device__ __forceinline__ void fused_row_dispatch(int hwave, const Row &row, in
     }
 }
 
-// One half of a check row under the layered schedule (Section II, Algorithm
-// 2): as fused_half_row, and the row's new messages update its variables'
-// posteriors at once, L_n = q_mn + r_mn.  No other row of the layer touches
-// these edges or variables, so the forward pass parks q_k in the variable's
-// own L slot and a_k in the edge's r slot; the backward pass reads both back
-// and writes r_new and q_k + r_new.  Dummy edges keep their messages in this
-// thread's dummy slot and their posterior in the +inf word, which their
-// writes (+inf, and +inf + r) leave unchanged; loads are issued first.
+// One quarter of a layered check row (Section II, Algorithm 2, with the
+// layered combination order of spa_math.h): as layered_half_row, over this
+// lane's quarter (run-time length dq <= D); the quarter combinations are
+// exchanged in two steps, with the sibling quarter (lane ^ 16) and then
+// between the halves (lane ^ 32), which gives every lane O_i in the same
+// association as the streaming layer kernel.
 template <class A, int D, class Row>
-__device__ __forceinline__ void layered_half_row(const Row &row, int dh, unsigned char *__restrict__ s, Slots sl)
+__device__ __forceinline__ void layered_quarter_row(const Row &row, int dq, unsigned char *__restrict__ s, Slots sl)
 {
     using T = typename A::T;
     typename A::Acc p[D];
@@ -344,7 +354,7 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int dh, unsigne
     uint32_t ri[D], ci[D];
 #pragma unroll
     for (int j = 0; j < D; ++j)
-        slot_offsets(row, j, j < dh, sl.dslot, sl.inf_off, ri[j], ci[j]);
+        slot_offsets(row, j, j < dq, sl.dslot, sl.inf_off, ri[j], ci[j]);
     T lv[D], rv[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -360,12 +370,14 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int dh, unsigne
         lds_st<T>(s, ri[j], A::park(a_k));
         lds_st<T>(s, ci[j], q);
     }
-    const typename A::Acc s_other = pair_swap(acc);
-    const uint32_t sign_total = sign ^ pair_swap(sign);
-    typename A::Acc sx = A::seed(s_other);
+    const typename A::Acc c_sib = quad_swap(acc);
+    const typename A::Acc c_other = pair_swap(A::merge(acc, c_sib));  // the other half's combination
+    typename A::Acc sx = A::seed(A::merge(c_sib, c_other));
+    const uint32_t sign_half = sign ^ quad_swap(sign);
+    const uint32_t sign_total = sign_half ^ pair_swap(sign_half);
 #pragma unroll
     for (int j = D - 1; j >= 0; --j) {
-        const bool real = j < dh;
+        const bool real = j < dq;
         const T parked = lds_ld<T>(s, ri[j]);  // a dummy's slot is valid; its value may be a later dummy's message
         const typename A::Term a_k = A::unpark(real ? parked : T(A::kDummyParked), kp[j]);
         const T r = check_backward<A>(a_k, p[j], sx, sign_total);
@@ -376,20 +388,28 @@ __device__ __forceinline__ void layered_half_row(const Row &row, int dh, unsigne
 }
 
 template <class A, int D, int DB, class Row>
-__device__ __forceinline__ void layered_row_dispatch(int hwave, const Row &row, int dh, unsigned char *__restrict__ s,
-                                                     Slots sl)
+__device__ __forceinline__ void layered_quarter_dispatch(int qwave, const Row &row, int dq,
+                                                         unsigned char *__restrict__ s, Slots sl)
 {
     constexpr bool exact = std::is_same<A, ArithF32>::value && std::is_same<Row, RowQC>::value;
     if constexpr (!exact) {
-        layered_half_row<A, DB>(row, dh, s, sl);
+        layered_quarter_row<A, DB>(row, dq, s, sl);
     } else if constexpr (D < DB) {
-        if (hwave == D)
-            layered_half_row<A, D>(row, dh, s, sl);
+        if (qwave == D)
+            layered_quarter_row<A, D>(row, dq, s, sl);
         else
-            layered_row_dispatch<A, D + 1, DB>(hwave, row, dh, s, sl);
+            layered_quarter_dispatch<A, D + 1, DB>(qwave, row, dq, s, sl);
     } else {
-        layered_half_row<A, DB>(row, dh, s, sl);
+        layered_quarter_row<A, DB>(row, dq, s, sl);
     }
+}
+
+// This lane's quarter of a row of degree d: its first position k0 and length.
+__device__ __forceinline__ void quarter_span(int32_t d, int part, int32_t &k0, int32_t &dq)
+{
+    const Quarters Q = quarters(d);
+    k0 = part == 0 ? 0 : part == 1 ? Q.q1 : part == 2 ? Q.h : Q.q3;
+    dq = (part == 0 ? Q.q1 : part == 1 ? Q.h : part == 2 ? Q.q3 : d) - k0;
 }
 
 // One half of a check row under the min-sum rule, flooding or (LAYERED)
@@ -694,41 +714,56 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
         it = 0;
     } else {
         for (int32_t t = 1; t <= job.max_iter; ++t) {
-                if (c.qc) {
+            // min-sum rows: two lanes each (32 rows per wavefront); sum-product
+            // rows: four lanes each (16 rows per wavefront)
+            const int rows_per_wave = ms ? 32 : 16;
+            const int part = lane >> 4;
+            if (c.qc) {
                 for (int32_t i = 0; i < c.mb; ++i) {
-                    for (int rb = wave * 32; rb < Z; rb += nwaves * 32) {
-                        const int r = rb + (lane & 31);
+                    for (int rb = wave * rows_per_wave; rb < Z; rb += nwaves * rows_per_wave) {
+                        const int r = rb + (lane & (rows_per_wave - 1));
                         if (r >= Z)
                             continue;
-                        int32_t d, k0, dh;
-                        const RowQC row = qc_half(i, r, d, k0, dh);
-                        if (d == 0)
-                            continue;
-                        const int32_t h = (d + 1) >> 1;
-                        if (ms)
-                            ms_half_row<A, DB / 2, true>(row, k0, dh, s, fv.slots, no_parity, ms_scale, ms_offset);
-                        else
-                            layered_row_dispatch<A, 1, DB / 2>(h, row, dh, s, fv.slots);
+                        if (ms) {
+                            int32_t d, k0, dh;
+                            const RowQC row = qc_half(i, r, d, k0, dh);
+                            if (d > 0)
+                                ms_half_row<A, DB / 2, true>(row, k0, dh, s, fv.slots, no_parity, ms_scale,
+                                                             ms_offset);
+                        } else {
+                            const int32_t b0 = rbs[i], d = rbs[i + 1] - b0;
+                            if (d == 0)
+                                continue;
+                            int32_t k0, dq;
+                            quarter_span(d, part, k0, dq);
+                            const RowQC row{TS * static_cast<uint32_t>(r), z_t,
+                                            fv.r0 + z_t * static_cast<uint32_t>(b0 + k0), pack + b0 + k0};
+                            layered_quarter_dispatch<A, 1, DB / 4>(quarters(d).q1, row, dq, s, fv.slots);
+                        }
                     }
                     __syncthreads();
                 }
             } else {
                 for (int32_t l = 0; l < c.nlayers; ++l) {
                     const int32_t row0 = c.layer_ptr[l], rows = c.layer_ptr[l + 1] - row0;
-                    for (int rb = wave * 32; rb < rows; rb += nwaves * 32) {
-                        const int slot = rb + (lane & 31);
+                    for (int rb = wave * rows_per_wave; rb < rows; rb += nwaves * rows_per_wave) {
+                        const int slot = rb + (lane & (rows_per_wave - 1));
                         if (slot >= rows)
                             continue;
                         const int32_t e0 = c.row_ptr[row0 + slot], d = c.row_ptr[row0 + slot + 1] - e0;
                         if (d == 0)
                             continue;
-                        const int32_t h = (d + 1) >> 1;
-                        const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
-                        const RowCSR<TS> row{fv.r0 + TS * static_cast<uint32_t>(e0 + k0), c.col_idx + e0 + k0};
-                        if (ms)
+                        if (ms) {
+                            const int32_t h = (d + 1) >> 1;
+                            const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
+                            const RowCSR<TS> row{fv.r0 + TS * static_cast<uint32_t>(e0 + k0), c.col_idx + e0 + k0};
                             ms_half_row<A, DB / 2, true>(row, k0, dh, s, fv.slots, no_parity, ms_scale, ms_offset);
-                        else
-                            layered_row_dispatch<A, 1, DB / 2>(h, row, dh, s, fv.slots);
+                        } else {
+                            int32_t k0, dq;
+                            quarter_span(d, part, k0, dq);
+                            const RowCSR<TS> row{fv.r0 + TS * static_cast<uint32_t>(e0 + k0), c.col_idx + e0 + k0};
+                            layered_quarter_dispatch<A, 1, DB / 4>(quarters(d).q1, row, dq, s, fv.slots);
+                        }
                     }
                     __syncthreads();
                 }

@@ -9,8 +9,9 @@
 // Consecutive rows that share no variable commute, so a maximal run of them
 // (a layer: a block-row of a QC code) is one launch, one wavefront per row and
 // 64 frames; within a layer every L_n is read and written by one row only.
-// The check rule is the flooding path's (same two-half exclusive
-// combinations, same arithmetic), so a row gives the same messages for the
+// The check rule is the flooding path's arithmetic with the layered
+// combination order (four quarters, spa_math.h), the one the fused kernel's
+// layered jobs use, so both layered paths give the same messages for the
 // same q.
 #pragma once
 
@@ -40,7 +41,7 @@ __device__ __forceinline__ void layer_row(const int32_t *__restrict__ cols, type
 {
     using T = typename A::T;
     constexpr bool kBuf = std::is_same<T, float>::value;  // posterior gathers and scatters by buffer access
-    constexpr int H = (D + 1) / 2;
+    constexpr Quarters Q = quarters(D);
     const __amdgpu_buffer_rsrc_t rsrc = chunk_rsrc(L, n);
     T q[D], rv[D];
 #pragma unroll
@@ -53,18 +54,19 @@ __device__ __forceinline__ void layer_row(const int32_t *__restrict__ cols, type
     }
     typename A::Term a[D];
     typename A::Acc p[D];
-    typename A::Acc acc0 = A::identity(), acc1 = A::identity();
+    typename A::Acc acc[4] = {A::identity(), A::identity(), A::identity(), A::identity()};
     uint32_t sign = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         if (!FIRST)
             q[k] = q[k] - rv[k];
-        check_forward<A>(q[k], a[k], p[k], k < H ? acc0 : acc1, sign);
+        check_forward<A>(q[k], a[k], p[k], acc[quarter_of(Q, k)], sign);
     }
-    typename A::Acc s0 = A::seed(acc1), s1 = A::seed(acc0);
+    typename A::Acc sx[4];
+    quarter_seeds<A>(acc, sx);
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) {
-        const T r = k < H ? check_backward<A>(a[k], p[k], s0, sign) : check_backward<A>(a[k], p[k], s1, sign);
+        const T r = check_backward<A>(a[k], p[k], sx[quarter_of(Q, k)], sign);
         st_lane_nt(Rrow + k * kChunk, off, r);
         if constexpr (kBuf)
             st_scatter(rsrc, off, cols[k], q[k] + r);
@@ -81,7 +83,7 @@ __device__ __forceinline__ void layer_row_guarded(const int32_t *__restrict__ co
                                                   uint32_t off)
 {
     using T = typename A::T;
-    const int h = (d + 1) / 2;
+    const Quarters Q = quarters(d);  // d is the wavefront's row's: the branches below are uniform
     T q[DMAX], rv[DMAX];
 #pragma unroll
     for (int k = 0; k < DMAX; ++k) {
@@ -92,25 +94,56 @@ __device__ __forceinline__ void layer_row_guarded(const int32_t *__restrict__ co
     }
     typename A::Term a[DMAX];
     typename A::Acc p[DMAX];
-    typename A::Acc acc0 = A::identity(), acc1 = A::identity();
+    // One running combination, closed into C[i] at each quarter boundary
+    // (quarters may be empty: their combination is the identity).
+    typename A::Acc C[4], cur = A::identity();
     uint32_t sign = 0;
 #pragma unroll
     for (int k = 0; k < DMAX; ++k) {
         if (k < d) {
+            if (k == Q.q1) {
+                C[0] = cur;
+                cur = A::identity();
+            }
+            if (k == Q.h) {
+                C[1] = cur;
+                cur = A::identity();
+            }
+            if (k == Q.q3) {
+                C[2] = cur;
+                cur = A::identity();
+            }
             if (!FIRST)
                 q[k] = q[k] - rv[k];
-            if (k < h)
-                check_forward<A>(q[k], a[k], p[k], acc0, sign);
-            else
-                check_forward<A>(q[k], a[k], p[k], acc1, sign);
+            check_forward<A>(q[k], a[k], p[k], cur, sign);
         }
     }
-    typename A::Acc s0 = A::seed(acc1), s1 = A::seed(acc0);
+    if (Q.q1 >= d) {
+        C[0] = cur;
+        cur = A::identity();
+    }
+    if (Q.h >= d) {
+        C[1] = cur;
+        cur = A::identity();
+    }
+    if (Q.q3 >= d) {
+        C[2] = cur;
+        cur = A::identity();
+    }
+    C[3] = cur;
+    typename A::Acc sx[4];
+    quarter_seeds<A>(C, sx);
+    typename A::Acc sq = sx[3];  // the running suffix, switched to each quarter's seed at its last edge
 #pragma unroll
     for (int k = DMAX - 1; k >= 0; --k) {
         if (k < d) {
-            const T r = k < h ? check_backward<A>(a[k], p[k], s0, sign)
-                              : check_backward<A>(a[k], p[k], s1, sign);
+            if (k == Q.q3 - 1)
+                sq = sx[2];
+            if (k == Q.h - 1)
+                sq = sx[1];
+            if (k == Q.q1 - 1)
+                sq = sx[0];
+            const T r = check_backward<A>(a[k], p[k], sq, sign);
             st_lane_nt(Rrow + k * kChunk, off, r);
             st_lane(L + cols[k] * kChunk, off, q[k] + r);
         }

@@ -187,6 +187,43 @@ struct ArithF64 {
 // half each, exchanging C and the sign) while the streaming kernels evaluate
 // the same expression in one lane, bit for bit.
 
+// Layered rows (Section II, Algorithm 2; both layered paths) split each half
+// once more, into quarters Q0 = [0, q1), Q1 = [q1, h), Q2 = [h, q3) and
+// Q3 = [q3, d), with h = ceil(d/2), q1 = ceil(h/2), q3 = h + ceil((d - h)/2).
+// For edge k in Qi, excl_k = merge(p_k, s_k) as above, with p_k the
+// combination of the earlier edges of Qi and s_k = seed(O_i) grown by its
+// later edges, where O_i combines the other three quarters (C_j, each left
+// to right) in this fixed association:
+//     O_0 = merge(C_1, merge(C_2, C_3))    O_1 = merge(C_0, merge(C_2, C_3))
+//     O_2 = merge(C_3, merge(C_0, C_1))    O_3 = merge(C_2, merge(C_0, C_1))
+// merge is commutative bit for bit (a product, and a (+) b, whose fused
+// multiply-add forms the exact product either way) but not associative.  The
+// fused kernel spreads a layered row over four lanes, one quarter each, which
+// halves the serial length of a layer step; the streaming layer kernel
+// evaluates the same expressions in one lane.
+struct Quarters {
+    int q1, h, q3;
+};
+__host__ __device__ constexpr Quarters quarters(int d)
+{
+    return Quarters{((d + 1) / 2 + 1) / 2, (d + 1) / 2, (d + 1) / 2 + (d - (d + 1) / 2 + 1) / 2};
+}
+__host__ __device__ constexpr int quarter_of(const Quarters &q, int k)
+{
+    return k < q.q1 ? 0 : k < q.h ? 1 : k < q.q3 ? 2 : 3;
+}
+
+// seed(O_i) for the four quarters from their combinations C.
+template <class A>
+__device__ __forceinline__ void quarter_seeds(const typename A::Acc C[4], typename A::Acc S[4])
+{
+    const typename A::Acc c01 = A::merge(C[0], C[1]), c23 = A::merge(C[2], C[3]);
+    S[0] = A::seed(A::merge(C[1], c23));
+    S[1] = A::seed(A::merge(C[0], c23));
+    S[2] = A::seed(A::merge(C[3], c01));
+    S[3] = A::seed(A::merge(C[2], c01));
+}
+
 // Forward step for an edge with incoming message q: its term a_k, p_k = the
 // half's running combination, which then grows by a_k.
 template <class A>
