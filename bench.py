@@ -363,12 +363,15 @@ def extra_workloads():
         if tune:
             L.ldpc_autotune_batch(cj, dtype, bws, bw)
             chosen = L.ldpc_batch_launch_config(cj, dtype)
+            per_job = L.ldpc_batch_job_threads(cj, dtype)
             tt = _time_ms(batched, reps)
             plan = L.Plan(jobs)
             tg = _time_ms(plan.launch, reps)
             plan.close()
+            L.ldpc_tuning_clear()  # later workloads are measured with the defaults
             res.update({"batch_tuned_ms": tt, "batch_tuned_mbps": bits / (tt * 1e-3) / 1e6,
-                        "tuned_threads": chosen["threads"], "tuned_frames_per_group": chosen["frames_per_group"],
+                        "tuned_threads": chosen["threads"], "tuned_threads_per_job": per_job,
+                        "tuned_frames_per_group": chosen["frames_per_group"],
                         "plan_replay_ms": tg, "plan_replay_mbps": bits / (tg * 1e-3) / 1e6,
                         "batch_tuned_floor": frac(tt)})
         return res
@@ -565,7 +568,10 @@ def _batch_ms(L, items, dtype, reps, tune=False):
     def run():
         if L.ldpc_decode_batch(cj, dtype, ws, nb) != 0:
             raise RuntimeError("ldpc_decode_batch failed")
-    return _time_ms(run, reps)
+    t = _time_ms(run, reps)
+    if tune:
+        L.ldpc_tuning_clear()  # later workloads are measured with the defaults
+    return t
 
 
 def copy_probe(mb):

@@ -383,8 +383,9 @@ void ldpc_server_destroy(ldpc_server server);
 /*
  * Workgroup size (a multiple of 64, at most 512) of the fused frame-resident
  * kernel used by ldpc_decode_batch (Section III-A: the threads that decode
- * one frame); default 512.  EINVAL for other values.  Process-wide setting (the
- * autotuner writes it); affects speed only, never results.
+ * one frame); default 512.  EINVAL for other values.  Process-wide default
+ * for jobs whose code has no tuned size (ldpc_autotune_batch records one per
+ * code; ldpc_tuning_clear forgets them); affects speed only, never results.
  */
 ldpc_status ldpc_batch_set_threads(int32_t threads);
 
@@ -400,30 +401,46 @@ ldpc_status ldpc_batch_set_threads(int32_t threads);
 ldpc_status ldpc_batch_set_frames_per_group(int32_t frames);
 
 /*
- * The launch configuration ldpc_decode_batch would use for these jobs: the
- * tuned one if ldpc_autotune_batch (or ldpc_tuning_load) recorded this batch
- * shape, else the process-wide defaults.  Any output may be NULL; *tuned is 1
- * for a tuned shape.  Errors as ldpc_decode_batch's argument checks.
+ * The launch configuration ldpc_decode_batch would use for these jobs: frames
+ * per workgroup as tuned for this batch shape by ldpc_autotune_batch (or
+ * ldpc_tuning_load), else the process-wide default; *threads the workgroup
+ * size of the first job that runs in the fused kernel (jobs of other codes
+ * may differ: ldpc_batch_job_threads gives each).  Any output may be NULL;
+ * *tuned is 1 for a tuned batch shape.  Errors as ldpc_decode_batch's
+ * argument checks.
  */
 ldpc_status ldpc_batch_launch_config(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, int32_t *threads,
                                      int32_t *frames_per_group, int32_t *tuned);
 
 /*
+ * Workgroup size each job would run with in the fused kernel
+ * (threads[njobs], caller-allocated; 0 for a job with no frames or one that
+ * runs on the plain path).  Jobs of different sizes run as separate fused
+ * launches on the same stream.  Errors as ldpc_decode_batch's argument
+ * checks; EINVAL if threads is NULL with njobs > 0.  (Library bookkeeping of
+ * the autotuner, Section III-A's mapping of frames onto the GPU.)
+ */
+ldpc_status ldpc_batch_job_threads(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, int32_t *threads);
+
+/*
  * Autotuner of the batch path (Section III-A: the mapping of frames onto the
- * GPU, chosen per batch shape).  Decodes the given batch (its output buffers
- * are overwritten, inputs untouched) once per candidate launch
- * configuration: workgroup sizes 64, 128, 192, 256, 384, 512 of the fused
- * kernel, each with one frame per workgroup and, where some job can use it,
- * two (ldpc_batch_set_frames_per_group); checks that every candidate gives
- * bit-identical outputs, times each (HIP events, 3 runs after a warm-up) and
- * records the fastest for this batch shape (device architecture, code shapes
- * by sizes and degree profiles, frame counts rounded up to a power of two,
- * iteration caps, flags, dtype); later ldpc_decode_batch calls of the same
- * shape use it.  Blocks until done.  *best_threads and *best_ms (may be NULL)
- * receive the choice's workgroup size and time (ldpc_batch_launch_config
- * gives the whole choice).  The workspace must hold
- * ldpc_batch_workspace_bytes (which covers every candidate).  LDPC_EDEVICE if
- * candidates disagree (then nothing is recorded).
+ * GPU).  Decodes the given jobs (their output buffers are overwritten,
+ * inputs untouched) under candidate launch configurations, in two stages:
+ * first, for each code (device architecture, code shape by sizes and degree
+ * profiles, dtype, flags), that code's jobs alone at workgroup sizes 64, 128,
+ * 192, 256, 384 and 512, recording the fastest size for the code (used by
+ * every later batch with jobs of that code); then the whole batch with one
+ * frame per workgroup and, where some job can use it, two
+ * (ldpc_batch_set_frames_per_group), recording the faster for this batch
+ * shape (the codes, frame counts rounded up to a power of two, iteration
+ * caps, flags, dtype).  Every candidate's outputs must be bit-identical to
+ * the first run's; each is timed with HIP events (3 runs after a warm-up).
+ * Blocks until done.  *best_threads and *best_ms (may be NULL) receive the
+ * first fused job's workgroup size and the batch's time
+ * (ldpc_batch_launch_config and ldpc_batch_job_threads give the whole
+ * choice).  The workspace must hold ldpc_batch_workspace_bytes (which covers
+ * every candidate).  LDPC_EDEVICE if candidates disagree (then nothing is
+ * recorded for these codes and this shape).
  */
 ldpc_status ldpc_autotune_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, void *workspace,
                                 size_t workspace_bytes, void *stream, int32_t *best_threads, double *best_ms);
@@ -431,15 +448,18 @@ ldpc_status ldpc_autotune_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype 
 /*
  * The tuning table on disk (library bookkeeping of the autotuner above): save
  * writes every recorded choice, one text line each ("<arch> <key> <threads>
- * <frames per workgroup> <ms>", the key being the hash of the batch shape,
- * device architecture included); load merges a saved table into the
- * process's (*entries, may be NULL, receives the number of lines read), so a
- * later process skips tuning for shapes already tuned on that architecture.
- * EINVAL if the file cannot be opened or a line is malformed (load keeps the
- * lines read before it).
+ * <frames per workgroup> <ms>", the key being the hash of the batch shape or,
+ * for a per-code workgroup size, of the code, device architecture included;
+ * per-code lines have frames per workgroup 0); load merges a saved table
+ * into the process's (*entries, may be NULL, receives the number of lines
+ * read), so a later process skips tuning for shapes already tuned on that
+ * architecture.  EINVAL if the file cannot be opened or a line is malformed
+ * (load keeps the lines read before it).  clear forgets every recorded
+ * choice (the process-wide defaults apply again).
  */
 ldpc_status ldpc_tuning_save(const char *path);
 ldpc_status ldpc_tuning_load(const char *path, int32_t *entries);
+void ldpc_tuning_clear(void);
 
 /*
  * Whether frames of `code` in `dtype` can run in the fused frame-resident

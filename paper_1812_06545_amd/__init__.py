@@ -100,6 +100,8 @@ _sig("ldpc_batch_set_frames_per_group", ctypes.c_int, [_I32])
 _sig("ldpc_batch_launch_config", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, ctypes.POINTER(_I32),
                                                 ctypes.POINTER(_I32), ctypes.POINTER(_I32)])
 _sig("ldpc_tuning_save", ctypes.c_int, [ctypes.c_char_p])
+_sig("ldpc_tuning_clear", None, [])
+_sig("ldpc_batch_job_threads", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, ctypes.POINTER(_I32)])
 _sig("ldpc_tuning_load", ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_I32)])
 _sig("ldpc_autotune_batch", ctypes.c_int, [ctypes.POINTER(ldpc_job), _I32, ctypes.c_int, _P, ctypes.c_size_t, _P,
                                            ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double)])
@@ -327,6 +329,18 @@ def ldpc_batch_launch_config(jobs, dtype):
     _check(_lib.ldpc_batch_launch_config(arr, len(jobs), _dtype_code(dtype), ctypes.byref(t), ctypes.byref(f),
                                          ctypes.byref(tu)), "ldpc_batch_launch_config")
     return {"threads": t.value, "frames_per_group": f.value, "tuned": bool(tu.value)}
+
+
+def ldpc_batch_job_threads(jobs, dtype):
+    """-> list of the fused workgroup size of each job (0: no frames, or the plain path)."""
+    arr = _jobs_array(jobs)
+    out = (_I32 * max(len(jobs), 1))()
+    _check(_lib.ldpc_batch_job_threads(arr, len(jobs), _dtype_code(dtype), out), "ldpc_batch_job_threads")
+    return [out[i] for i in range(len(jobs))]
+
+
+def ldpc_tuning_clear():
+    _lib.ldpc_tuning_clear()
 
 
 def ldpc_tuning_save(path) -> int:

@@ -33,6 +33,7 @@ struct Tuned {
     double ms = 0.0;
 };
 std::map<uint64_t, Tuned> g_tuned;      // batch shape key -> configuration chosen by ldpc_autotune_batch
+std::map<uint64_t, Tuned> g_code_tuned; // code key -> workgroup size chosen for its jobs (fpw unused: 0)
 
 constexpr int kMaxArchDevices = 64;
 uint64_t g_arch_hash[kMaxArchDevices];  // per device: hash of its architecture name, 0 until looked up
@@ -91,6 +92,30 @@ uint64_t shape_key(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt)
         x = fnv(x, jobs[i].flags);
     }
     return x;
+}
+
+// Key of one job's code for the per-code workgroup size: device
+// architecture, dtype, the code's shape and the job's flags (the decoding
+// mode selects the kernel body).  Caller holds g_mu.
+uint64_t code_key(const ldpc_job &j, ldpc_dtype dt)
+{
+    uint64_t arch = 0;
+    arch_of_current(&arch);
+    uint64_t x = fnv(fnv(1099511628211ull, arch), 0xc0de);
+    x = fnv(x, static_cast<uint64_t>(dt));
+    x = fnv(x, j.code->shape_hash);
+    return fnv(x, j.flags);
+}
+
+// Workgroup size of one job's fused launch: its code's tuned size, else the
+// batch's.
+int job_threads(const ldpc_job &j, ldpc_dtype dt, int batch_threads)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_code_tuned.empty())
+        return batch_threads;
+    auto it = g_code_tuned.find(code_key(j, dt));
+    return it != g_code_tuned.end() ? it->second.cfg.threads : batch_threads;
 }
 
 LaunchCfg cfg_for(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt)
@@ -152,7 +177,8 @@ FusedFit fused_fit(const ldpc_code_s *c, ldpc_dtype dt, size_t limit)
 // One fused launch: up to kMaxJobs jobs over up to kMaxCodes codes (fixed
 // storage, so planning needs no heap).
 struct Group {
-    int fpw = 1;  // frames per workgroup of this launch
+    int fpw = 1;        // frames per workgroup of this launch
+    int threads = 512;  // workgroup size of this launch
     int32_t njobs = 0, ncodes = 0;
     int32_t jobs[fused::kMaxJobs];
     const ldpc_code_s *codes[fused::kMaxCodes];
@@ -198,48 +224,71 @@ int job_fpw(const ldpc_job &j, ldpc_dtype dt, int fpw_pref, size_t limit)
     return two <= limit ? 2 : 1;
 }
 
-// Greedy packing of the fusable jobs, in order, into launch groups (at most
-// max_groups); consecutive jobs share a group while they run with the same
-// frames per workgroup (job_fpw of fpw_pref).  Jobs whose code does not fit
-// go to plain[] (*nplain of them), or, with plain == nullptr, make the plan
-// fail.  Returns the group count or kPlanNotFused / kPlanTooMany.
-int plan(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, int fpw_pref, Group *groups, int max_groups,
+// Packing of the fusable jobs into launch groups (at most max_groups): jobs
+// that run with the same frames per workgroup (job_fpw of cfg.fpw) and the
+// same workgroup size (job_threads) form a class; classes are packed in the
+// order of their first job, the jobs of a class in job order, and a group
+// closes at kMaxJobs jobs, at kMaxCodes codes, or when one more code would
+// not fit its LDS.  Jobs whose code does not fit go to plain[] (*nplain of
+// them), or, with plain == nullptr, make the plan fail.  Returns the group
+// count or kPlanNotFused / kPlanTooMany.  Allocates nothing.
+int plan(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, const LaunchCfg &cfg, Group *groups, int max_groups,
          int32_t *plain, int32_t *nplain)
 {
     const size_t limit = lds_limit();
     const size_t tsize = dt == LDPC_F64 ? sizeof(double) : sizeof(float);
-    int ng = 0;
+    constexpr int kMaxClasses = 2 * 8;  // frames per workgroup 1, 2 x workgroup sizes 64 .. 512
+    int cls_fpw[kMaxClasses], cls_threads[kMaxClasses], ncls = 0;
     if (nplain)
         *nplain = 0;
     for (int32_t i = 0; i < njobs; ++i) {
         if (jobs[i].frames == 0)
             continue;
-        const FusedFit fit = fused_fit(jobs[i].code, dt, limit);
-        if (!fit.ok) {
+        if (!fused_fit(jobs[i].code, dt, limit).ok) {
             if (!plain)
                 return kPlanNotFused;
             plain[(*nplain)++] = i;
             continue;
         }
-        const int fpw = job_fpw(jobs[i], dt, fpw_pref, limit);
-        bool need_new = ng == 0 || groups[ng - 1].njobs == fused::kMaxJobs || groups[ng - 1].fpw != fpw;
-        if (!need_new && groups[ng - 1].code_index(jobs[i].code) < 0) {
-            Group trial = groups[ng - 1];
-            trial.add_code(jobs[i].code);
-            need_new = groups[ng - 1].ncodes == fused::kMaxCodes || trial.lds() > limit;
+        const int fpw = job_fpw(jobs[i], dt, cfg.fpw, limit), threads = job_threads(jobs[i], dt, cfg.threads);
+        int c = 0;
+        while (c < ncls && (cls_fpw[c] != fpw || cls_threads[c] != threads))
+            ++c;
+        if (c == ncls) {
+            cls_fpw[ncls] = fpw;
+            cls_threads[ncls++] = threads;
         }
-        if (need_new) {
-            if (ng == max_groups)
-                return kPlanTooMany;
-            groups[ng++] = Group{};
-            groups[ng - 1].tsize = tsize;
-            groups[ng - 1].fpw = fpw;
+    }
+    int ng = 0;
+    for (int c = 0; c < ncls; ++c) {
+        const int first = ng;  // a job joins only the last group of its own class
+        for (int32_t i = 0; i < njobs; ++i) {
+            if (jobs[i].frames == 0)
+                continue;
+            const FusedFit fit = fused_fit(jobs[i].code, dt, limit);
+            if (!fit.ok || job_fpw(jobs[i], dt, cfg.fpw, limit) != cls_fpw[c] ||
+                job_threads(jobs[i], dt, cfg.threads) != cls_threads[c])
+                continue;
+            bool need_new = ng == first || groups[ng - 1].njobs == fused::kMaxJobs;
+            if (!need_new && groups[ng - 1].code_index(jobs[i].code) < 0) {
+                Group trial = groups[ng - 1];
+                trial.add_code(jobs[i].code);
+                need_new = groups[ng - 1].ncodes == fused::kMaxCodes || trial.lds() > limit;
+            }
+            if (need_new) {
+                if (ng == max_groups)
+                    return kPlanTooMany;
+                groups[ng++] = Group{};
+                groups[ng - 1].tsize = tsize;
+                groups[ng - 1].fpw = cls_fpw[c];
+                groups[ng - 1].threads = cls_threads[c];
+            }
+            Group &g = groups[ng - 1];
+            g.jobs[g.njobs++] = i;
+            if (g.code_index(jobs[i].code) < 0)
+                g.add_code(jobs[i].code);
+            g.bucket = std::max(g.bucket, fit.bucket);
         }
-        Group &g = groups[ng - 1];
-        g.jobs[g.njobs++] = i;
-        if (g.code_index(jobs[i].code) < 0)
-            g.add_code(jobs[i].code);
-        g.bucket = std::max(g.bucket, fit.bucket);
     }
     return ng;
 }
@@ -429,26 +478,28 @@ struct FullPlan {
     std::vector<int32_t> plain;
     int ngroups = 0;
     int32_t nplain = 0;
-    void make(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, int fpw)
+    void make(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, const LaunchCfg &cfg)
     {
         groups.resize(std::max(njobs, 1));
         plain.resize(std::max(njobs, 1));
-        ngroups = plan(jobs, njobs, dtype, fpw, groups.data(), static_cast<int>(groups.size()), plain.data(),
+        ngroups = plan(jobs, njobs, dtype, cfg, groups.data(), static_cast<int>(groups.size()), plain.data(),
                        &nplain);
     }
 };
 
-// Workspace of a batch under either frames-per-workgroup choice (the
-// autotuner tries both in the caller's workspace).
+// Workspace of a batch under any launch configuration (the autotuner tries
+// them in the caller's workspace, and tuning may split a batch into more
+// launches later): one group table per fused job at most, and the plain
+// path's largest workspace.
 size_t batch_bytes_any(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype)
 {
-    size_t need = 0;
-    for (int fpw : {1, 2}) {
-        FullPlan p;
-        p.make(jobs, njobs, dtype, fpw);
-        need = std::max(need, batch_bytes(jobs, p.ngroups, p.plain.data(), p.nplain, dtype));
-    }
-    return need;
+    FullPlan p;
+    p.make(jobs, njobs, dtype, LaunchCfg{});
+    int32_t fused_jobs = 0;
+    for (int32_t i = 0; i < njobs; ++i)
+        fused_jobs += jobs[i].frames > 0 ? 1 : 0;
+    fused_jobs -= p.nplain;
+    return static_cast<size_t>(fused_jobs) * kGroupBytes + batch_bytes(jobs, 0, p.plain.data(), p.nplain, dtype);
 }
 
 }  // namespace
@@ -475,7 +526,7 @@ try {
         return st;
     const LaunchCfg cfg = cfg_for(jobs, njobs, dtype);
     FullPlan p;
-    p.make(jobs, njobs, dtype, cfg.fpw);
+    p.make(jobs, njobs, dtype, cfg);
     const size_t need = batch_bytes(jobs, p.ngroups, p.plain.data(), p.nplain, dtype);
     if (need == 0)
         return LDPC_OK;
@@ -485,8 +536,8 @@ try {
     char *ws = static_cast<char *>(workspace);
     for (int gi = 0; gi < p.ngroups; ++gi) {
         const Group &g = p.groups[gi];
-        const ldpc_status r = dtype == LDPC_F64 ? launch_group<ArithF64>(jobs, g, ws, cfg.threads, s, true)
-                                                : launch_group<ArithF32>(jobs, g, ws, cfg.threads, s, true);
+        const ldpc_status r = dtype == LDPC_F64 ? launch_group<ArithF64>(jobs, g, ws, g.threads, s, true)
+                                                : launch_group<ArithF32>(jobs, g, ws, g.threads, s, true);
         if (r != LDPC_OK)
             return r;
         ws += kGroupBytes;
@@ -511,7 +562,7 @@ try {
         return st;
     const LaunchCfg cfg = cfg_for(jobs, njobs, dtype);
     Group groups[LDPC_NOALLOC_MAX_GROUPS];
-    const int ng = plan(jobs, njobs, dtype, cfg.fpw, groups, LDPC_NOALLOC_MAX_GROUPS, nullptr, nullptr);
+    const int ng = plan(jobs, njobs, dtype, cfg, groups, LDPC_NOALLOC_MAX_GROUPS, nullptr, nullptr);
     if (ng < 0)
         return LDPC_EUNSUPPORTED;  // a code too large for the fused kernel, or more groups than the scratch holds
     if (ng == 0)
@@ -522,8 +573,9 @@ try {
         return sc;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     for (int gi = 0; gi < ng; ++gi) {
-        const ldpc_status r = dtype == LDPC_F64 ? launch_group<ArithF64>(jobs, groups[gi], ws, cfg.threads, s, false)
-                                                : launch_group<ArithF32>(jobs, groups[gi], ws, cfg.threads, s, false);
+        const ldpc_status r = dtype == LDPC_F64
+                                  ? launch_group<ArithF64>(jobs, groups[gi], ws, groups[gi].threads, s, false)
+                                  : launch_group<ArithF32>(jobs, groups[gi], ws, groups[gi].threads, s, false);
         if (r != LDPC_OK)
             return r;
         ws += kGroupBytes;
@@ -561,25 +613,64 @@ try {
     const ldpc_status st = validate_jobs(jobs, njobs, dtype);
     if (st != LDPC_OK)
         return st;
-    std::lock_guard<std::mutex> lk(g_mu);
-    LaunchCfg cfg = g_cfg;
-    auto it = g_tuned.find(shape_key(jobs, njobs, dtype));
-    if (it != g_tuned.end())
-        cfg = it->second.cfg;
+    LaunchCfg cfg;
+    bool found = false;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        cfg = g_cfg;
+        auto it = g_tuned.find(shape_key(jobs, njobs, dtype));
+        found = it != g_tuned.end();
+        if (found)
+            cfg = it->second.cfg;
+    }
+    int t = cfg.threads;
+    const size_t limit = lds_limit();
+    for (int32_t i = 0; i < njobs; ++i)
+        if (jobs[i].frames > 0 && fused_fit(jobs[i].code, dtype, limit).ok) {
+            t = job_threads(jobs[i], dtype, cfg.threads);
+            break;
+        }
     if (threads)
-        *threads = cfg.threads;
+        *threads = t;
     if (frames_per_group)
         *frames_per_group = cfg.fpw;
     if (tuned)
-        *tuned = it != g_tuned.end();
+        *tuned = found;
     return LDPC_OK;
 } catch (...) {
     return ldpc::status_of_exception();
 }
 
+extern "C" ldpc_status ldpc_batch_job_threads(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, int32_t *threads)
+try {
+    const ldpc_status st = validate_jobs(jobs, njobs, dtype);
+    if (st != LDPC_OK)
+        return st;
+    if (njobs > 0 && !threads)
+        return LDPC_EINVAL;
+    const LaunchCfg cfg = cfg_for(jobs, njobs, dtype);
+    const size_t limit = lds_limit();
+    for (int32_t i = 0; i < njobs; ++i)
+        threads[i] = jobs[i].frames > 0 && fused_fit(jobs[i].code, dtype, limit).ok
+                         ? job_threads(jobs[i], dtype, cfg.threads)
+                         : 0;
+    return LDPC_OK;
+} catch (...) {
+    return ldpc::status_of_exception();
+}
+
+extern "C" void ldpc_tuning_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tuned.clear();
+    g_code_tuned.clear();
+}
+
 // Tuning file: one line per entry, "<arch> <key> <threads> <frames per
-// workgroup> <ms>", key in hex.  Entries of another architecture keep their
-// line but, their key including the architecture, never match here.
+// workgroup> <ms>", key in hex; a per-code entry (workgroup size of one
+// code's jobs) has frames per workgroup 0.  Entries of another architecture
+// keep their line but, their key including the architecture, never match
+// here.
 extern "C" ldpc_status ldpc_tuning_save(const char *path)
 try {
     if (!path)
@@ -590,9 +681,11 @@ try {
     FILE *f = std::fopen(path, "w");
     if (!f)
         return LDPC_EINVAL;
-    for (const auto &e : g_tuned)
-        std::fprintf(f, "%s %016llx %d %d %.6f\n", name[0] ? name : "unknown",
-                     static_cast<unsigned long long>(e.first), e.second.cfg.threads, e.second.cfg.fpw, e.second.ms);
+    for (const auto *table : {&g_tuned, &g_code_tuned})
+        for (const auto &e : *table)
+            std::fprintf(f, "%s %016llx %d %d %.6f\n", name[0] ? name : "unknown",
+                         static_cast<unsigned long long>(e.first), e.second.cfg.threads, e.second.cfg.fpw,
+                         e.second.ms);
     return std::fclose(f) == 0 ? LDPC_OK : LDPC_EINVAL;
 } catch (...) {
     return ldpc::status_of_exception();
@@ -616,7 +709,7 @@ try {
         const int got = std::fscanf(f, "%127s %llx %d %d %lf", arch, &key, &threads, &fpw, &ms);
         if (got == EOF)
             break;
-        if (got != 5 || threads < 64 || threads > 512 || threads % 64 != 0 || (fpw != 1 && fpw != 2)) {
+        if (got != 5 || threads < 64 || threads > 512 || threads % 64 != 0 || fpw < 0 || fpw > 2) {
             rc = LDPC_EINVAL;  // malformed: the entries read so far are kept
             break;
         }
@@ -624,7 +717,7 @@ try {
         t.cfg.threads = threads;
         t.cfg.fpw = fpw;
         t.ms = ms;
-        g_tuned[static_cast<uint64_t>(key)] = t;
+        (fpw == 0 ? g_code_tuned : g_tuned)[static_cast<uint64_t>(key)] = t;
         ++count;
     }
     std::fclose(f);
@@ -674,6 +767,46 @@ ldpc_status snapshot(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt, hipStre
 
 }  // namespace
 
+namespace {
+
+// Times `reps` decodes of a batch after one warm-up whose outputs are
+// checked against `ref` (taken from this warm-up when ref is empty).
+ldpc_status time_candidate(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, void *workspace,
+                           size_t workspace_bytes, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                           std::vector<char> &ref, std::vector<char> &cur, double &ms_out)
+{
+    constexpr int kReps = 3;
+    ldpc_status rc = ldpc_decode_batch(jobs, njobs, dtype, workspace, workspace_bytes, s);
+    if (rc == LDPC_OK)
+        rc = snapshot(jobs, njobs, dtype, s, cur);
+    if (rc != LDPC_OK)
+        return rc;
+    if (ref.empty())
+        ref = cur;
+    else if (ref.size() != cur.size() || std::memcmp(ref.data(), cur.data(), ref.size()) != 0)
+        return LDPC_EDEVICE;  // a launch shape changed the results: never expected, refuse to tune
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < kReps && rc == LDPC_OK; ++r)
+        rc = ldpc_decode_batch(jobs, njobs, dtype, workspace, workspace_bytes, s);
+    (void)hipEventRecord(e1, s);
+    float ms = 0.f;
+    if (rc != LDPC_OK)
+        return rc;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        return LDPC_EDEVICE;
+    ms_out = ms / kReps;
+    return LDPC_OK;
+}
+
+}  // namespace
+
+// Two stages.  Per code (device architecture, shape, dtype, flags): the jobs
+// of that code alone, at each workgroup size; the fastest is recorded for
+// the code and used by every later batch (small codes keep more frames per
+// CU in flight with smaller workgroups, large ones decode each frame faster
+// with larger ones; jobs of different sizes run as separate launches).  Per
+// batch shape: frames per workgroup 1, and 2 where some job can use it, with
+// the per-code sizes.  Every candidate's outputs must equal the first run's.
 extern "C" ldpc_status ldpc_autotune_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dtype, void *workspace,
                                            size_t workspace_bytes, void *stream, int32_t *best_threads,
                                            double *best_ms)
@@ -683,75 +816,104 @@ try {
         return st;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     static const int kThreads[] = {64, 128, 192, 256, 384, 512};
+    const size_t limit = lds_limit();
     uint64_t key = 0;
+    int default_threads = 512;
+    std::vector<uint64_t> ckeys;
+    std::vector<std::vector<ldpc_job>> subs;
+    int fpw_max = 1;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         key = shape_key(jobs, njobs, dtype);
+        default_threads = g_cfg.threads;
+        for (int32_t i = 0; i < njobs; ++i) {
+            if (jobs[i].frames == 0 || !fused_fit(jobs[i].code, dtype, limit).ok)
+                continue;
+            if (job_fpw(jobs[i], dtype, 2, limit) == 2)
+                fpw_max = 2;
+            const uint64_t ck = code_key(jobs[i], dtype);
+            size_t c = 0;
+            while (c < ckeys.size() && ckeys[c] != ck)
+                ++c;
+            if (c == ckeys.size()) {
+                ckeys.push_back(ck);
+                subs.emplace_back();
+            }
+            subs[c].push_back(jobs[i]);
+        }
     }
-    // frames per workgroup: 2 only where some job would run with it
-    int fpw_max = 1;
-    const size_t limit = lds_limit();
-    for (int32_t i = 0; i < njobs; ++i)
-        if (jobs[i].frames > 0 && fused_fit(jobs[i].code, dtype, limit).ok && job_fpw(jobs[i], dtype, 2, limit) == 2)
-            fpw_max = 2;
-    std::vector<char> ref, cur;
-    LaunchCfg best;
-    double best_t = 0.0;
-    bool have = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0)
+            (void)hipEventDestroy(e0);
         return LDPC_EDEVICE;
+    }
+    std::vector<char> ref, cur;
     ldpc_status rc = LDPC_OK;
-    for (int fpw = 1; fpw <= fpw_max && rc == LDPC_OK; ++fpw) {
+    // stage 1: workgroup size per code
+    for (size_t c = 0; c < ckeys.size() && rc == LDPC_OK; ++c) {
+        std::vector<char> cref;
+        int best_t = 0;
+        double best = 0.0;
         for (int threads : kThreads) {
-            LaunchCfg cand;
-            cand.threads = threads;
-            cand.fpw = fpw;
             {
                 std::lock_guard<std::mutex> lk(g_mu);
-                g_tuned[key] = Tuned{cand, 0.0};
+                g_code_tuned[ckeys[c]] = Tuned{LaunchCfg{threads, 0}, 0.0};
             }
-            rc = ldpc_decode_batch(jobs, njobs, dtype, workspace, workspace_bytes, stream);  // warm-up
+            double ms = 0.0;
+            rc = time_candidate(subs[c].data(), static_cast<int32_t>(subs[c].size()), dtype, workspace,
+                                workspace_bytes, s, e0, e1, cref, cur, ms);
             if (rc != LDPC_OK)
                 break;
-            rc = snapshot(jobs, njobs, dtype, s, cur);
-            if (rc != LDPC_OK)
-                break;
-            if (ref.empty())
-                ref = cur;
-            else if (ref.size() != cur.size() || std::memcmp(ref.data(), cur.data(), ref.size()) != 0) {
-                rc = LDPC_EDEVICE;  // a launch shape changed the results: never expected, refuse to tune
-                break;
+            if (best_t == 0 || ms < best) {
+                best_t = threads;
+                best = ms;
             }
-            constexpr int kReps = 3;
-            (void)hipEventRecord(e0, s);
-            for (int r = 0; r < kReps && rc == LDPC_OK; ++r)
-                rc = ldpc_decode_batch(jobs, njobs, dtype, workspace, workspace_bytes, stream);
-            (void)hipEventRecord(e1, s);
-            float ms = 0.f;
-            if (rc != LDPC_OK || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                rc = rc == LDPC_OK ? LDPC_EDEVICE : rc;
-                break;
-            }
-            const double t = ms / kReps;
-            if (!have || t < best_t) {
-                best = cand;
-                best_t = t;
-                have = true;
-            }
+        }
+        if (rc == LDPC_OK) {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_code_tuned[ckeys[c]] = Tuned{LaunchCfg{best_t, 0}, best};
+        }
+    }
+    // stage 2: frames per workgroup for the whole batch
+    LaunchCfg best_cfg{default_threads, 1};
+    double best_t = 0.0;
+    bool have = false;
+    for (int fpw = 1; fpw <= fpw_max && rc == LDPC_OK; ++fpw) {
+        const LaunchCfg cand{default_threads, fpw};
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_tuned[key] = Tuned{cand, 0.0};
+        }
+        double ms = 0.0;
+        rc = time_candidate(jobs, njobs, dtype, workspace, workspace_bytes, s, e0, e1, ref, cur, ms);
+        if (rc == LDPC_OK && (!have || ms < best_t)) {
+            best_cfg = cand;
+            best_t = ms;
+            have = true;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    std::lock_guard<std::mutex> lk(g_mu);
     if (rc != LDPC_OK || !have) {
+        std::lock_guard<std::mutex> lk(g_mu);
         g_tuned.erase(key);
+        for (const uint64_t ck : ckeys)
+            g_code_tuned.erase(ck);
         return rc != LDPC_OK ? rc : LDPC_EDEVICE;
     }
-    g_tuned[key] = Tuned{best, best_t};
-    if (best_threads)
-        *best_threads = best.threads;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tuned[key] = Tuned{best_cfg, best_t};
+    }
+    if (best_threads) {
+        *best_threads = best_cfg.threads;
+        for (int32_t i = 0; i < njobs; ++i)
+            if (jobs[i].frames > 0 && fused_fit(jobs[i].code, dtype, limit).ok) {
+                *best_threads = job_threads(jobs[i], dtype, best_cfg.threads);
+                break;
+            }
+    }
     if (best_ms)
         *best_ms = best_t;
     return LDPC_OK;

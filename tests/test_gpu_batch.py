@@ -196,6 +196,7 @@ def test_fused_noiseless_zero_iterations(L):
 def test_fused_threads_do_not_change_results(L, threads):
     b = configs.qc_mix(total=200)
     items = [(L.Code.from_workload(m.code), m.llr) for m in b[:4]]
+    L.ldpc_tuning_clear()  # no tuned per-code size may override the one set here
     assert L.ldpc_batch_set_threads(threads) == 0
     try:
         got = [_np(j) for j in _batch(L, items)]
@@ -218,6 +219,7 @@ def test_fused_early_stop_many_rows_per_lane(L, threads):
     from mapref import dense_syndrome
     mix = configs.qc_mix(total=2000)
     items = [(L.Code.from_workload(m.code), m.llr) for m in mix]
+    L.ldpc_tuning_clear()
     assert L.ldpc_batch_set_threads(threads) == 0
     try:
         jobs = _batch(L, items)
@@ -268,10 +270,16 @@ def test_autotune_keeps_results(L):
     items = [(L.Code.from_workload(m.code), m.llr) for m in mix]
     before = [_np(j) for j in _batch(L, items)]
     jobs = [L.Job(h, torch.from_numpy(llr).cuda(), 10, early_stop=True) for h, llr in items]
-    threads, ms = L.autotune_batch(jobs)
-    _log(f"[gpu] autotune: threads={threads} ms={ms:.3f}")
-    assert threads in (64, 128, 192, 256, 384, 512) and ms > 0
-    after = [_np(j) for j in _batch(L, items)]
-    for b, a in zip(before, after):
-        for x, y in zip(b, a):
-            assert np.array_equal(x, y)
+    try:
+        threads, ms = L.autotune_batch(jobs)
+        per_job = L.ldpc_batch_job_threads([j.c_struct() for j in jobs], torch.float32)
+        _log(f"[gpu] autotune: threads={threads} ms={ms:.3f} per code={per_job}")
+        assert threads in (64, 128, 192, 256, 384, 512) and ms > 0
+        assert all(t in (64, 128, 192, 256, 384, 512) for t in per_job) and threads == per_job[0]
+        # a batch of these codes now runs as one launch per workgroup size, with the same results
+        after = [_np(j) for j in _batch(L, items)]
+        for b, a in zip(before, after):
+            for x, y in zip(b, a):
+                assert np.array_equal(x, y)
+    finally:
+        L.ldpc_tuning_clear()

@@ -105,20 +105,31 @@ def test_autotune_chooses_and_persists(L, tmp_path):
     hs = [L.Code.from_workload(m.code) for m in mix]
     jobs = [L.Job(h, torch.from_numpy(m.llr).cuda(), 10, early_stop=True) for h, m in zip(hs, mix)]
     cj = [j.c_struct() for j in jobs]
-    threads, ms = L.autotune_batch(jobs)
-    cfg = L.ldpc_batch_launch_config(cj, torch.float32)
-    _log(f"[gpu] autotune: {cfg}, {ms:.3f} ms")
-    assert cfg["tuned"] and cfg["threads"] == threads and cfg["frames_per_group"] in (1, 2)
-    path = tmp_path / "tune.txt"
-    assert L.ldpc_tuning_save(str(path)) == L.LDPC_OK
-    lines = path.read_text().splitlines()
-    assert lines and all(len(line.split()) == 5 for line in lines)
-    st, n = L.ldpc_tuning_load(str(path))
-    assert st == L.LDPC_OK and n == len(lines)
-    assert L.ldpc_batch_launch_config(cj, torch.float32) == cfg
-    # a later decode of the same shape uses the choice and gives the same outputs
-    ref = [(j.bits.clone(), j.iters.clone()) for j in jobs]
-    L.decode_batch(jobs)
-    torch.cuda.synchronize()
-    for (b0, i0), j in zip(ref, jobs):
-        assert torch.equal(b0, j.bits) and torch.equal(i0, j.iters)
+    L.ldpc_tuning_clear()
+    try:
+        threads, ms = L.autotune_batch(jobs)
+        cfg = L.ldpc_batch_launch_config(cj, torch.float32)
+        per_job = L.ldpc_batch_job_threads(cj, torch.float32)
+        _log(f"[gpu] autotune: {cfg}, per code {per_job}, {ms:.3f} ms")
+        assert cfg["tuned"] and cfg["threads"] == threads == per_job[0] and cfg["frames_per_group"] in (1, 2)
+        path = tmp_path / "tune.txt"
+        assert L.ldpc_tuning_save(str(path)) == L.LDPC_OK
+        lines = path.read_text().splitlines()
+        assert all(len(line.split()) == 5 for line in lines)
+        fpw_fields = [int(line.split()[3]) for line in lines]
+        assert fpw_fields.count(0) == 4 and len(fpw_fields) == 5  # one line per code, one for the batch
+        L.ldpc_tuning_clear()
+        assert not L.ldpc_batch_launch_config(cj, torch.float32)["tuned"]
+        assert L.ldpc_batch_job_threads(cj, torch.float32) == [512] * 4
+        st, n = L.ldpc_tuning_load(str(path))
+        assert st == L.LDPC_OK and n == len(lines)
+        assert L.ldpc_batch_launch_config(cj, torch.float32) == cfg
+        assert L.ldpc_batch_job_threads(cj, torch.float32) == per_job
+        # a later decode of the same shape uses the choice and gives the same outputs
+        ref = [(j.bits.clone(), j.iters.clone()) for j in jobs]
+        L.decode_batch(jobs)
+        torch.cuda.synchronize()
+        for (b0, i0), j in zip(ref, jobs):
+            assert torch.equal(b0, j.bits) and torch.equal(i0, j.iters)
+    finally:
+        L.ldpc_tuning_clear()
