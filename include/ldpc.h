@@ -240,7 +240,8 @@ ldpc_status ldpc_decode_batch(const ldpc_job *jobs, int32_t njobs, ldpc_dtype dt
  * device or the host, and creates no events (ldpc_profile_* does not time
  * it).  Every job's code must fit the fused kernel (ldpc_batch_fits_fused)
  * and the jobs must pack into at most LDPC_NOALLOC_MAX_GROUPS launches (24
- * jobs and 16 codes per launch, fewer if the codes' LDS needs add up);
+ * jobs and 16 codes per launch, fewer if the codes' LDS needs add up, and
+ * one launch per tuned workgroup size and frames per workgroup among them);
  * otherwise LDPC_EUNSUPPORTED and nothing is enqueued.  The array is shared
  * by every call on a device: calls whose work overlaps on one device
  * (different streams, or threads) race on it and must be serialised by the
