@@ -217,3 +217,35 @@ def test_server_merges_alike_requests(L, pool):
         assert np.array_equal(r["iters"], iters.cpu().numpy()), f"request {k} iters differ from alone"
         if r["post"] is not None:
             assert np.array_equal(r["post"], post.cpu().numpy()), f"request {k} posterior differs from alone"
+
+
+def test_server_with_tuned_workgroup_sizes(L, pool):
+    """After the autotuner has given the codes different workgroup sizes, a
+    server group of mixed codes runs as one fused launch per size; every
+    request still equals decoding it alone, bit for bit."""
+    import torch
+    handles = [L.Code.from_workload(c) for c in pool.codes]
+    L.ldpc_tuning_clear()
+    try:
+        tune = [L.Job(h, torch.from_numpy(np.ascontiguousarray(pool.llr_pool(i)[:64])).cuda(), 10, early_stop=True)
+                for i, h in enumerate(handles)]
+        L.autotune_batch(tune)
+        sizes = L.ldpc_batch_job_threads([j.c_struct() for j in tune], torch.float32)
+        _log(f"[gpu] serve after tuning: per-code workgroup sizes {sizes}")
+        srv = L.ldpc_server_create(handles, 64 << 20, max_inflight=3, max_group_frames=512)
+        try:
+            reqs = _requests(pool, 60, seed=7)
+            for t in _submit_all(L, srv, reqs):
+                assert L.ldpc_server_wait(srv, t, 60000.0) == 0
+            stats = L.ldpc_server_stats_get(srv)
+            assert stats["completed"] == len(reqs) and stats["failed"] == 0
+        finally:
+            L.ldpc_server_destroy(srv)
+        for k, r in enumerate(reqs):
+            bits, iters, post = L.decode(handles[r["code"]], torch.from_numpy(r["llr"]).cuda(), 10, early_stop=True)
+            torch.cuda.synchronize()
+            assert np.array_equal(r["bits"], bits.cpu().numpy()), f"request {k} bits differ from alone"
+            assert np.array_equal(r["iters"], iters.cpu().numpy()), f"request {k} iters differ from alone"
+            assert np.array_equal(r["post"], post.cpu().numpy()), f"request {k} posterior differs from alone"
+    finally:
+        L.ldpc_tuning_clear()
