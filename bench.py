@@ -418,11 +418,14 @@ def layered_workloads(steps):
     per_decode = fp * (12 * E + 9 * 16 * E)
     achieved = per_decode * (kcount / (10 * layers)) / (kms * 1e-3) / 1e9 if kcount else None
     fused_ms = _batch_ms(L, [(h, llr, 10, False, True)], torch.float32, steps, tune=True)
+    chain = copy_chain(per_decode / (10 * layers), 10 * layers) if kcount else None
     out["qc1944_2dB_10passes"] = {
         "plain_ms": ms, "plain_mbps": F * n / (ms * 1e-3) / 1e6, "layers": layers,
         "layer_kernel": {"launches": kcount, "avg_us": kms * 1e3 / max(kcount, 1),
                          "bytes_per_decode": per_decode, "achieved_gbs": achieved,
-                         "frac_of_peak": achieved / HBM_PEAK_GBS if achieved else None},
+                         "frac_of_peak": achieved / HBM_PEAK_GBS if achieved else None,
+                         "copy_chain": chain,
+                         "frac_of_copy_chain": achieved / chain["gbs"] if chain and achieved else None},
         "batch_ms": fused_ms, "batch_mbps": F * n / (fused_ms * 1e-3) / 1e6}
 
     def converge(batch, dtype, T, reps):
@@ -572,6 +575,35 @@ def _batch_ms(L, items, dtype, reps, tune=False):
     if tune:
         L.ldpc_tuning_clear()  # later workloads are measured with the defaults
     return t
+
+
+def copy_chain(bytes_moved, count):
+    """The same streaming copy as copy_probe, as `count` dependent launches
+    that each move `bytes_moved` bytes (read + write), timed between two HIP
+    events (median of 5): the rate a chain of launches of that size can reach,
+    ramp-up and drain included."""
+    import torch
+
+    import paper_1812_06545_amd as L
+    nbytes = max(16, int(bytes_moved) // 2 // 16 * 16)
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        L.ldpc_copy_probe(dst, src, nbytes)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(count):
+            if L.ldpc_copy_probe(dst, src, nbytes) != 0:
+                raise RuntimeError("ldpc_copy_probe failed")
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / count)
+    ms = sorted(times)[len(times) // 2]
+    return {"bytes_per_launch": 2 * nbytes, "launches": count, "us_per_launch": ms * 1e3,
+            "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
 def copy_probe(mb):
