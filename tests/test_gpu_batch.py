@@ -283,3 +283,33 @@ def test_autotune_keeps_results(L):
                 assert np.array_equal(x, y)
     finally:
         L.ldpc_tuning_clear()
+
+
+def test_plan_under_tuned_sizes_matches_eager(L):
+    """With per-code workgroup sizes tuned, a batch is several fused launches;
+    a plan captured then replays them and matches the eager call bit for bit."""
+    import torch
+    mix = configs.qc_mix(total=1200)
+    items = [(L.Code.from_workload(m.code), m.llr) for m in mix]
+    jobs = [L.Job(h, torch.from_numpy(np.ascontiguousarray(llr)).cuda(), 10, early_stop=True) for h, llr in items]
+    L.ldpc_tuning_clear()
+    try:
+        L.autotune_batch(jobs)
+        sizes = L.ldpc_batch_job_threads([j.c_struct() for j in jobs], torch.float32)
+        _log(f"[gpu] tuned sizes {sizes}")
+        plan = L.Plan(jobs)
+        try:
+            for rep in range(3):
+                plan.launch()
+                torch.cuda.synchronize()
+                got = [_np(j) for j in jobs]
+                eager = [L.Job(j.code, j.llr.clone(), 10, early_stop=True) for j in jobs]
+                L.decode_batch(eager)
+                torch.cuda.synchronize()
+                for g, e in zip(got, eager):
+                    for x, y in zip(g, _np(e)):
+                        assert np.array_equal(x, y), f"replay {rep} differs from eager"
+        finally:
+            plan.close()
+    finally:
+        L.ldpc_tuning_clear()
