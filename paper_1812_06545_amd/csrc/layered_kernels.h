@@ -201,6 +201,93 @@ __global__ __launch_bounds__(256) void k_layer(const int32_t *__restrict__ row_p
     }
 }
 
+// One row of a layer spread over the four wavefronts of a workgroup, one
+// quarter of the row each (the layered combination order of spa_math.h),
+// 64 frames per wavefront: a layer launch then has four times the
+// wavefronts, each with a quarter of the work, which evens out the launch's
+// last round of resident wavefronts.  Each wavefront forms its quarter's
+// combination, the four exchange them through LDS, and each finishes its
+// quarter with the seed of the other three in the fixed association: the
+// same expressions as layer_row in one lane, bit for bit.  The quarter body
+// has DQ slots; slots past the quarter's length are skipped by a branch that
+// is uniform across the wavefront (the row is the wavefront's).  FP32 rows of
+// degree <= 4 DQ.
+template <class A, int DQ, bool FIRST, bool ES>
+__global__ __launch_bounds__(256) void k_layer_q(const int32_t *__restrict__ row_ptr,
+                                                 const int32_t *__restrict__ col_idx, int32_t row0, int32_t rows,
+                                                 int32_t n, int64_t E, int32_t nchunk, typename A::T *__restrict__ R,
+                                                 typename A::T *__restrict__ L, const int32_t *__restrict__ done)
+{
+    using T = typename A::T;
+    using Acc = typename A::Acc;
+    __shared__ Acc sC[4][kChunk];
+    __shared__ uint32_t sS[4][kChunk];
+    const int part = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    int group, chunk;
+    map_block(static_cast<int>(blockIdx.x), rows, nchunk, group, chunk);
+    if (ES && flood::chunk_active(done, nchunk, chunk) == 0)
+        return;  // the whole workgroup (one chunk), before any barrier
+    const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
+    const bool live = !ES || done[f] < 0;  // a stopped frame's lanes compute but store nothing
+    const uint32_t off = static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(T));
+    const int row = row0 + group;
+    const int32_t e0 = row_ptr[row];
+    const int32_t d = __builtin_amdgcn_readfirstlane(row_ptr[row + 1] - e0);
+    const Quarters Q = quarters(d);
+    const int32_t k0 = part == 0 ? 0 : part == 1 ? Q.q1 : part == 2 ? Q.h : Q.q3;
+    const int32_t dq = (part == 0 ? Q.q1 : part == 1 ? Q.h : part == 2 ? Q.q3 : d) - k0;
+    const int32_t *cols = col_idx + e0 + k0;
+    T *Rq = R + (static_cast<int64_t>(chunk) * E + e0 + k0) * kChunk;
+    T *Lc = L + static_cast<int64_t>(chunk) * n * kChunk;
+    const __amdgpu_buffer_rsrc_t rsrc = chunk_rsrc(Lc, n);
+    T q[DQ], rv[DQ];
+#pragma unroll
+    for (int k = 0; k < DQ; ++k) {
+        if (k < dq) {
+            q[k] = ld_gather(rsrc, off, cols[k], T(0));
+            rv[k] = FIRST ? T(0) : ld_lane_nt(Rq + k * kChunk, off);
+        }
+    }
+    typename A::Term a[DQ];
+    Acc p[DQ];
+    Acc acc = A::identity();
+    uint32_t sign = 0;
+#pragma unroll
+    for (int k = 0; k < DQ; ++k) {
+        if (k < dq) {
+            if (!FIRST)
+                q[k] = q[k] - rv[k];
+            check_forward<A>(q[k], a[k], p[k], acc, sign);
+        }
+    }
+    sC[part][lane] = acc;
+    sS[part][lane] = sign;
+    __syncthreads();
+    const Acc C0 = sC[0][lane], C1 = sC[1][lane], C2 = sC[2][lane], C3 = sC[3][lane];
+    const uint32_t sign_total = sS[0][lane] ^ sS[1][lane] ^ sS[2][lane] ^ sS[3][lane];
+    Acc other;
+    if (part == 0)
+        other = A::merge(C1, A::merge(C2, C3));
+    else if (part == 1)
+        other = A::merge(C0, A::merge(C2, C3));
+    else if (part == 2)
+        other = A::merge(C3, A::merge(C0, C1));
+    else
+        other = A::merge(C2, A::merge(C0, C1));
+    Acc sx = A::seed(other);
+#pragma unroll
+    for (int k = DQ - 1; k >= 0; --k) {
+        if (k < dq) {
+            const T r = check_backward<A>(a[k], p[k], sx, sign_total);
+            if (live) {
+                st_lane_nt(Rq + k * kChunk, off, r);
+                st_scatter(rsrc, off, cols[k], q[k] + r);
+            }
+        }
+    }
+}
+
 }  // namespace layered
 
 // Arguments of one layer launch.
@@ -228,19 +315,40 @@ void launch_layer_bucket(const LayerArgs<A> &a, bool first, bool es, dim3 grid, 
                     a.row0, a.rows, a.n, a.E, a.groups, a.nchunk, a.R, a.L, a.done);                            \
     } while (0)
 
+// FP32 exact buckets run the quarter kernel (one row per workgroup of four
+// wavefronts, grid rows x chunks); the others the one-wavefront-per-row kernel.
+#define LDPC_LAYER_LAUNCH_Q(A_, DB_, F_, E_)                                                                     \
+    do {                                                                                                         \
+        ProfScope ps(LDPC_KERNEL_CHECK, s);                                                                      \
+        LDPC_LAUNCH(ps, (layered::k_layer_q<A_, (DB_) / 4, F_, E_>), qgrid, dim3(256), 0, s, a.row_ptr,          \
+                    a.col_idx, a.row0, a.rows, a.n, a.E, a.nchunk, a.R, a.L, a.done);                            \
+    } while (0)
+
 #define LDPC_DEFINE_LAYER_BUCKET(A_, DB_, EX_)                                                                  \
     template <>                                                                                                 \
     void launch_layer_bucket<A_, DB_, EX_>(const LayerArgs<A_> &a, bool first, bool es, dim3 grid,              \
                                            hipStream_t s)                                                       \
     {                                                                                                           \
-        if (first && es)                                                                                        \
-            LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, true, true);                                                    \
-        else if (first)                                                                                         \
-            LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, true, false);                                                   \
-        else if (es)                                                                                            \
-            LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, false, true);                                                   \
-        else                                                                                                    \
-            LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, false, false);                                                  \
+        if constexpr (EX_ && std::is_same<A_, ArithF32>::value) {                                              \
+            const dim3 qgrid(static_cast<unsigned>(a.rows) * static_cast<unsigned>(a.nchunk));                  \
+            if (first && es)                                                                                    \
+                LDPC_LAYER_LAUNCH_Q(A_, DB_, true, true);                                                       \
+            else if (first)                                                                                     \
+                LDPC_LAYER_LAUNCH_Q(A_, DB_, true, false);                                                      \
+            else if (es)                                                                                        \
+                LDPC_LAYER_LAUNCH_Q(A_, DB_, false, true);                                                      \
+            else                                                                                                \
+                LDPC_LAYER_LAUNCH_Q(A_, DB_, false, false);                                                     \
+        } else {                                                                                                \
+            if (first && es)                                                                                    \
+                LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, true, true);                                                \
+            else if (first)                                                                                     \
+                LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, true, false);                                               \
+            else if (es)                                                                                        \
+                LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, false, true);                                               \
+            else                                                                                                \
+                LDPC_LAYER_LAUNCH_ONE(A_, DB_, EX_, false, false);                                              \
+        }                                                                                                       \
     }
 
 }  // namespace ldpc
