@@ -62,7 +62,7 @@ PROFILE_EVERY = 10  # timed steps per step whose launches are bracketed by HIP e
 # only for the kernel source they were taken on (hash below); otherwise null.
 CHECK_TRAFFIC = {
     "bytes_per_launch": 543.1e6,
-    "source_sha256": "9940f618e65e13b48ea0b4deb333d343896098bcc96b98e5ee4957a45b70acf3",
+    "source_sha256": "a3106c90e407f8897c1385d47829ff15770e00aa0a419879e150a4f24eae300e",
     "profile": "profiles/hbm_traffic_check_qc1944.md",
 }
 CHECK_SOURCES = ("flood_kernels.h", "spa_math.h", "check_f32_d24.hip")

@@ -41,12 +41,50 @@
 // shared.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "flood_kernels.h"
 #include "layered_kernels.h"
 #include "minsum_kernels.h"
 
 namespace ldpc {
+
+unsigned stride_grid(const void *fn, unsigned items)
+{
+    struct Entry {
+        const void *fn;
+        int dev;
+        unsigned blocks;
+    };
+    constexpr int kEntries = 64;
+    static std::mutex mu;
+    static Entry cache[kEntries];
+    static int used = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return items;
+    unsigned blocks = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (int i = 0; i < used && blocks == 0; ++i)
+            if (cache[i].fn == fn && cache[i].dev == dev)
+                blocks = cache[i].blocks;
+    }
+    if (blocks == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1 ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+            (void)hipGetLastError();  // the failed query, not a launch, set it
+            return items;
+        }
+        blocks = std::max(8u, static_cast<unsigned>(per_cu * cus) & ~7u);
+        std::lock_guard<std::mutex> lk(mu);
+        if (used < kEntries)
+            cache[used++] = Entry{fn, dev, blocks};
+    }
+    return std::min(items, blocks);
+}
+
 namespace {
 
 using namespace flood;
@@ -322,6 +360,9 @@ ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, 
     const int32_t rgroups = (c->m + kWaves - 1) / kWaves;
     const int32_t cgroups = (c->n + kWaves - 1) / kWaves;
     const dim3 rgrid(static_cast<unsigned>(rgroups) * nchunk), cgrid(static_cast<unsigned>(cgroups) * nchunk);
+    // With early stop the variable kernel's resident blocks stride over its
+    // items (flood_kernels.h); every other launch has one block per item.
+    const dim3 cgrid_es(es ? stride_grid(reinterpret_cast<const void *>(&k_variable<A, true>), cgrid.x) : cgrid.x);
     const bool layered = (flags & LDPC_LAYERED) != 0;
     const bool ms = (flags & LDPC_MIN_SUM) != 0;
     const T scale = static_cast<T>(ms_scale), offset = static_cast<T>(ms_offset * A::kIn);
@@ -365,7 +406,7 @@ ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, 
         }
         ProfScope ps(LDPC_KERNEL_VARIABLE, s);
         if (es)
-            LDPC_LAUNCH(ps, (k_variable<A, true>), cgrid, dim3(256), 0, s, c->col_ptr, c->col_edge, c->n, c->E,
+            LDPC_LAUNCH(ps, (k_variable<A, true>), cgrid_es, dim3(256), 0, s, c->col_ptr, c->col_edge, c->n, c->E,
                                cgroups, nchunk, R, Lch, L, done, unsat_t, t - 1);
         else
             LDPC_LAUNCH(ps, (k_variable<A, false>), cgrid, dim3(256), 0, s, c->col_ptr, c->col_edge, c->n, c->E,

@@ -264,24 +264,22 @@ __device__ __forceinline__ typename A::T column_sum_exact(int dv, typename A::T 
 }
 
 // Variable-node kernel (Loops 3 and 4): one wavefront = one variable x 64
-// frames.  The hard decision is the sign of the stored posterior.
+// frames.  The hard decision is the sign of the stored posterior.  One item
+// is one block's worth of work, kWaves columns of one frame chunk; the
+// chunk's running count has been tested by the caller.
 template <class A, bool ES>
-__global__ __launch_bounds__(256) void k_variable(const int32_t *__restrict__ col_ptr,
-                                                  const int32_t *__restrict__ col_edge, int32_t n, int64_t E,
-                                                  int32_t groups, int32_t nchunk, const typename A::T *__restrict__ R,
-                                                  const typename A::T *__restrict__ Lch, typename A::T *__restrict__ L,
-                                                  int32_t *__restrict__ done, const int32_t *__restrict__ unsat,
-                                                  int32_t t_prev)
+__device__ __forceinline__ void variable_item(int group, int chunk, const int32_t *__restrict__ col_ptr,
+                                              const int32_t *__restrict__ col_edge, int32_t n, int64_t E,
+                                              int32_t nchunk, const typename A::T *__restrict__ R,
+                                              const typename A::T *__restrict__ Lch, typename A::T *__restrict__ L,
+                                              int32_t *__restrict__ done, const int32_t *__restrict__ unsat,
+                                              int32_t t_prev)
 {
     using T = typename A::T;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int lane = static_cast<int>(threadIdx.x & 63);
-    int group, chunk;
-    map_block(static_cast<int>(blockIdx.x), groups, nchunk, group, chunk);
     const int col = group * kWaves + wave;
     if (col >= n)
-        return;
-    if (ES && chunk_active(done, nchunk, chunk) == 0)
         return;
     const uint32_t f = static_cast<uint32_t>(chunk) * 64u + static_cast<uint32_t>(lane);
     const uint32_t off = static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(T));
@@ -289,16 +287,20 @@ __global__ __launch_bounds__(256) void k_variable(const int32_t *__restrict__ co
     const int32_t dv = __builtin_amdgcn_readfirstlane(col_ptr[col + 1] - k0);
     const int64_t vo = (static_cast<int64_t>(chunk) * n + col) * kChunk;
     const T *Rc = R + static_cast<int64_t>(chunk) * E * kChunk;
+    // With early stop the frame's state is loaded beside the column's values
+    // (both words, so that neither load waits for the other).
+    int32_t dn = -1, us = 1;
+    if constexpr (ES) {
+        dn = done[f];
+        us = unsat[f];
+    }
     const T acc = ld_lane(Lch + vo, off);
-    // the column's loads are issued before the frame's stop test, so that
-    // test's loads add no round trip in front of them
     const T v = column_sum_exact<A, 0>(dv, acc, col_edge + k0, Rc, off);
     if (ES) {
         // A frame runs iteration t unless it stopped earlier or its decision
         // x^(t-1) satisfies every row (it stops at t-1).  The column-0 wave of
         // each chunk records the stops and the chunk's count of running frames.
-        const int32_t dn = done[f];
-        const bool running = dn < 0 && unsat[f] != 0;
+        const bool running = (dn < 0) & (us != 0);
         if (col == 0) {
             if (dn < 0 && !running)
                 done[f] = t_prev;
@@ -310,6 +312,50 @@ __global__ __launch_bounds__(256) void k_variable(const int32_t *__restrict__ co
             return;
     }
     st_lane(L + vo, off, v);
+}
+
+// Without early stop the grid holds one block per item.  With early stop it
+// holds at most the blocks the device keeps resident at once (stride_grid, a
+// multiple of 8, so that item b still runs on XCD b mod 8), which stride over
+// the items in order: the items in flight form one window moving through the
+// item order, as under the hardware's own dispatch, and a launch over stopped
+// chunks costs those blocks' passes over the item list instead of the
+// dispatch of one block per column group and chunk.  A block tests a chunk's
+// running count when its items move to another chunk.  The count may drop
+// to 0 during the launch (the column-0 wave writes it); a block that still
+// holds the older count computes the item, whose frames have all stopped and
+// store nothing, and one that reads the 0 skips it: the same result.
+// Measured on MI355X (stair64800, 256 frames): a launch over four running
+// chunks took 69-70 us instead of 91, one after every frame stopped 13 us
+// instead of 20.  Without early stop the strided form was 3% slower than one
+// block per item, and a strided check kernel 13% slower per launch (a
+// block's items are fixed, so the CUs of an XCD cannot even out its row
+// groups' run times as the dispatcher does).
+template <class A, bool ES>
+__global__ __launch_bounds__(256) void k_variable(const int32_t *__restrict__ col_ptr,
+                                                  const int32_t *__restrict__ col_edge, int32_t n, int64_t E,
+                                                  int32_t groups, int32_t nchunk, const typename A::T *__restrict__ R,
+                                                  const typename A::T *__restrict__ Lch, typename A::T *__restrict__ L,
+                                                  int32_t *__restrict__ done, const int32_t *__restrict__ unsat,
+                                                  int32_t t_prev)
+{
+    int group, chunk;
+    if constexpr (ES) {
+        const int items = groups * nchunk;
+        int tested = -1, running = 0;
+        for (int b = static_cast<int>(blockIdx.x); b < items; b += static_cast<int>(gridDim.x)) {
+            map_block(b, groups, nchunk, group, chunk);
+            if (chunk != tested) {
+                tested = chunk;
+                running = chunk_active(done, nchunk, chunk);
+            }
+            if (running != 0)
+                variable_item<A, ES>(group, chunk, col_ptr, col_edge, n, E, nchunk, R, Lch, L, done, unsat, t_prev);
+        }
+    } else {
+        map_block(static_cast<int>(blockIdx.x), groups, nchunk, group, chunk);
+        variable_item<A, ES>(group, chunk, col_ptr, col_edge, n, E, nchunk, R, Lch, L, done, unsat, t_prev);
+    }
 }
 
 }  // namespace flood
@@ -327,6 +373,13 @@ struct CheckArgs {
     const int32_t *done;
     int32_t *unsat;
 };
+
+// Grid of a launch whose 256-thread blocks stride over `items` items: as many
+// blocks of kernel fn as the current device keeps resident at once (rounded
+// down to a multiple of 8), or `items` if that is fewer.  The occupancy query
+// and the CU count are cached per (kernel, device) in a fixed-size table; if
+// either query fails the grid is `items` (one block per item).
+unsigned stride_grid(const void *fn, unsigned items);
 
 // Launcher of the check kernel for rows of degree <= DB; each (dtype, bucket)
 // is defined in its own translation unit.
