@@ -536,7 +536,9 @@ __device__ __forceinline__ void start_messages(const Code &c, const FrameView &f
 //   [.., +mb)                     brow_order
 //   [.., +nblocks)                column view: r0 + tsize * Z * b for block-column slot w
 //   [.., +kColSpare)              zero words
-template <class A, int DB>
+// QCF: every job of the launch is sum-product flooding on a circulant view
+// (no min-sum or CSR rows compiled in).
+template <class A, int DB, bool QCF = false>
 __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int64_t f, const FrameView &fv)
 {
     using T = typename A::T;
@@ -559,7 +561,7 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
     __syncthreads();
 
     const bool es = (job.flags & LDPC_EARLY_STOP) != 0;
-    const bool ms = (job.flags & LDPC_MIN_SUM) != 0;
+    const bool ms = !QCF && (job.flags & LDPC_MIN_SUM) != 0;
     const T ms_scale = static_cast<T>(job.ms_scale), ms_offset = static_cast<T>(job.ms_offset * A::kIn);
     int32_t it = job.max_iter;
     for (int32_t t = 1; t <= job.max_iter; ++t) {
@@ -573,7 +575,7 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
             if (dwave == 0 || sr >= m)
                 continue;
             const int hwave = (dwave + 1) >> 1;
-            if (c.qc) {
+            if (QCF || c.qc) {
                 const int32_t si = div_z(sr, c.zmagic);
                 const int32_t r = sr - si * Z;
                 const int32_t i = border[si];
@@ -613,7 +615,7 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
             const int dwave = c.col_gmax[__builtin_amdgcn_readfirstlane(j) >> 6];
             const T acc = llr[j] * T(A::kIn);
             T v;
-            if (c.qc) {
+            if (QCF || c.qc) {
                 const int32_t bj = div_z(j, c.zmagic);
                 const uint32_t cc_t = TS * static_cast<uint32_t>(j - bj * Z);
                 const int32_t k0 = cbs[bj];
@@ -1106,7 +1108,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
 template <class A>
 constexpr int kFusedWavesPerEU = std::is_same<A, ArithF32>::value ? 4 : 2;
 
-template <class A, int DB>
+template <class A, int DB, bool QCF = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWavesPerEU<A>))) void k_fused(const Batch *__restrict__ batch, unsigned long long *counter)
 {
     using T = typename A::T;
@@ -1138,12 +1140,25 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWaves
             cur_code = job.code;
             load_tables<TS>(c, sTab, lay.r0);
         }
-        if (job.flags & LDPC_LAYERED)
+        if (!QCF && (job.flags & LDPC_LAYERED))
             decode_frame_layered<A, DB>(c, job, item - job.item_begin, fv);
         else
-            decode_frame<A, DB>(c, job, item - job.item_begin, fv);
+            decode_frame<A, DB, QCF>(c, job, item - job.item_begin, fv);
         __syncthreads();
     }
+}
+
+// True if every job of the batch can run k_fused<A, DB, true>: sum-product
+// flooding (no LDPC_LAYERED, no LDPC_MIN_SUM) on codes with a circulant view.
+inline bool qc_flood_only(const Batch &b)
+{
+    for (int32_t k = 0; k < b.njobs; ++k)
+        if ((b.jobs[k].flags & (LDPC_LAYERED | LDPC_MIN_SUM)) != 0)
+            return false;
+    for (int32_t k = 0; k < b.ncodes; ++k)
+        if (!b.codes[k].qc)
+            return false;
+    return b.njobs > 0;
 }
 
 }  // namespace fused
@@ -1248,6 +1263,9 @@ ldpc_status launch_fused_kernel(K kern, const fused::Batch &batch, fused::Batch 
         if constexpr (std::is_same<A_, ArithF32>::value) {                                                       \
             if (fpw == 2)                                                                                        \
                 return launch_fused_kernel(fused::k_fused_pair<A_, DB_>, batch, d_batch, counter, lds_bytes,    \
+                                           threads, s, profile);                                                 \
+            if (fpw == 1 && fused::qc_flood_only(batch))                                                         \
+                return launch_fused_kernel(fused::k_fused<A_, DB_, true>, batch, d_batch, counter, lds_bytes,   \
                                            threads, s, profile);                                                 \
         }                                                                                                        \
         if (fpw != 1)                                                                                            \

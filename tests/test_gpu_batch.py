@@ -110,6 +110,36 @@ def test_fused_mix_isolation_and_oracle(L):
         compare(ref, bits[idx], iters[idx], post[idx], np.float32, f"mix job {k}")
 
 
+def test_flooding_instance_matches_general_instance(L):
+    """A batch whose jobs are all FP32 sum-product flooding on codes with a
+    circulant view runs a kernel instance compiled without the other rules,
+    schedules and row views.  Adding a min-sum job, a layered job or a job on
+    a code without a circulant view makes the same jobs run the general
+    instance: their outputs stay the same, bit for bit."""
+    import torch
+    mix = configs.qc_mix(total=720)[::3]
+    hs = [L.Code.from_workload(m.code) for m in mix]
+    g = configs.gallager504(frames=64)
+    hg = L.Code.from_workload(g.code)
+    for es in (True, False):
+        base = [_np(j) for j in _batch(L, list(zip(hs, [m.llr for m in mix])), es=es)]
+        x0 = torch.from_numpy(np.ascontiguousarray(mix[0].llr)).cuda()
+        extras = {
+            "min-sum": L.Job(hs[0], x0, 10, early_stop=es, rule="minsum", ms_scale=0.75),
+            "layered": L.Job(hs[0], x0, 10, early_stop=es, layered=True),
+            "csr code": L.Job(hg, torch.from_numpy(g.llr.astype(np.float32)).cuda(), 10, early_stop=es),
+        }
+        for name, extra in extras.items():
+            _log(f"[gpu] flooding instance vs general (+{name}, early stop {es})")
+            jobs = [L.Job(h, torch.from_numpy(np.ascontiguousarray(m.llr)).cuda(), 10, early_stop=es)
+                    for h, m in zip(hs, mix)]
+            L.decode_batch(jobs + [extra])
+            torch.cuda.synchronize()
+            for k, (j, ref) in enumerate(zip(jobs, base)):
+                for x, y in zip(_np(j), ref):
+                    assert np.array_equal(x, y), f"job {k} differs with a {name} job in the batch"
+
+
 def test_fused_f64_gallager(L):
     b = configs.gallager504(frames=300)
     h = L.Code.from_workload(b.code)
