@@ -536,6 +536,11 @@ __device__ __forceinline__ void start_messages(const Code &c, const FrameView &f
 //   [.., +mb)                     brow_order
 //   [.., +nblocks)                column view: r0 + tsize * Z * b for block-column slot w
 //   [.., +kColSpare)              zero words
+// Kernel instances: one for any batch, and two compiled with one schedule's
+// sum-product rows on circulant views only (no min-sum, no CSR rows, no
+// other schedule), for batches whose jobs all allow it.
+enum Instance { kAnyJob = 0, kFloodQC = 1, kLayeredQC = 2 };
+
 // QCF: every job of the launch is sum-product flooding on a circulant view
 // (no min-sum or CSR rows compiled in).
 template <class A, int DB, bool QCF = false>
@@ -648,7 +653,9 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
 // each and a workgroup barrier between layers.  With early stop the syndrome
 // of [L < 0] is tested before the first pass and after every pass but the
 // last.  Each row's arithmetic is the plain layered path's, bit for bit.
-template <class A, int DB>
+// QCL: every job of the launch is sum-product layered on a circulant view
+// (no min-sum or CSR rows compiled in).
+template <class A, int DB, bool QCL = false>
 __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &job, int64_t f, const FrameView &fv)
 {
     using T = typename A::T;
@@ -686,7 +693,7 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
             const int sr = rb + (lane & 31);
             uint32_t par = 0;
             if (sr < m) {
-                if (c.qc) {
+                if (QCL || c.qc) {
                     const int32_t si = div_z(sr, c.zmagic);
                     int32_t d, k0, dh;
                     const RowQC row = qc_half(si, sr - si * Z, d, k0, dh);
@@ -708,7 +715,7 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
     };
 
     const bool es = (job.flags & LDPC_EARLY_STOP) != 0;
-    const bool ms = (job.flags & LDPC_MIN_SUM) != 0;
+    const bool ms = !QCL && (job.flags & LDPC_MIN_SUM) != 0;
     const T ms_scale = static_cast<T>(job.ms_scale), ms_offset = static_cast<T>(job.ms_offset * A::kIn);
     uint32_t no_parity = 0;
     int32_t it = job.max_iter;
@@ -720,7 +727,7 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
             // rows: four lanes each (16 rows per wavefront)
             const int rows_per_wave = ms ? 32 : 16;
             const int part = lane >> 4;
-            if (c.qc) {
+            if (QCL || c.qc) {
                 for (int32_t i = 0; i < c.mb; ++i) {
                     for (int rb = wave * rows_per_wave; rb < Z; rb += nwaves * rows_per_wave) {
                         const int r = rb + (lane & (rows_per_wave - 1));
@@ -1108,7 +1115,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
 template <class A>
 constexpr int kFusedWavesPerEU = std::is_same<A, ArithF32>::value ? 4 : 2;
 
-template <class A, int DB, bool QCF = false>
+template <class A, int DB, int INST = kAnyJob>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWavesPerEU<A>))) void k_fused(const Batch *__restrict__ batch, unsigned long long *counter)
 {
     using T = typename A::T;
@@ -1140,25 +1147,29 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWaves
             cur_code = job.code;
             load_tables<TS>(c, sTab, lay.r0);
         }
-        if (!QCF && (job.flags & LDPC_LAYERED))
-            decode_frame_layered<A, DB>(c, job, item - job.item_begin, fv);
+        if (INST == kLayeredQC || (INST == kAnyJob && (job.flags & LDPC_LAYERED)))
+            decode_frame_layered<A, DB, INST == kLayeredQC>(c, job, item - job.item_begin, fv);
         else
-            decode_frame<A, DB, QCF>(c, job, item - job.item_begin, fv);
+            decode_frame<A, DB, INST == kFloodQC>(c, job, item - job.item_begin, fv);
         __syncthreads();
     }
 }
 
-// True if every job of the batch can run k_fused<A, DB, true>: sum-product
-// flooding (no LDPC_LAYERED, no LDPC_MIN_SUM) on codes with a circulant view.
-inline bool qc_flood_only(const Batch &b)
+// The instance of k_fused that runs every job of the batch: kFloodQC or
+// kLayeredQC when all jobs are sum-product (no LDPC_MIN_SUM) on codes with a
+// circulant view and all take that schedule, else kAnyJob.
+inline Instance batch_instance(const Batch &b)
 {
-    for (int32_t k = 0; k < b.njobs; ++k)
-        if ((b.jobs[k].flags & (LDPC_LAYERED | LDPC_MIN_SUM)) != 0)
-            return false;
+    if (b.njobs == 0)
+        return kAnyJob;
     for (int32_t k = 0; k < b.ncodes; ++k)
         if (!b.codes[k].qc)
-            return false;
-    return b.njobs > 0;
+            return kAnyJob;
+    const uint32_t first = b.jobs[0].flags & LDPC_LAYERED;
+    for (int32_t k = 0; k < b.njobs; ++k)
+        if ((b.jobs[k].flags & LDPC_MIN_SUM) != 0 || (b.jobs[k].flags & LDPC_LAYERED) != first)
+            return kAnyJob;
+    return first ? kLayeredQC : kFloodQC;
 }
 
 }  // namespace fused
@@ -1264,9 +1275,13 @@ ldpc_status launch_fused_kernel(K kern, const fused::Batch &batch, fused::Batch 
             if (fpw == 2)                                                                                        \
                 return launch_fused_kernel(fused::k_fused_pair<A_, DB_>, batch, d_batch, counter, lds_bytes,    \
                                            threads, s, profile);                                                 \
-            if (fpw == 1 && fused::qc_flood_only(batch))                                                         \
-                return launch_fused_kernel(fused::k_fused<A_, DB_, true>, batch, d_batch, counter, lds_bytes,   \
-                                           threads, s, profile);                                                 \
+            const fused::Instance inst_ = fpw == 1 ? fused::batch_instance(batch) : fused::kAnyJob;              \
+            if (inst_ == fused::kFloodQC)                                                                        \
+                return launch_fused_kernel(fused::k_fused<A_, DB_, fused::kFloodQC>, batch, d_batch, counter,   \
+                                           lds_bytes, threads, s, profile);                                      \
+            if (inst_ == fused::kLayeredQC)                                                                      \
+                return launch_fused_kernel(fused::k_fused<A_, DB_, fused::kLayeredQC>, batch, d_batch, counter, \
+                                           lds_bytes, threads, s, profile);                                      \
         }                                                                                                        \
         if (fpw != 1)                                                                                            \
             return LDPC_EUNSUPPORTED;                                                                            \
