@@ -363,6 +363,7 @@ fused::Code code_entry(const ldpc_code_s *c, size_t tsize)
     e.col_gmax = c->col_gmax;
     e.layer_ptr = c->d_layer_ptr;
     e.nlayers = static_cast<int32_t>(c->layer_dmax.size());
+    e.half_rows = qc ? c->half_rows : nullptr;
     return e;
 }
 

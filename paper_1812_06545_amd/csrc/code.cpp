@@ -101,6 +101,32 @@ void slot_tables(const HostLayout &h, const std::vector<int32_t> &row_blk_start,
         col_gmax[j / 64] = std::max(col_gmax[j / 64], h.col_ptr[j + 1] - h.col_ptr[j]);
 }
 
+// Half-row words of the fused kernel's circulant view (see ldpc_code_s):
+// row slot sr is row r = sr mod Z of block-row brow_order[sr / Z], whose
+// blocks are b0 .. b0 + d - 1; its first half holds ceil(d / 2) blocks from
+// b0, its second the rest.  Empty when there is no circulant view or a
+// field would overflow (13 bits of block index, 6 of length, 13 of row).
+std::vector<int32_t> half_row_words(const std::vector<int32_t> &row_blk_start, const std::vector<int32_t> &brow_order,
+                                    int32_t Z, int32_t m)
+{
+    std::vector<int32_t> out;
+    if (row_blk_start.empty() || brow_order.empty() || Z < 1 || Z >= (1 << 13) || row_blk_start.back() >= (1 << 13))
+        return out;
+    out.resize(2 * static_cast<size_t>(m));
+    for (int32_t sr = 0; sr < m; ++sr) {
+        const int32_t i = brow_order[sr / Z], r = sr % Z;
+        const int32_t b0 = row_blk_start[i], d = row_blk_start[i + 1] - b0, h = (d + 1) / 2;
+        if (h >= (1 << 6))
+            return {};
+        for (int32_t half = 0; half < 2; ++half) {
+            const uint32_t k0 = half ? h : 0, dh = half ? d - h : h;
+            const uint32_t w = (static_cast<uint32_t>(b0) + k0) | dh << 13 | static_cast<uint32_t>(r) << 19;
+            out[2 * static_cast<size_t>(sr) + half] = static_cast<int32_t>(w);
+        }
+    }
+    return out;
+}
+
 // Greedy layers over the rows in ascending order: a row opens a new layer
 // when it shares a variable with a row of the current one.  Visiting the
 // layers in order, each as a parallel step, equals visiting the rows one at a
@@ -166,9 +192,10 @@ ldpc_status upload(const HostLayout &h, const std::vector<int32_t> *qc_tab, cons
     layer_tables(h, c->layer_ptr, c->layer_dmax);
     std::vector<int32_t> brow_order, row_gmax, col_gmax;
     slot_tables(h, row_blk_start, Z, brow_order, row_gmax, col_gmax);
+    const std::vector<int32_t> halves = half_row_words(row_blk_start, brow_order, Z, h.m);
     const size_t words = h.row_ptr.size() + h.col_idx.size() + h.col_ptr.size() + h.col_edge.size() +
                          (qc_tab ? qc_tab->size() : 0) + brow_order.size() + row_gmax.size() + col_gmax.size() +
-                         c->layer_ptr.size();
+                         c->layer_ptr.size() + halves.size();
     std::vector<int32_t> blob;
     blob.reserve(words);
     auto put = [&](const std::vector<int32_t> &v) {
@@ -179,6 +206,7 @@ ldpc_status upload(const HostLayout &h, const std::vector<int32_t> *qc_tab, cons
     const size_t o_rp = put(h.row_ptr), o_ci = put(h.col_idx), o_cp = put(h.col_ptr), o_ce = put(h.col_edge);
     const size_t o_qc = qc_tab ? put(*qc_tab) : 0;
     const size_t o_bo = put(brow_order), o_rg = put(row_gmax), o_cg = put(col_gmax), o_lp = put(c->layer_ptr);
+    const size_t o_hr = put(halves);
     void *d = nullptr;
     if (hipMalloc(&d, std::max<size_t>(blob.size(), 1) * sizeof(int32_t)) != hipSuccess)
         return LDPC_ENOMEM;
@@ -197,6 +225,7 @@ ldpc_status upload(const HostLayout &h, const std::vector<int32_t> *qc_tab, cons
     c->row_gmax = base + o_rg;
     c->col_gmax = base + o_cg;
     c->d_layer_ptr = base + o_lp;
+    c->half_rows = halves.empty() ? nullptr : reinterpret_cast<const uint32_t *>(base + o_hr);
     c->m = h.m;
     c->n = h.n;
     c->E = static_cast<int64_t>(h.col_idx.size());

@@ -57,6 +57,7 @@ struct Code {
     const int32_t *tab, *row_ptr, *col_idx, *col_ptr, *col_edge, *brow_order, *row_gmax, *col_gmax;
     const int32_t *layer_ptr;  // layered schedule, CSR view: layer l = rows [layer_ptr[l], layer_ptr[l+1])
     int32_t nlayers;
+    const uint32_t *half_rows;  // circulant view: word 2 sr + h = half h of row slot sr (or null)
 };
 
 struct Job {
@@ -580,7 +581,17 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
             if (dwave == 0 || sr >= m)
                 continue;
             const int hwave = (dwave + 1) >> 1;
-            if (QCF || c.qc) {
+            if constexpr (QCF) {
+                // the half row's first block, length and row in one word
+                const uint32_t w = c.half_rows[2 * sr + half];
+                const uint32_t bk = w & 0x1fffu, r = w >> 19;
+                const int32_t dh = static_cast<int32_t>((w >> 13) & 63u);
+                const RowQC row{TS * r, z_t, fv.r0 + z_t * bk, pack + bk};
+                if (es)
+                    fused_row_dispatch<A, 1, DB / 2, true>(hwave, row, dh, s, fv.slots, parity);
+                else
+                    fused_row_dispatch<A, 1, DB / 2, false>(hwave, row, dh, s, fv.slots, parity);
+            } else if (c.qc) {
                 const int32_t si = div_z(sr, c.zmagic);
                 const int32_t r = sr - si * Z;
                 const int32_t i = border[si];
@@ -1169,7 +1180,12 @@ inline Instance batch_instance(const Batch &b)
     for (int32_t k = 0; k < b.njobs; ++k)
         if ((b.jobs[k].flags & LDPC_MIN_SUM) != 0 || (b.jobs[k].flags & LDPC_LAYERED) != first)
             return kAnyJob;
-    return first ? kLayeredQC : kFloodQC;
+    if (first)
+        return kLayeredQC;
+    for (int32_t k = 0; k < b.ncodes; ++k)  // the flooding instance reads the half-row words
+        if (b.codes[k].half_rows == nullptr)
+            return kAnyJob;
+    return kFloodQC;
 }
 
 }  // namespace fused

@@ -84,6 +84,11 @@ struct ldpc_code_s {
     const int32_t *brow_order = nullptr;
     const int32_t *row_gmax = nullptr;
     const int32_t *col_gmax = nullptr;
+    // Half-row words of the fused kernel's circulant view (QC codes whose
+    // sizes fit the fields, else null): word 2 sr + h describes half h of
+    // row slot sr as (first block of the half) | (its length) << 13 |
+    // (the row's index within its block-row) << 19.
+    const uint32_t *half_rows = nullptr;
     // Layers of the layered schedule (host): maximal runs of consecutive rows,
     // in ascending order, in which no two rows share a variable.  Layer l is
     // rows [layer_ptr[l], layer_ptr[l+1]); layer_dmax[l] its largest degree.
