@@ -697,10 +697,12 @@ __device__ __forceinline__ void decode_frame_layered(const Code &c, const Job &j
     };
 
     // 1 if some row is unsatisfied by [sL < 0]: each lane takes one half of a
-    // row, partner lanes combine their parities.
+    // row, partner lanes combine their parities.  A wavefront stops at its
+    // first group of 32 rows holding an unsatisfied one (the answer is then
+    // known; in most passes that is the first group).
     auto unsatisfied = [&]() -> int {
         uint32_t bad = 0;
-        for (int rb = wave * 32; rb < m; rb += nwaves * 32) {
+        for (int rb = wave * 32; rb < m && !__any(static_cast<int>(bad)); rb += nwaves * 32) {
             const int sr = rb + (lane & 31);
             uint32_t par = 0;
             if (sr < m) {
