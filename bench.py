@@ -45,6 +45,8 @@ def parse():
                     help="seconds of the same traffic before the measured run (statistics reset after it)")
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="offered requests per second")
     ap.add_argument("--no-extra", action="store_true", help="skip the batch-path and other-workload timings")
+    ap.add_argument("--only-workload", choices=("gallager504_f64", "qc_mix_16384", "stair64800"), default=None,
+                    help="of the other workloads, time this one alone (for a profile of its kernels)")
     ap.add_argument("--profile-every", type=int, default=PROFILE_EVERY,
                     help="bracket the launches of every N-th timed step with HIP events (kernel durations)")
     ap.add_argument("--copy-probe-mb", type=int, default=512,
@@ -215,12 +217,13 @@ def main():
     kernels = {k: {"ms_total": v[0], "launches": v[1]} for k, v in prof.items() if v[1]}
 
     other_path = None
-    if args.path == "plain" and not args.no_extra:
+    rest = not args.no_extra and args.only_workload is None
+    if args.path == "plain" and rest:
         other_path = batch_path_run(h, llrs, bits, iters, post, F, n, T, args.steps)
-    extra = None if args.no_extra else extra_workloads()
-    layered = None if args.no_extra else layered_workloads(args.steps)
-    minsum = None if args.no_extra else minsum_workloads(args.steps)
-    mstream = None if args.no_extra else mstream_run()
+    extra = None if args.no_extra else extra_workloads(args.only_workload)
+    layered = layered_workloads(args.steps) if rest else None
+    minsum = minsum_workloads(args.steps) if rest else None
+    mstream = mstream_run() if rest else None
 
     copy = copy_probe(args.copy_probe_mb) if args.copy_probe_mb > 0 else None
     if copy and achieved:
@@ -311,7 +314,7 @@ def batch_path_run(h, llrs, bits, iters, post, F, n, T, steps):
             "mbps": F * n / (ms * 1e-3) / 1e6, "step_floor": floor_frac(h.edges, n, 4, F * T, ms)}
 
 
-def extra_workloads():
+def extra_workloads(only=None):
     """The other seeded workloads, each timed with HIP events on the device:
     - gallager504 (FP64, 1000 frames, 20 iterations, early stop): plain and batch;
     - qc_mix (12 codes, 16384 frames, 10 iterations, early stop): one batched
@@ -320,6 +323,7 @@ def extra_workloads():
       from a HIP-graph plan;
     - stair64800 (256 frames, 50 iterations, early stop): plain path and
       ldpc_decode_batch (which takes the plain kernels for this code).
+    `only` names one of them to time alone.
     Each carries the whole step's algorithmic-floor fraction (floor_frac)
     over the iterations its frames actually ran."""
     import torch
@@ -376,11 +380,14 @@ def extra_workloads():
                         "batch_tuned_floor": frac(tt)})
         return res
 
-    out["gallager504_f64"] = plain_and_batch([configs.gallager504()], torch.float64, 5)
-    out["qc_mix_16384"] = plain_and_batch(configs.qc_mix(), torch.float32, 5, tune=True)
-    st = plain_and_batch([configs.stair64800()], torch.float32, 3)
-    st["batch_entry"] = "ldpc_decode_batch routes this code to the plain kernels (too large for one workgroup's LDS)"
-    out["stair64800"] = st
+    if only in (None, "gallager504_f64"):
+        out["gallager504_f64"] = plain_and_batch([configs.gallager504()], torch.float64, 5)
+    if only in (None, "qc_mix_16384"):
+        out["qc_mix_16384"] = plain_and_batch(configs.qc_mix(), torch.float32, 5, tune=True)
+    if only in (None, "stair64800"):
+        st = plain_and_batch([configs.stair64800()], torch.float32, 3)
+        st["batch_entry"] = "ldpc_decode_batch routes this code to the plain kernels (too large for one workgroup's LDS)"
+        out["stair64800"] = st
     return out
 
 
