@@ -540,11 +540,12 @@ __device__ __forceinline__ void start_messages(const Code &c, const FrameView &f
 // Kernel instances: one for any batch, and two compiled with one schedule's
 // sum-product rows on circulant views only (no min-sum, no CSR rows, no
 // other schedule), for batches whose jobs all allow it.
-enum Instance { kAnyJob = 0, kFloodQC = 1, kLayeredQC = 2 };
+enum Instance { kAnyJob = 0, kFloodQC = 1, kLayeredQC = 2, kMinSumQC = 3 };
 
 // QCF: every job of the launch is sum-product flooding on a circulant view
-// (no min-sum or CSR rows compiled in).
-template <class A, int DB, bool QCF = false>
+// (no min-sum or CSR rows compiled in); MSQ: every job is min-sum flooding on
+// a circulant view (no sum-product or CSR rows compiled in).
+template <class A, int DB, bool QCF = false, bool MSQ = false>
 __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int64_t f, const FrameView &fv)
 {
     using T = typename A::T;
@@ -567,7 +568,7 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
     __syncthreads();
 
     const bool es = (job.flags & LDPC_EARLY_STOP) != 0;
-    const bool ms = !QCF && (job.flags & LDPC_MIN_SUM) != 0;
+    const bool ms = MSQ || (!QCF && (job.flags & LDPC_MIN_SUM) != 0);
     const T ms_scale = static_cast<T>(job.ms_scale), ms_offset = static_cast<T>(job.ms_offset * A::kIn);
     int32_t it = job.max_iter;
     for (int32_t t = 1; t <= job.max_iter; ++t) {
@@ -601,11 +602,13 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
                                 pack + b0 + k0};
                 if (ms)
                     ms_half_row<A, DB / 2, false>(row, k0, dh, s, fv.slots, parity, ms_scale, ms_offset);
-                else if (es)
-                    fused_row_dispatch<A, 1, DB / 2, true>(hwave, row, dh, s, fv.slots, parity);
-                else
-                    fused_row_dispatch<A, 1, DB / 2, false>(hwave, row, dh, s, fv.slots, parity);
-            } else {
+                else if constexpr (!MSQ) {
+                    if (es)
+                        fused_row_dispatch<A, 1, DB / 2, true>(hwave, row, dh, s, fv.slots, parity);
+                    else
+                        fused_row_dispatch<A, 1, DB / 2, false>(hwave, row, dh, s, fv.slots, parity);
+                }
+            } else if constexpr (!MSQ) {
                 const int32_t e0 = c.row_ptr[sr], d = c.row_ptr[sr + 1] - e0, h = (d + 1) >> 1;
                 const int32_t k0 = half ? h : 0, dh = half ? d - h : h;
                 const RowCSR<TS> row{fv.r0 + TS * static_cast<uint32_t>(e0 + k0), c.col_idx + e0 + k0};
@@ -631,7 +634,7 @@ __device__ __forceinline__ void decode_frame(const Code &c, const Job &job, int6
             const int dwave = c.col_gmax[__builtin_amdgcn_readfirstlane(j) >> 6];
             const T acc = llr[j] * T(A::kIn);
             T v;
-            if (QCF || c.qc) {
+            if (QCF || MSQ || c.qc) {
                 const int32_t bj = div_z(j, c.zmagic);
                 const uint32_t cc_t = TS * static_cast<uint32_t>(j - bj * Z);
                 const int32_t k0 = cbs[bj];
@@ -1163,14 +1166,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kFusedWaves
         if (INST == kLayeredQC || (INST == kAnyJob && (job.flags & LDPC_LAYERED)))
             decode_frame_layered<A, DB, INST == kLayeredQC>(c, job, item - job.item_begin, fv);
         else
-            decode_frame<A, DB, INST == kFloodQC>(c, job, item - job.item_begin, fv);
+            decode_frame<A, DB, INST == kFloodQC, INST == kMinSumQC>(c, job, item - job.item_begin, fv);
         __syncthreads();
     }
 }
 
 // The instance of k_fused that runs every job of the batch: kFloodQC or
 // kLayeredQC when all jobs are sum-product (no LDPC_MIN_SUM) on codes with a
-// circulant view and all take that schedule, else kAnyJob.
+// circulant view and all take that schedule, kMinSumQC when all are min-sum
+// flooding on such codes, else kAnyJob.
 inline Instance batch_instance(const Batch &b)
 {
     if (b.njobs == 0)
@@ -1178,10 +1182,14 @@ inline Instance batch_instance(const Batch &b)
     for (int32_t k = 0; k < b.ncodes; ++k)
         if (!b.codes[k].qc)
             return kAnyJob;
-    const uint32_t first = b.jobs[0].flags & LDPC_LAYERED;
+    const uint32_t first = b.jobs[0].flags & (LDPC_LAYERED | LDPC_MIN_SUM);
     for (int32_t k = 0; k < b.njobs; ++k)
-        if ((b.jobs[k].flags & LDPC_MIN_SUM) != 0 || (b.jobs[k].flags & LDPC_LAYERED) != first)
+        if ((b.jobs[k].flags & (LDPC_LAYERED | LDPC_MIN_SUM)) != first)
             return kAnyJob;
+    if (first == LDPC_MIN_SUM)
+        return kMinSumQC;
+    if (first != 0 && first != LDPC_LAYERED)
+        return kAnyJob;  // layered min-sum
     if (first)
         return kLayeredQC;
     for (int32_t k = 0; k < b.ncodes; ++k)  // the flooding instance reads the half-row words
@@ -1299,6 +1307,9 @@ ldpc_status launch_fused_kernel(K kern, const fused::Batch &batch, fused::Batch 
                                            lds_bytes, threads, s, profile);                                      \
             if (inst_ == fused::kLayeredQC)                                                                      \
                 return launch_fused_kernel(fused::k_fused<A_, DB_, fused::kLayeredQC>, batch, d_batch, counter, \
+                                           lds_bytes, threads, s, profile);                                      \
+            if (inst_ == fused::kMinSumQC)                                                                       \
+                return launch_fused_kernel(fused::k_fused<A_, DB_, fused::kMinSumQC>, batch, d_batch, counter,  \
                                            lds_bytes, threads, s, profile);                                      \
         }                                                                                                        \
         if (fpw != 1)                                                                                            \

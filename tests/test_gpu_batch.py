@@ -110,36 +110,34 @@ def test_fused_mix_isolation_and_oracle(L):
         compare(ref, bits[idx], iters[idx], post[idx], np.float32, f"mix job {k}")
 
 
-@pytest.mark.parametrize("layered", [False, True])
-def test_schedule_instance_matches_general_instance(L, layered):
-    """A batch whose jobs are all FP32 sum-product on codes with a circulant
-    view, all flooding or all layered, runs a kernel instance compiled with
-    that schedule's rows alone (no min-sum, no CSR rows, no other schedule).
-    Adding a min-sum job, a job of the other schedule or a job on a code
-    without a circulant view makes the same jobs run the general instance:
+@pytest.mark.parametrize("mode", ["flooding", "layered", "min-sum"])
+def test_schedule_instance_matches_general_instance(L, mode):
+    """A batch whose jobs are all FP32 on codes with a circulant view and all
+    take one of sum-product flooding, sum-product layered or min-sum flooding
+    runs a kernel instance compiled with those rows alone (no other rule or
+    schedule, no CSR rows).  Adding a job of another kind, or a job on a code
+    without a circulant view, makes the same jobs run the general instance:
     their outputs stay the same, bit for bit."""
     import torch
+    kinds = {"flooding": {}, "layered": {"layered": True}, "min-sum": {"rule": "minsum", "ms_scale": 0.75}}
+    kw = kinds[mode]
     mix = configs.qc_mix(total=720)[::3]
     hs = [L.Code.from_workload(m.code) for m in mix]
     g = configs.gallager504(frames=64)
     hg = L.Code.from_workload(g.code)
     for es in (True, False):
         def jobs_of():
-            return [L.Job(h, torch.from_numpy(np.ascontiguousarray(m.llr)).cuda(), 10, early_stop=es,
-                          layered=layered) for h, m in zip(hs, mix)]
+            return [L.Job(h, torch.from_numpy(np.ascontiguousarray(m.llr)).cuda(), 10, early_stop=es, **kw)
+                    for h, m in zip(hs, mix)]
         first = jobs_of()
         L.decode_batch(first)
         torch.cuda.synchronize()
         base = [_np(j) for j in first]
         x0 = torch.from_numpy(np.ascontiguousarray(mix[0].llr)).cuda()
-        extras = {
-            "min-sum": L.Job(hs[0], x0, 10, early_stop=es, rule="minsum", ms_scale=0.75, layered=layered),
-            "other schedule": L.Job(hs[0], x0, 10, early_stop=es, layered=not layered),
-            "csr code": L.Job(hg, torch.from_numpy(g.llr.astype(np.float32)).cuda(), 10, early_stop=es,
-                              layered=layered),
-        }
+        extras = {other: L.Job(hs[0], x0, 10, early_stop=es, **kinds[other]) for other in kinds if other != mode}
+        extras["csr code"] = L.Job(hg, torch.from_numpy(g.llr.astype(np.float32)).cuda(), 10, early_stop=es, **kw)
         for name, extra in extras.items():
-            _log(f"[gpu] schedule instance vs general (layered {layered}, +{name}, early stop {es})")
+            _log(f"[gpu] {mode} instance vs general (+{name}, early stop {es})")
             jobs = jobs_of()
             L.decode_batch(jobs + [extra])
             torch.cuda.synchronize()
