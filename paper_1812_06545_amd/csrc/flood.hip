@@ -345,9 +345,11 @@ ldpc_status decode_impl(const ldpc_code_s *c, int32_t frames, int32_t max_iter, 
     int32_t *done = cv.take<int32_t>(Fp + nchunk);  // per frame, then per chunk (flood_kernels.h)
     int32_t *unsat = cv.take<int32_t>(static_cast<size_t>(std::max(max_iter, 1)) * Fp);
 
-    const int64_t unsat_words = es ? static_cast<int64_t>(max_iter) * Fp : 0;
-    const int init_blocks = static_cast<int>(std::min<int64_t>((Fp + nchunk + unsat_words + 255) / 256, 4096));
-    {
+    // The frame state is read only with early stop (every read is under the
+    // kernels' ES flag), so only then is it initialised.
+    if (es) {
+        const int64_t unsat_words = static_cast<int64_t>(max_iter) * Fp;
+        const int init_blocks = static_cast<int>(std::min<int64_t>((Fp + nchunk + unsat_words + 255) / 256, 4096));
         ProfScope ps(LDPC_KERNEL_OTHER, s);
         LDPC_LAUNCH(ps, k_frames_init, dim3(init_blocks), dim3(256), 0, s, Fp, done, unsat, unsat_words);
     }
